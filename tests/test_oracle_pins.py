@@ -1,0 +1,431 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Nothing here compares the oracle with itself: every expected value comes from
+quadrature, a closed form, an identity of the integrals, the paper's printed
+tables / worked examples, or an invariance of the physics.
+"""
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import analytic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# single-cell integrals: quadrature and closed forms (Section 2.1)
+# ---------------------------------------------------------------------------
+
+def quad_cell(ua, ub, va, vb, dps=25):
+    """[I0, Ixx, Ixy, J0, Jyy, Jyx] by 2-D Gauss-Legendre quadrature of the
+    integrands themselves (cells not containing the target)."""
+    uc, vc = (ua + ub) / 2, (va + vb) / 2
+    out = []
+    with mp.workdps(dps):
+        integrands = [
+            lambda u, v: u / (u * u + v * v) ** 1.5,
+            lambda u, v: (u - uc) * u / (u * u + v * v) ** 1.5,
+            lambda u, v: (v - vc) * u / (u * u + v * v) ** 1.5,
+            lambda u, v: v / (u * u + v * v) ** 1.5,
+            lambda u, v: (v - vc) * v / (u * u + v * v) ** 1.5,
+            lambda u, v: (u - uc) * v / (u * u + v * v) ** 1.5,
+        ]
+        for f in integrands:
+            out.append(float(mp.quad(f, [ua, ub], [va, vb])))
+    return np.array(out)
+
+
+CELLS = [
+    (0.5, 1.5, -0.5, 0.5),     # right neighbour, straddles the target row
+    (0.0, 1.0, 1.0, 2.0),      # corner at the target's column (u = 0 branch)
+    (-3.0, -2.0, -0.5, 0.5),   # left, straddling
+    (2.5, 3.5, 4.5, 5.5),      # diagonal
+    (-7.0, -6.0, -2.0, -1.0),  # far, third quadrant
+    (-1.0, 1.0, 3.0, 5.0),     # coarse cell straddling the target column
+    (0.0, 0.25, -0.5, -0.25),  # fine cell with an edge on u = 0
+    (40.0, 41.0, -12.0, -11.0),
+]
+
+
+@pytest.mark.parametrize("cell", CELLS)
+def test_cell_integrals_match_quadrature(cell):
+    got = oracle.cell_integrals(*cell)
+    want = quad_cell(*cell)
+    scale = np.abs(want).max()
+    # long-double corner sums: absolute error ~1e-19 x (corner magnitude)
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-13 * scale)
+
+
+def test_self_cell_closed_forms():
+    # Self cell, side h: I0 = 0 by antisymmetry; int u^2/r^3 over [-h/2,h/2]^2
+    # is half of int 1/r, which in polar form is 8 * int_0^{pi/4} (h/2)/cos
+    # = 4h ln(1 + sqrt 2) -> Ixx = 2 h asinh(1).
+    for h in (1.0, 0.125, 3.0):
+        c = oracle.cell_integrals(-h / 2, h / 2, -h / 2, h / 2)
+        assert c[0] == 0.0 and c[2] == 0.0 and c[3] == 0.0 and c[5] == 0.0
+        assert c[1] == pytest.approx(2 * h * math.asinh(1.0), rel=1e-15)
+        assert c[4] == pytest.approx(2 * h * math.asinh(1.0), rel=1e-15)
+
+
+def test_right_neighbour_closed_form():
+    # int_{1/2}^{3/2} int_{-1/2}^{1/2} u/r^3 = int [1/sqrt(u^2+v^2)] ... in closed
+    # form 2 (asinh(1) - asinh(1/3)).
+    c = oracle.cell_integrals(0.5, 1.5, -0.5, 0.5)
+    assert c[0] == pytest.approx(2 * (math.asinh(1.0) - math.asinh(1.0 / 3.0)), rel=1e-15)
+
+
+def test_cell_parities_and_scaling():
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        ua, va = rng.uniform(-6, 6, 2)
+        w = rng.uniform(0.2, 2)
+        base = oracle.cell_integrals(ua, ua + w, va, va + w)
+        mx = oracle.cell_integrals(-ua - w, -ua, va, va + w)      # mirror in u
+        my = oracle.cell_integrals(ua, ua + w, -va - w, -va)      # mirror in v
+        sw = oracle.cell_integrals(va, va + w, ua, ua + w)        # exchange axes
+        # I0 odd/even, Ixx even/even, Ixy odd/odd, J0 even/odd, Jyy even/even, Jyx odd/odd
+        np.testing.assert_allclose(mx, base * [-1, 1, -1, 1, 1, -1], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(my, base * [1, 1, -1, -1, 1, -1], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(sw[[3, 4, 5, 0, 1, 2]], base, rtol=1e-12, atol=1e-15)
+        lam = 0.37
+        sc = oracle.cell_integrals(lam * ua, lam * (ua + w), lam * va, lam * (va + w))
+        np.testing.assert_allclose(sc, base * [1, lam, lam, 1, lam, lam], rtol=1e-12,
+                                   atol=1e-15)
+
+
+def test_cell_additivity_prolongation():
+    """A cell with linear sigma equals its m^2 sub-cells carrying the same
+    linear function (the identity behind coarse-to-fine pairs)."""
+    rng = np.random.default_rng(1)
+    for m in (2, 4):
+        for _ in range(5):
+            ua, va = rng.uniform(-5, 5, 2)
+            w = 1.0
+            s, dx, dy = rng.normal(size=3)
+            big = oracle.cell_integrals(ua, ua + w, va, va + w)
+            uc, vc = ua + w / 2, va + w / 2
+            fx_big = s * big[0] + dx * big[1] + dy * big[2]
+            fy_big = s * big[3] + dy * big[4] + dx * big[5]
+            fx = fy = 0.0
+            for a in range(m):
+                for b in range(m):
+                    sa, sb = ua + a * w / m, va + b * w / m
+                    c = oracle.cell_integrals(sa, sa + w / m, sb, sb + w / m)
+                    ss = s + dx * (sa + w / (2 * m) - uc) + dy * (sb + w / (2 * m) - vc)
+                    fx += ss * c[0] + dx * c[1] + dy * c[2]
+                    fy += ss * c[3] + dy * c[4] + dx * c[5]
+            assert fx == pytest.approx(fx_big, rel=1e-9, abs=1e-13)
+            assert fy == pytest.approx(fy_big, rel=1e-9, abs=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# whole-domain pins: telescoping against polar quadrature
+# ---------------------------------------------------------------------------
+
+def domain_integrals_polar(xt, yt, L, R, B, T):
+    """Principal-value domain integrals for a target inside [L,R]x[B,T], in
+    polar form about the target: with rho(theta) the distance to the
+    boundary,  int u/r^3 = int cos(t) ln rho dt  (the ln eps part integrates
+    to zero),  int u^2/r^3 = int cos^2 rho dt,  int uv/r^3 = int cos sin rho dt,
+    and likewise with sin for v."""
+    with mp.workdps(25):
+        def rho(t):
+            c, s = mp.cos(t), mp.sin(t)
+            cands = []
+            if c > 0: cands.append((R - xt) / c)
+            if c < 0: cands.append((L - xt) / c)
+            if s > 0: cands.append((T - yt) / s)
+            if s < 0: cands.append((B - yt) / s)
+            return min(cands)
+        corners = sorted(float(mp.atan2(cy - yt, cx - xt)) % (2 * math.pi)
+                         for cx in (L, R) for cy in (B, T))
+        pts = [0.0] + corners + [2 * math.pi]
+        f = lambda g: float(mp.quad(g, pts))
+        i0 = f(lambda t: mp.cos(t) * mp.log(rho(t)))
+        j0 = f(lambda t: mp.sin(t) * mp.log(rho(t)))
+        uu = f(lambda t: mp.cos(t) ** 2 * rho(t))
+        vv = f(lambda t: mp.sin(t) ** 2 * rho(t))
+        uv = f(lambda t: mp.cos(t) * mp.sin(t) * rho(t))
+    return i0, j0, uu, vv, uv
+
+
+HIERS = {
+    "one": synth.nested_hierarchy(-1.0, -1.0, 2 / 12, 2, [(12, 0, 0)]),
+    "two": synth.nested_hierarchy(-1.0, -1.0, 2 / 10, 2, [(10, 0, 0), (8, 6, 4)]),
+    "three": synth.nested_hierarchy(-1.0, -1.0, 2 / 8, 2, [(8, 0, 0), (8, 4, 2), (6, 10, 8)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(HIERS))
+def test_telescoping_linear_density(name):
+    """sigma = a + b x + c y with exact slopes is reproduced exactly by the
+    linear reconstruction, so the sum over all active cells of all levels is
+    the whole-domain integral (Section 2.1 with the source-centred
+    expansion)."""
+    hier = HIERS[name]
+    a, b, c = 0.7, -1.3, 0.45
+    fn = lambda X, Y: a + b * X + c * Y
+    sig, _, _ = synth.sample_fields(hier, fn, "none")
+    dx = [np.full_like(s, b) for s in sig]
+    dy = [np.full_like(s, c) for s in sig]
+    p0 = hier.patches[0]
+    L, B = hier.x0, hier.y0
+    Rr, T = L + p0.n * hier.h0, B + p0.n * hier.h0
+    rng = np.random.default_rng(2)
+    tp, ti, tj = [], [], []
+    for k, p in enumerate(hier.patches):
+        act = np.argwhere(~synth.covered_mask(hier, p))
+        for j, i in act[rng.choice(len(act), size=min(3, len(act)), replace=False)]:
+            tp.append(k); ti.append(i); tj.append(j)
+    fx, fy = oracle.forces(hier, sig, dx, dy, (np.array(tp), np.array(ti), np.array(tj)))
+    for k in range(len(tp)):
+        p = hier.patches[tp[k]]
+        h = hier.h(p.level)
+        xl, yl = hier.lower_left(p)
+        xt, yt = xl + (ti[k] + 0.5) * h, yl + (tj[k] + 0.5) * h
+        i0, j0, uu, vv, uv = domain_integrals_polar(xt, yt, L, Rr, B, T)
+        wx = a * i0 + b * (uu + xt * i0) + c * (uv + yt * i0)
+        wy = a * j0 + c * (vv + yt * j0) + b * (uv + xt * j0)
+        assert fx[k] == pytest.approx(wx, rel=1e-11, abs=1e-12)
+        assert fy[k] == pytest.approx(wy, rel=1e-11, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# invariants of the direct sum
+# ---------------------------------------------------------------------------
+
+def _rand_fields(hier, seed):
+    rng = np.random.default_rng(seed)
+    sig = [rng.normal(size=(p.n, p.n)) for p in hier.patches]
+    dx = [rng.normal(size=(p.n, p.n)) for p in hier.patches]
+    dy = [rng.normal(size=(p.n, p.n)) for p in hier.patches]
+    return sig, dx, dy
+
+
+def test_mirror_symmetry():
+    """Mirror x -> -x of density and (mirror-symmetric) grid: Fx odd, Fy even."""
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2 / 12, 2, [(12, 0, 0), (8, 8, 6)])
+    sig, dx, dy = _rand_fields(hier, 3)
+    msig = [s[:, ::-1].copy() for s in sig]
+    mdx = [-d[:, ::-1].copy() for d in dx]
+    mdy = [d[:, ::-1].copy() for d in dy]
+    fx, fy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = oracle.forces(hier, msig, mdx, mdy)
+    for k in range(2):
+        np.testing.assert_allclose(gx[k], -fx[k][:, ::-1], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(gy[k], fy[k][:, ::-1], rtol=1e-12, atol=1e-13)
+
+
+def test_rotation_symmetry():
+    """Rotating density and grid by 90 degrees rotates the force."""
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2 / 10, 2, [(10, 0, 0), (8, 6, 6)])
+    sig, dx, dy = _rand_fields(hier, 4)
+    # rotation (x, y) -> (-y, x): new[j][i] = old at (x, y) = (y', -x')
+    rs = [np.rot90(s, k=1).copy() for s in sig]
+    rdx = [np.rot90(d, k=1).copy() for d in dy]
+    rdy = [-np.rot90(d, k=1).copy() for d in dx]
+    fx, fy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = oracle.forces(hier, rs, rdx, rdy)
+    for k in range(2):
+        np.testing.assert_allclose(gx[k], np.rot90(fy[k], 1), rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(gy[k], -np.rot90(fx[k], 1), rtol=1e-12, atol=1e-13)
+
+
+def test_translation_and_scale_invariance():
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2 / 8, 2, [(8, 0, 0), (8, 4, 4)])
+    sig, dx, dy = _rand_fields(hier, 5)
+    fx, fy = oracle.forces(hier, sig, dx, dy)
+    lam = 0.5
+    h2 = synth.nested_hierarchy(3.0, -7.5, lam * 2 / 8, 2, [(8, 0, 0), (8, 4, 4)])
+    # force from sigma is scale-free; the slope terms carry delta*h
+    gx, gy = oracle.forces(h2, sig, [d / lam for d in dx], [d / lam for d in dy])
+    for k in range(2):
+        np.testing.assert_allclose(gx[k], fx[k], rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(gy[k], fy[k], rtol=1e-11, atol=1e-12)
+
+
+def test_zero_net_self_force_single_level():
+    """Single level, slopes 0: the kernel I0 is antisymmetric under exchange
+    of equal cells, so sum sigma_t F_t = 0 (Newton's third law)."""
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2 / 16, 2, [(16, 0, 0)])
+    sig, _, _ = _rand_fields(hier, 6)
+    sig = [np.abs(s) for s in sig]
+    fx, fy = oracle.forces(hier, sig)
+    scale = np.abs(sig[0] * fx[0]).sum()
+    assert abs((sig[0] * fx[0]).sum()) < 1e-13 * scale
+    assert abs((sig[0] * fy[0]).sum()) < 1e-13 * scale
+
+
+def test_linearity_and_covered_targets():
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2 / 8, 2, [(8, 0, 0), (8, 4, 2)])
+    a = _rand_fields(hier, 7)
+    b = _rand_fields(hier, 8)
+    fa = oracle.forces(hier, *a)
+    fb = oracle.forces(hier, *b)
+    comb = [[2 * x - 3 * y for x, y in zip(ea, eb)] for ea, eb in zip(a, b)]
+    fc = oracle.forces(hier, *comb)
+    for c in range(2):
+        for k in range(2):
+            np.testing.assert_allclose(fc[c][k], 2 * fa[c][k] - 3 * fb[c][k], rtol=1e-11,
+                                       atol=1e-12)
+    cov = synth.covered_mask(hier, hier.patches[0])
+    assert cov.sum() == 16
+    assert np.all(fa[0][0][cov] == 0) and np.all(fa[1][0][cov] == 0)
+    # covered sources do not contribute: changing sigma under the child
+    # leaves every force unchanged
+    a2 = [list(x) for x in a]
+    a2[0][0] = a[0][0].copy()
+    a2[0][0][cov] += 100.0
+    f2 = oracle.forces(hier, *a2)
+    for c in range(2):
+        for k in range(2):
+            np.testing.assert_allclose(f2[c][k], fa[c][k], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# analytic disks (appendix) and the paper's convergence tables (Section 3)
+# ---------------------------------------------------------------------------
+
+def test_maclaurin_interior_force():
+    # Phi_{D1} = -pi^2 sigma0 (2 alpha^2 - R^2) / (4 alpha)  =>  F_R = -pi^2 R/(2 alpha)
+    for R in (0.1, 0.4, 0.79):
+        assert float(analytic.radial_force(1, R, 0.8)) == pytest.approx(
+            -math.pi ** 2 * R / (2 * 0.8), rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_closed_form_matches_recursion(n):
+    """Closed form eqnPhiDn (with b_{n+1,0}'s middle denominator read as 2k+2)
+    against quadrature of the defining recursion eqnPhiDnp1."""
+    for R in (0.2, 0.6, 0.85, 1.4):
+        a = analytic.potential(n, R, 0.85)
+        b = analytic.potential_by_recursion(n, R, 0.85)
+        assert float(abs(a - b)) < 1e-14 * float(abs(b))
+
+
+def test_printed_b_coefficient_fails_recursion():
+    """With the printed denominator 2k+1 the closed form disagrees with the
+    recursion from n = 3 on (the reason for the reading above)."""
+    from fractions import Fraction
+    b2, c2 = analytic.coefficients(2)
+    nn = 2
+    A = b2[nn] / (2 * nn + 2) + c2[nn - 1]
+    mid_printed = sum((b2[k] / (2 * k + 1) + c2[k] + c2[k - 1]) * analytic.H(k, 0)
+                      for k in range(1, nn))
+    mid_read = sum((b2[k] / (2 * k + 2) + c2[k] + c2[k - 1]) * analytic.H(k, 0)
+                   for k in range(1, nn))
+    assert mid_printed != mid_read
+    b3, _ = analytic.coefficients(3)
+    assert b3[0] == A * analytic.H(nn, 0) + mid_read + (b2[0] / 4 + c2[0] / 2)
+
+
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_far_field_is_point_mass(n):
+    R = 2000.0
+    f = float(analytic.radial_force(n, R, 0.85))
+    assert f * R * R == pytest.approx(-float(analytic.disk_mass(n, 0.85)), rel=1e-6)
+
+
+def _example_errors(example, N):
+    hier = synth.example_hierarchy(example, N)
+    sig, dx, dy = synth.sample_fields(hier, synth.disk_dn(5, 0.85), "analytic",
+                                      synth.disk_dn_gradient(5, 0.85))
+    fx, fy = oracle.forces(hier, sig, dx, dy)
+    ex, eR = [], []
+    for k, p in enumerate(hier.patches):
+        X, Y = synth.cell_centres(hier, p)
+        act = ~synth.covered_mask(hier, p)
+        ax, ay = analytic.force_xy(5, X[act], Y[act], 0.85)
+        ex.append(np.abs(fx[k][act] - ax))
+        r = np.hypot(X[act], Y[act])
+        eR.append(np.abs((X[act] * (fx[k][act] - ax) + Y[act] * (fy[k][act] - ay)) / r))
+    ex, eR = np.concatenate(ex), np.concatenate(eR)
+    return ex.mean(), eR.mean()
+
+
+def _golden(name):
+    rows = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, e1x, e1r = line.split()
+        rows[int(n)] = (float(e1x), float(e1r))
+    return rows
+
+
+def test_example1_second_order_and_table1():
+    tab = _golden("table1_example1_e1.txt")
+    e16, _ = _example_errors(1, 16)
+    e32, r32 = _example_errors(1, 32)
+    e64, r64 = _example_errors(1, 64)
+    assert 3.6 < e16 / e32 < 4.4 and 3.8 < e32 / e64 < 4.2
+    assert e32 == pytest.approx(tab[32][0], rel=0.025)
+    assert e64 == pytest.approx(tab[64][0], rel=0.015)
+    assert r32 == pytest.approx(tab[32][1], rel=0.03)
+    assert r64 == pytest.approx(tab[64][1], rel=0.02)
+
+
+def test_example2_table2():
+    tab = _golden("table2_example2_e1.txt")
+    e32, r32 = _example_errors(2, 32)
+    assert e32 == pytest.approx(tab[32][0], rel=0.01)
+    assert r32 == pytest.approx(tab[32][1], rel=0.03)
+
+
+# ---------------------------------------------------------------------------
+# generalized convolutions: the paper's worked examples (Section 2.2)
+# ---------------------------------------------------------------------------
+
+def test_worked_examples_m2():
+    rng = np.random.default_rng(9)
+    b = rng.normal(size=8)
+    c = rng.normal(size=4)
+    a2 = oracle.genconv1d(2, 2, b, c, 6)
+    a3 = oracle.genconv1d(3, 2, b, c, 14)
+    seen = {"case2": set(), "case3": set()}
+    for line in open(os.path.join(GOLDEN, "worked_examples_m2.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        tag, n, *terms = line.split()
+        n = int(n)
+        want = sum(b[int(t.split(":")[0])] * c[int(t.split(":")[1])] for t in terms)
+        got = (a2 if tag == "case2" else a3)[n]
+        assert got == pytest.approx(want, rel=1e-14, abs=1e-15)
+        seen[tag].add(n)
+    assert seen["case2"] == set(range(6)) and seen["case3"] == set(range(14))
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_polyphase_identities(m):
+    """The generalized z-transform identities of Cases 2' and 3', checked on
+    random sequences: a(z^m;1,0) = sum_k b(z;m,-k) c(z;m,k), and
+    sum_n' a_{mn'+k} z^{mn'+k} = c(z^m;1,0) b(z;m,k).  Polynomials are
+    evaluated at random complex points."""
+    rng = np.random.default_rng(m)
+    b = rng.normal(size=11)
+    c = rng.normal(size=5)
+    na2 = (len(b) + len(c)) // m + 2
+    a2 = oracle.genconv1d(2, m, b, c, na2)
+    na3 = len(b) + m * len(c)
+    a3 = oracle.genconv1d(3, m, b, c, na3)
+    for z in rng.normal(size=3) + 1j * rng.normal(size=3):
+        z = z / abs(z) * 0.9
+        lhs = sum(a2[n] * z ** (m * n) for n in range(na2))
+        rhs = 0
+        for k in range(m):
+            # b(z;m,-k) = sum_n b_{mn-k} z^{mn-k};  c(z;m,k) = sum_n c_{mn+k} z^{mn+k}
+            bz = sum(b[i] * z ** i for i in range(len(b)) if (i + k) % m == 0)
+            cz = sum(c[i] * z ** i for i in range(len(c)) if i % m == k)
+            rhs += bz * cz
+        assert abs(lhs - rhs) < 1e-12 * (1 + abs(lhs))
+        cz1 = sum(c[i] * z ** (m * i) for i in range(len(c)))
+        for k in range(m):
+            lhs3 = sum(a3[n] * z ** n for n in range(na3) if n % m == k)
+            bz = sum(b[i] * z ** i for i in range(len(b)) if i % m == k)
+            assert abs(lhs3 - cz1 * bz) < 1e-12 * (1 + abs(lhs3))
