@@ -1,0 +1,221 @@
+/*
+ * thindisk.h -- C ABI of the MI355X (gfx950) thin-disk self-gravity solver.
+ *
+ * The library computes the mid-plane gravitational force of an
+ * infinitesimally thin disk whose surface density lives on a hierarchy of
+ * nested uniform grids (Wang, Taam & Yen, "Self-Gravitational Force
+ * Calculation of Infinitesimally Thin Gaseous Disks on Nested Grids"):
+ *
+ *   F_x(t) = sum over every active source cell c on every level of
+ *            integral_c (xbar - x_t) / |rbar - r_t|^3 sigma(xbar, ybar),
+ *
+ * G = 1, with sigma linear in each cell about the cell centre
+ * (Section 2.1, eq. eqnSigma):  sigma = s + dsdx (x - x_c) + dsdy (y - y_c).
+ * The cell integrals are closed-form four-corner differences (eqs. eqnCalK,
+ * eqnbnot0, eqnbeq0, with the slope antiderivatives v ln(u+r) and -r); the
+ * sums are evaluated as zero-padded 2-D FFT generalized convolutions, with
+ * the polyphase splits of Cases 2' and 3' (Section 2.2, eqs. eqnbmnn,
+ * eqnbnmn) for pairs of levels of different resolution.  F_y follows by
+ * exchanging x and y.
+ *
+ * Conventions
+ *   - Level l has one square patch of n_l x n_l cells of side h0 / ratio^l.
+ *     Its lower-left corner is (x0 + ox_l h_l, y0 + oy_l h_l): ox_l, oy_l are
+ *     integer offsets in level-l cells from the level-0 origin (ox_0 = oy_0
+ *     = 0).  Level l+1 must lie inside level l with its edges on level-l
+ *     nodes (Section 2.1: integer ratio between nested levels).
+ *   - A cell covered by level l+1 is not part of level l's domain: its
+ *     sigma / slopes are ignored, and its force outputs are written as 0.
+ *   - Every field is row-major [j][i] (x fastest), n_l * n_l elements of the
+ *     plan's dtype (float for TD_F32, double for TD_F64).
+ *   - Forces have the units of sigma (G = 1): F = -grad Phi, attractive.
+ *
+ * Ownership and errors
+ *   - Field pointers are DEVICE pointers owned by the caller; the library
+ *     reads / writes them only inside the stream work it enqueues.
+ *   - The context owns twiddle tables and the resident kernel spectra; a
+ *     plan owns its workspace and job lists.  Destroy plans before their
+ *     context.
+ *   - Every entry point returns td_status; on any error nothing has been
+ *     enqueued and no output has been written.  td_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - Solves are asynchronous on the given HIP stream (NULL = the null
+ *     stream); the caller synchronises before reading outputs.  Two solves
+ *     of the SAME plan must not run concurrently (they share workspace).
+ */
+#ifndef THINDISK_H
+#define THINDISK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TD_OK = 0,
+    TD_EINVAL = 1,       /* bad argument (NULL, size, count, dtype)          */
+    TD_EALIGN = 2,       /* a child patch edge is not on its parent lattice  */
+    TD_ENEST = 3,        /* a child patch is not inside its parent           */
+    TD_ENOMEM = 4,       /* device allocation failed or HBM budget exceeded  */
+    TD_EDEVICE = 5,      /* HIP runtime error                                */
+    TD_EBUSY = 6,        /* server admission refused (no room, no queueing)  */
+    TD_EUNSUPPORTED = 7  /* valid but not supported by this build            */
+} td_status;
+
+typedef enum { TD_F32 = 0, TD_F64 = 1 } td_dtype;
+
+typedef struct {
+    int32_t n;   /* cells per side                                         */
+    int32_t ox;  /* lower-left offset in this level's cells, from level 0  */
+    int32_t oy;
+} td_level;
+
+typedef struct {
+    double x0, y0;          /* lower-left corner of level 0               */
+    double h0;              /* level-0 cell side                          */
+    int32_t ratio;          /* refinement ratio between levels: 2 or 4    */
+    int32_t nlevels;        /* 1 .. TD_MAX_LEVELS                         */
+    const td_level* levels; /* [nlevels], level 0 first                   */
+} td_hierarchy;
+
+#define TD_MAX_LEVELS 8
+#define TD_MAX_N 2048   /* cells per side of one level                    */
+
+typedef struct td_context td_context;
+typedef struct td_plan td_plan;
+typedef struct td_batch td_batch;
+typedef struct td_server td_server;
+
+/* One force solve.  Arrays are indexed by level; all pointers are device
+ * pointers of the plan's dtype.  dsdx / dsdy may be NULL (all slopes zero);
+ * an individual entry may also be NULL. */
+typedef struct {
+    td_plan* plan;
+    const void* const* sigma;   /* [nlevels] sigma at cell centres          */
+    const void* const* dsdx;    /* [nlevels] or NULL: x-slope in each cell  */
+    const void* const* dsdy;    /* [nlevels] or NULL                        */
+    void* const* fx;            /* [nlevels] outputs                        */
+    void* const* fy;            /* [nlevels] outputs                        */
+} td_request;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold (resident spectra + plan workspace);
+ * 0 = no cap.  */
+td_status td_context_create(int hip_device, size_t hbm_budget_bytes, td_context** out);
+td_status td_context_destroy(td_context* ctx);
+/* Bytes currently held by the context and its plans. */
+td_status td_context_usage(const td_context* ctx, size_t* bytes_in_use, size_t* spectra_bytes);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Validate a hierarchy (ratio, sizes, alignment, nesting).  TD_OK if it can
+ * be planned. */
+td_status td_hierarchy_check(const td_hierarchy* h);
+
+/* Fill levels[1..nlevels-1].ox/oy so that each child patch (of the n given
+ * in levels[l].n) is centred as near as its parent lattice allows to
+ * (cx[l-1], cy[l-1]) -- lower-left rounded to the nearest parent node and
+ * clamped inside the parent.  levels[0] gets offset (0, 0). */
+td_status td_hierarchy_snap(td_hierarchy* inout, td_level* levels, const double* cx,
+                            const double* cy);
+
+/* ---------------------------------------------------------------- plans */
+
+/* Validate the hierarchy, build (or find resident) the kernel spectra for
+ * every level pair, and allocate the plan's workspace.  The kernel tables
+ * (cell integrals of every offset and polyphase phase) are generated on the
+ * GPU in FP64 and transformed in FP64; TD_F32 plans use them rounded to
+ * FP32.  Synchronous. */
+td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_dtype dtype,
+                         td_plan** out);
+/* Host-only planning: validate the hierarchy, build every job list of the
+ * plan that td_plan_create would build (default launch shapes) and prove
+ * on the host that each job's reads and writes stay inside its workspace,
+ * fields and kernel spectra and that every workspace row a pass reads was
+ * written by the pass before.  Needs no device.  workspace_bytes (may be
+ * NULL) receives the plan's workspace size. */
+td_status td_plan_check(const td_hierarchy* h, td_dtype dtype, size_t* workspace_bytes);
+/* Workspace and (shared, resident) spectrum bytes this plan uses. */
+td_status td_plan_footprint(const td_plan* plan, size_t* workspace_bytes,
+                            size_t* spectra_bytes);
+td_status td_plan_destroy(td_plan* plan);
+
+/* Enqueue one solve on `hip_stream` (a hipStream_t, or NULL). */
+td_status td_solve(const td_request* req, void* hip_stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* A batch plan fuses `count` plans (same dtype, same context) into one set
+ * of launches: each FFT pass runs for every hierarchy of the batch in one
+ * kernel launch per transform length.  The batch owns its own workspace. */
+td_status td_batch_create(td_context* ctx, int32_t count, td_plan* const* plans,
+                          td_batch** out);
+/* Enqueue the solves (reqs[k].plan must be the k-th plan given at creation).
+ * With use_graph != 0, the launches are captured once into a HIP graph and
+ * replayed; pointer tables are refreshed by a copy node each replay. */
+td_status td_batch_solve(td_batch* batch, const td_request* reqs, int use_graph,
+                         void* hip_stream);
+td_status td_batch_footprint(const td_batch* batch, size_t* workspace_bytes);
+td_status td_batch_destroy(td_batch* batch);
+
+/* ---------------------------------------------------------------- autotune */
+
+/* Time the candidate launch shapes (FFTs per workgroup, LDS budget) of every
+ * pass for transform lengths up to max_M in `dtype`, keep the fastest, and
+ * use them for plans created afterwards.  With db_path != NULL, results are
+ * read from / appended to that JSON file (keyed by pass, M, dtype, arch). */
+td_status td_autotune(td_context* ctx, td_dtype dtype, int32_t max_M, const char* db_path);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A server owns a worker thread that takes submitted solves, admits them by
+ * HBM footprint (plan workspace against the context budget), groups the
+ * admitted ones into batches as they arrive (continuous batching: requests
+ * that arrive while others run join the next launch) and runs up to
+ * max_inflight batches concurrently on its own streams. */
+td_status td_server_create(td_context* ctx, int32_t max_inflight, int32_t max_batch,
+                           td_server** out);
+/* Submit a solve.  The request's plan must stay alive until the ticket is
+ * done.  If the server has no room (queue at capacity) and queue_if_full is
+ * 0, returns TD_EBUSY.  Arrival time = time of the call. */
+td_status td_server_submit(td_server* s, const td_request* req, int32_t queue_if_full,
+                           uint64_t* ticket);
+/* done = 1 once the outputs of `ticket` are complete on the device.
+ * latency_s = completion - submission (seconds), valid when done. */
+td_status td_server_poll(td_server* s, uint64_t ticket, int32_t* done, double* latency_s);
+/* Block until every submitted request is done. */
+td_status td_server_drain(td_server* s);
+/* Cancel a request that has not started; TD_EINVAL if unknown or started. */
+td_status td_server_cancel(td_server* s, uint64_t ticket);
+/* Counters: completed, cancelled, refused, deferred (admission waited for
+ * memory), batches launched, peak queue depth. */
+td_status td_server_stats(const td_server* s, uint64_t* completed, uint64_t* cancelled,
+                          uint64_t* refused, uint64_t* deferred, uint64_t* batches,
+                          uint64_t* peak_queue);
+td_status td_server_destroy(td_server* s);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+/* Write the dimensionless FP64 kernel table of one level pair kind into
+ * host memory: out[6][M][M] (I0, Ixx, Ixy, J0, Jyy, Jyx), entry [ny][nx] is
+ * the cell integral for a lattice offset (output - input) of
+ * (nx or nx-M, ny or ny-M), in units of the finer cell side; kind = 1 (same
+ * level), 2 (finer source, ratio m), 3 (coarser source, ratio m); (kx, ky)
+ * the polyphase phase.  Case-3 slope entries include the 1/m factor that
+ * converts the coarse source's slope scaling.  Synchronous; for tests. */
+td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m, int32_t kx,
+                          int32_t ky, double* out_host);
+
+const char* td_status_string(td_status s);
+const char* td_last_error(void);
+/* Library version string. */
+const char* td_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THINDISK_H */

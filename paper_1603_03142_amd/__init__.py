@@ -1,0 +1,281 @@
+"""MI355X-native thin-disk self-gravity on nested grids.
+
+Python face of ``libthindisk.so`` (C ABI in ``include/thindisk.h``).  PyTorch
+supplies device memory and streams; every step of a solve runs in the HIP
+kernels of ``csrc/``.
+
+    import paper_1603_03142_amd as td
+    ctx = td.Context()
+    plan = ctx.plan(hierarchy, "f32")
+    fx, fy = plan.solve(sigma, dsdx, dsdy)      # lists of (n, n) tensors per level
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+from . import _binding as B
+from ._binding import TdError, lib
+
+__all__ = ["Context", "Plan", "Batch", "Server", "TdError", "lib", "version"]
+
+_DT = {"f32": B.TD_F32, "f64": B.TD_F64}
+
+
+def version() -> str:
+    return lib().td_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_fields(plan: "Plan", arrays, name, required=True):
+    torch = _torch()
+    if arrays is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return None
+    if len(arrays) != plan.nlevels:
+        raise ValueError(f"{name}: expected {plan.nlevels} arrays, got {len(arrays)}")
+    for l, (t, n) in enumerate(zip(arrays, plan.sizes)):
+        if t is None:
+            if required:
+                raise ValueError(f"{name}[{l}] is None")
+            continue
+        if not t.is_cuda or t.dtype != plan.torch_dtype or tuple(t.shape) != (n, n) \
+                or not t.is_contiguous():
+            raise ValueError(f"{name}[{l}] must be a contiguous {plan.torch_dtype} CUDA tensor "
+                             f"of shape ({n}, {n})")
+    return arrays
+
+
+class Context:
+    """td_context: one device, resident spectra, HBM budget (0 = none)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        B.check(lib().td_context_create(device, hbm_budget, ctypes.byref(h)), "td_context_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            B.check(lib().td_context_destroy(self.handle), "td_context_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def usage(self):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        B.check(lib().td_context_usage(self.handle, ctypes.byref(a), ctypes.byref(b)),
+                "td_context_usage")
+        return a.value, b.value
+
+    def plan(self, hier, dtype: str = "f32") -> "Plan":
+        return Plan(self, hier, dtype)
+
+    def autotune(self, dtype: str = "f32", max_M: int = 2048, db_path: Optional[str] = None):
+        B.check(lib().td_autotune(self.handle, _DT[dtype], max_M,
+                                  db_path.encode() if db_path else None), "td_autotune")
+
+    def kernel_table(self, M: int, kind: int, m: int = 1, kx: int = 0, ky: int = 0):
+        import numpy as np
+        out = np.zeros((6, M, M))
+        B.check(lib().td_kernel_table(self.handle, M, kind, m, kx, ky,
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                "td_kernel_table")
+        return out
+
+
+def check_hierarchy(hier) -> None:
+    h = B.make_hierarchy(hier)
+    B.check(lib().td_hierarchy_check(ctypes.byref(h)), "td_hierarchy_check")
+
+
+def check_plan(hier, dtype: str = "f32") -> int:
+    """td_plan_check: host-only job building and bounds proof; returns the
+    workspace bytes."""
+    h = B.make_hierarchy(hier)
+    ws = ctypes.c_size_t()
+    B.check(lib().td_plan_check(ctypes.byref(h), _DT[dtype], ctypes.byref(ws)), "td_plan_check")
+    return ws.value
+
+
+class Plan:
+    """td_plan for one hierarchy (one patch per level) and dtype."""
+
+    def __init__(self, ctx: Context, hier, dtype: str = "f32"):
+        if dtype not in _DT:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        self.ctx = ctx
+        self.dtype = dtype
+        self.hier = hier
+        h = B.make_hierarchy(hier)
+        self.nlevels = h.nlevels
+        self.sizes = [h.levels[l].n for l in range(h.nlevels)]
+        handle = ctypes.c_void_p()
+        B.check(lib().td_plan_create(ctx.handle, ctypes.byref(h), _DT[dtype],
+                                     ctypes.byref(handle)), "td_plan_create")
+        self.handle = handle
+        torch = _torch()
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+
+    @property
+    def cells(self) -> int:
+        return sum(n * n for n in self.sizes)
+
+    def footprint(self):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        B.check(lib().td_plan_footprint(self.handle, ctypes.byref(a), ctypes.byref(b)),
+                "td_plan_footprint")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.check(lib().td_plan_destroy(self.handle), "td_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def outputs(self):
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        fx = [torch.empty((n, n), dtype=self.torch_dtype, device=dev) for n in self.sizes]
+        fy = [torch.empty((n, n), dtype=self.torch_dtype, device=dev) for n in self.sizes]
+        return fx, fy
+
+    def request(self, sigma, dsdx=None, dsdy=None, fx=None, fy=None):
+        _check_fields(self, sigma, "sigma")
+        _check_fields(self, dsdx, "dsdx", required=False)
+        _check_fields(self, dsdy, "dsdy", required=False)
+        if fx is None or fy is None:
+            fx, fy = self.outputs()
+        _check_fields(self, fx, "fx")
+        _check_fields(self, fy, "fy")
+        req = B.make_request(self.handle, sigma, dsdx, dsdy, fx, fy)
+        req._tensors = (sigma, dsdx, dsdy, fx, fy)
+        return req, fx, fy
+
+    def solve(self, sigma, dsdx=None, dsdy=None, fx=None, fy=None, stream=None):
+        """Enqueue td_solve on the current (or given) torch stream; returns
+        (fx, fy) lists.  Asynchronous: synchronise before reading."""
+        req, fx, fy = self.request(sigma, dsdx, dsdy, fx, fy)
+        B.check(lib().td_solve(ctypes.byref(req), _stream_handle(stream)), "td_solve")
+        return fx, fy
+
+
+class Batch:
+    """td_batch: many plans solved by one launch per pass and length."""
+
+    def __init__(self, ctx: Context, plans: Sequence[Plan]):
+        self.ctx = ctx
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+        h = ctypes.c_void_p()
+        B.check(lib().td_batch_create(ctx.handle, len(plans), arr, ctypes.byref(h)),
+                "td_batch_create")
+        self.handle = h
+
+    def solve(self, fields: List[tuple], outs: Optional[List[tuple]] = None,
+              use_graph: bool = False, stream=None):
+        """fields[k] = (sigma, dsdx, dsdy) for plan k; returns [(fx, fy)]."""
+        reqs = (B.td_request * len(self.plans))()
+        keep, res = [], []
+        for k, (p, f) in enumerate(zip(self.plans, fields)):
+            fx, fy = (outs[k] if outs is not None else (None, None))
+            r, fx, fy = p.request(f[0], f[1], f[2], fx, fy)
+            keep.append(r)
+            reqs[k] = r
+            res.append((fx, fy))
+        self._keep = (keep, reqs)
+        B.check(lib().td_batch_solve(self.handle, reqs, 1 if use_graph else 0,
+                                     _stream_handle(stream)), "td_batch_solve")
+        return res
+
+    def footprint(self) -> int:
+        a = ctypes.c_size_t()
+        B.check(lib().td_batch_footprint(self.handle, ctypes.byref(a)), "td_batch_footprint")
+        return a.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.check(lib().td_batch_destroy(self.handle), "td_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """td_server: continuous batching of submitted solves."""
+
+    def __init__(self, ctx: Context, max_inflight: int = 2, max_batch: int = 16):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        B.check(lib().td_server_create(ctx.handle, max_inflight, max_batch, ctypes.byref(h)),
+                "td_server_create")
+        self.handle = h
+        self._live = {}
+
+    def submit(self, plan: Plan, sigma, dsdx=None, dsdy=None, fx=None, fy=None,
+               queue_if_full: bool = True):
+        req, fx, fy = plan.request(sigma, dsdx, dsdy, fx, fy)
+        t = ctypes.c_uint64()
+        B.check(lib().td_server_submit(self.handle, ctypes.byref(req), 1 if queue_if_full else 0,
+                                       ctypes.byref(t)), "td_server_submit")
+        self._live[t.value] = req
+        return t.value, fx, fy
+
+    def poll(self, ticket: int):
+        d, lat = ctypes.c_int32(), ctypes.c_double()
+        B.check(lib().td_server_poll(self.handle, ticket, ctypes.byref(d), ctypes.byref(lat)),
+                "td_server_poll")
+        if d.value:
+            self._live.pop(ticket, None)
+        return bool(d.value), lat.value
+
+    def cancel(self, ticket: int):
+        B.check(lib().td_server_cancel(self.handle, ticket), "td_server_cancel")
+        self._live.pop(ticket, None)
+
+    def drain(self):
+        B.check(lib().td_server_drain(self.handle), "td_server_drain")
+
+    def stats(self):
+        v = [ctypes.c_uint64() for _ in range(6)]
+        B.check(lib().td_server_stats(self.handle, *[ctypes.byref(x) for x in v]),
+                "td_server_stats")
+        return dict(zip(["completed", "cancelled", "refused", "deferred", "batches",
+                         "peak_queue"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.check(lib().td_server_destroy(self.handle), "td_server_destroy")
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

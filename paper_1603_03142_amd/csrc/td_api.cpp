@@ -1,0 +1,1842 @@
+// Host side of the thin-disk force solver: validation, planning of the four
+// FFT passes for a nested hierarchy, resident kernel spectra, solves,
+// batches (one launch per pass and transform length for many hierarchies,
+// optionally replayed from a HIP graph), the serving loop and the
+// launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "td_launch.h"
+#include "thindisk.h"
+
+using namespace td;
+
+namespace {
+
+thread_local std::string g_err;
+
+td_status fail(td_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define TD_HIP(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return fail(TD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));    \
+    } while (0)
+
+#define TD_TRY(expr)                    \
+    do {                                \
+        td_status _s = (expr);          \
+        if (_s != TD_OK) return _s;     \
+    } while (0)
+
+int floor_div(int a, int b)
+{
+    int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+int ceil_div(int a, int b) { return -floor_div(-a, b); }
+
+int fft_len(int n)
+{
+    int M = 16;
+    while (M < 2 * n) M *= 2;
+    return M;
+}
+
+size_t elem_size(td_dtype dt) { return dt == TD_F64 ? 16 : 8; }  // complex element
+
+enum Pass { P_ROWFWD = 0, P_GATHER = 1, P_SCATTER = 2, P_ROWINV = 3 };
+
+// Default sequences per workgroup: about 256 threads, LDS <= 64 KiB.
+int default_C(int pass, int M, td_dtype dt)
+{
+    int C = std::max(1, 2048 / M);
+    while (C > 1 && lds_bytes(pass, M, C, elem_size(dt)) > 64 * 1024) C /= 2;
+    return C;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+
+struct SpecEntry {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    int nphase = 0;
+};
+
+struct td_context {
+    int device = 0;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    std::atomic<size_t> spectra_bytes{0};
+    std::recursive_mutex mu;
+    std::map<int, void*> tw32, tw64;
+    std::map<std::tuple<int, int, int, int>, SpecEntry> spectra;  // (M, kind, m, dtype)
+    std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> C
+    hipStream_t stream = nullptr;                                 // plan-time work
+    std::vector<void*> allocs;
+
+    td_status alloc(size_t bytes, void** out)
+    {
+        if (budget && used.load() + bytes > budget)
+            return fail(TD_ENOMEM, "HBM budget exceeded: need " + std::to_string(bytes) +
+                                       " more bytes, " + std::to_string(used.load()) + " of " +
+                                       std::to_string(budget) + " in use");
+        hipError_t e = hipMalloc(out, bytes ? bytes : 16);
+        if (e != hipSuccess) return fail(TD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        used += bytes;
+        return TD_OK;
+    }
+    void release(void* p, size_t bytes)
+    {
+        if (p) {
+            (void)hipFree(p);
+            used -= bytes;
+        }
+    }
+    int C(int pass, int M, td_dtype dt)
+    {
+        std::lock_guard<std::recursive_mutex> lk(mu);
+        auto it = tune.find(std::make_tuple(pass, M, (int)dt));
+        return it != tune.end() ? it->second : default_C(pass, M, dt);
+    }
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+td_status twiddles(td_context* ctx, int M, td_dtype dt, const void** out)
+{
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto& tab = dt == TD_F64 ? ctx->tw64 : ctx->tw32;
+    auto it = tab.find(M);
+    if (it != tab.end()) {
+        *out = it->second;
+        return TD_OK;
+    }
+    std::vector<double> h64(2 * (size_t)M);
+    std::vector<float> h32(2 * (size_t)M);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < M; ++k) {
+        // exp(-2 pi i k / M) with the angle reduced to the first octant-free
+        // range by symmetry of the integer k.
+        long double a = two_pi * (long double)k / (long double)M;
+        long double c = cosl(a), s = -sinl(a);
+        if (4 * k == M) { c = 0; s = -1; }
+        if (2 * k == M) { c = -1; s = 0; }
+        if (4 * k == 3 * M) { c = 0; s = 1; }
+        h64[2 * k] = (double)c;
+        h64[2 * k + 1] = (double)s;
+        h32[2 * k] = (float)c;
+        h32[2 * k + 1] = (float)s;
+    }
+    size_t bytes = (dt == TD_F64 ? sizeof(double) : sizeof(float)) * 2 * (size_t)M;
+    void* d = nullptr;
+    TD_TRY(ctx->alloc(bytes, &d));
+    TD_HIP(hipMemcpy(d, dt == TD_F64 ? (void*)h64.data() : (void*)h32.data(), bytes,
+                     hipMemcpyHostToDevice));
+    tab[M] = d;
+    ctx->allocs.push_back(d);
+    *out = d;
+    return TD_OK;
+}
+
+template <typename Job>
+SegTable<Job> single_seg(const Job* jobs, int n, int slot_base, const void* aux, char* ws)
+{
+    SegTable<Job> s;
+    memset(&s, 0, sizeof(s));
+    s.nseg = 1;
+    s.start[0] = 0;
+    s.start[1] = n;
+    s.slot_base[0] = slot_base;
+    s.jobs[0] = jobs;
+    s.aux[0] = aux;
+    s.ws[0] = ws;
+    return s;
+}
+
+// Build (once per context) the kernel spectra of one (M, kind, m, dtype).
+// Stored phases: kind 1 -> (0,0); kinds 2/3 -> (kx, ky) in [0, m/2)^2, the
+// others being mirror images.  Layout [phase][X][M/2+1][M] complex.
+td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const SpecEntry** out)
+{
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto key = std::make_tuple(M, kind, m, (int)dt);
+    auto it = ctx->spectra.find(key);
+    if (it != ctx->spectra.end()) {
+        *out = &it->second;
+        return TD_OK;
+    }
+    const int hp = (kind == 1) ? 1 : m / 2;
+    const int nphase = hp * hp;
+    const size_t NCOL = M / 2 + 1;
+    const size_t per_phase = 6 * NCOL * (size_t)M;
+    SpecEntry e;
+    e.nphase = nphase;
+    e.bytes = per_phase * nphase * elem_size(dt);
+    TD_TRY(ctx->alloc(e.bytes, &e.ptr));
+    // FP64 scratch: the six real tables, their row transforms, pointer table.
+    void *table = nullptr, *rows = nullptr, *dptr = nullptr;
+    const size_t tbytes = 6 * (size_t)M * M * sizeof(double);
+    const size_t rbytes = per_phase * 16;
+    td_status st = ctx->alloc(tbytes, &table);
+    if (st == TD_OK) st = ctx->alloc(rbytes, &rows);
+    if (st == TD_OK) st = ctx->alloc(6 * sizeof(void*), &dptr);
+    const void* tw64 = nullptr;
+    if (st == TD_OK) st = twiddles(ctx, M, TD_F64, &tw64);
+    RowFwdJob* djobs = nullptr;
+    std::vector<RowFwdJob> jobs;
+    const int C = std::max(1, std::min(ctx->C(P_ROWFWD, M, TD_F64), 1024 / (M / 8)));
+    if (st == TD_OK) {
+        void* hp_ptr[6];
+        for (int X = 0; X < 6; ++X) hp_ptr[X] = (char*)table + X * (size_t)M * M * sizeof(double);
+        hipError_t he = hipMemcpy(dptr, hp_ptr, sizeof(hp_ptr), hipMemcpyHostToDevice);
+        if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
+        for (int X = 0; X < 6; ++X)
+            for (int r0 = 0; r0 < M; r0 += 2 * C) {
+                RowFwdJob j;
+                memset(&j, 0, sizeof(j));
+                j.src_slot = X;
+                j.n_src = M;
+                j.m = 1;
+                j.ld = M;
+                j.row0 = r0;
+                j.nrow = std::min(2 * C, M - r0);
+                j.scale = 1.0;
+                j.out = (int64_t)(X * NCOL * (size_t)M * 16);
+                jobs.push_back(j);
+            }
+    }
+    if (st == TD_OK) st = ctx->alloc(jobs.size() * sizeof(RowFwdJob), (void**)&djobs);
+    if (st == TD_OK) {
+        hipError_t he = hipMemcpy(djobs, jobs.data(), jobs.size() * sizeof(RowFwdJob),
+                                  hipMemcpyHostToDevice);
+        if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
+    }
+    for (int p = 0; st == TD_OK && p < nphase; ++p) {
+        TableJob tj;
+        memset(&tj, 0, sizeof(tj));
+        tj.M = M;
+        tj.kind = kind;
+        tj.m = (kind == 1) ? 1 : m;
+        tj.kx = p % hp;
+        tj.ky = p / hp;
+        tj.out = (double*)table;
+        hipError_t he = launch_table(tj, ctx->stream);
+        if (he == hipSuccess)
+            he = launch_row_fwd<double>(M, C, (int)jobs.size(),
+                                        single_seg<RowFwdJob>(djobs, (int)jobs.size(), 0, nullptr, (char*)rows),
+                                        (const void* const*)dptr, tw64, ctx->stream);
+        const int Cs = std::max(1, std::min(default_C(P_ROWINV, M, TD_F64), 1024 / (M / 8)));
+        void* dst = (char*)e.ptr + (size_t)p * per_phase * elem_size(dt);
+        if (he == hipSuccess)
+            he = dt == TD_F64 ? launch_spec_col<double>(M, Cs, rows, dst, tw64, ctx->stream)
+                              : launch_spec_col<float>(M, Cs, rows, dst, tw64, ctx->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) st = fail(TD_EDEVICE, std::string("kernel-table build: ") + hipGetErrorString(he));
+    }
+    ctx->release(table, tbytes);
+    ctx->release(rows, rbytes);
+    ctx->release(dptr, 6 * sizeof(void*));
+    if (djobs) ctx->release(djobs, jobs.size() * sizeof(RowFwdJob));
+    if (st != TD_OK) {
+        ctx->release(e.ptr, e.bytes);
+        return st;
+    }
+    ctx->spectra_bytes += e.bytes;
+    auto ins = ctx->spectra.emplace(key, e);
+    *out = &ins.first->second;
+    return TD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// hierarchy validation
+// ===========================================================================
+
+extern "C" td_status td_hierarchy_check(const td_hierarchy* h)
+{
+    if (!h || !h->levels) return fail(TD_EINVAL, "hierarchy or levels is NULL");
+    if (h->nlevels < 1 || h->nlevels > TD_MAX_LEVELS)
+        return fail(TD_EINVAL, "nlevels must be in 1.." + std::to_string(TD_MAX_LEVELS));
+    if (h->ratio != 2 && h->ratio != 4)
+        return fail(TD_EUNSUPPORTED, "refinement ratio must be 2 or 4");
+    if (!(h->h0 > 0) || !std::isfinite(h->h0) || !std::isfinite(h->x0) || !std::isfinite(h->y0))
+        return fail(TD_EINVAL, "h0 must be positive and x0, y0, h0 finite");
+    const td_level* L = h->levels;
+    if (L[0].ox != 0 || L[0].oy != 0) return fail(TD_EINVAL, "level 0 offsets must be 0");
+    long span = 1;
+    for (int l = 0; l < h->nlevels; ++l) {
+        if (L[l].n < 1 || L[l].n > TD_MAX_N)
+            return fail(TD_EINVAL, "level " + std::to_string(l) + ": n must be in 1.." +
+                                       std::to_string(TD_MAX_N));
+        if (L[l].ox < 0 || L[l].oy < 0)
+            return fail(TD_ENEST, "level " + std::to_string(l) + ": negative offset");
+        if (l == 0) continue;
+        span *= h->ratio;
+        if (span * (long)L[0].n > (1L << 30)) return fail(TD_EINVAL, "hierarchy too deep");
+        const int r = h->ratio;
+        if (L[l].n % r || L[l].ox % r || L[l].oy % r)
+            return fail(TD_EALIGN, "level " + std::to_string(l) +
+                                       ": size and offsets must be multiples of the ratio");
+        const int px0 = L[l].ox / r, py0 = L[l].oy / r, w = L[l].n / r;
+        if (px0 < L[l - 1].ox || py0 < L[l - 1].oy || px0 + w > L[l - 1].ox + L[l - 1].n ||
+            py0 + w > L[l - 1].oy + L[l - 1].n)
+            return fail(TD_ENEST, "level " + std::to_string(l) + " is not inside level " +
+                                      std::to_string(l - 1));
+    }
+    return TD_OK;
+}
+
+extern "C" td_status td_hierarchy_snap(td_hierarchy* h, td_level* levels, const double* cx,
+                                       const double* cy)
+{
+    if (!h || !levels || (h->nlevels > 1 && (!cx || !cy)))
+        return fail(TD_EINVAL, "NULL argument");
+    if (h->nlevels < 1 || h->nlevels > TD_MAX_LEVELS) return fail(TD_EINVAL, "bad nlevels");
+    if (h->ratio != 2 && h->ratio != 4) return fail(TD_EUNSUPPORTED, "ratio must be 2 or 4");
+    levels[0].ox = levels[0].oy = 0;
+    double hh = h->h0;
+    for (int l = 1; l < h->nlevels; ++l) {
+        const int r = h->ratio, n = levels[l].n, pn = levels[l - 1].n;
+        if (n % r) return fail(TD_EALIGN, "child size must be a multiple of the ratio");
+        const int span = n / r;
+        if (span > pn) return fail(TD_ENEST, "child wider than its parent");
+        const double px0 = h->x0 + levels[l - 1].ox * hh, py0 = h->y0 + levels[l - 1].oy * hh;
+        const double ext = n * hh / r;
+        long kx = (long)std::floor((cx[l - 1] - ext / 2 - px0) / hh + 0.5);
+        long ky = (long)std::floor((cy[l - 1] - ext / 2 - py0) / hh + 0.5);
+        kx = std::min<long>(std::max<long>(kx, 0), pn - span);
+        ky = std::min<long>(std::max<long>(ky, 0), pn - span);
+        levels[l].ox = r * (levels[l - 1].ox + (int)kx);
+        levels[l].oy = r * (levels[l - 1].oy + (int)ky);
+        hh /= r;
+    }
+    h->levels = levels;
+    return TD_OK;
+}
+
+// ===========================================================================
+// planning
+// ===========================================================================
+
+namespace {
+
+// Jobs of one transform length M, on the host and on the device.
+struct Group {
+    int M = 0;
+    int C[4] = {1, 1, 1, 1};
+    std::vector<RowFwdJob> rowfwd;
+    std::vector<ColGatherJob> gather;
+    std::vector<ColTerm> terms;
+    std::vector<ColScatterJob> scatter;
+    std::vector<ColScatterOut> souts;
+    std::vector<RowInvJob> rinv[2];  // [0] write, [1] accumulate
+    std::vector<RowInvContrib> contribs;
+    // device copies
+    RowFwdJob* d_rowfwd = nullptr;
+    ColGatherJob* d_gather = nullptr;
+    ColTerm* d_terms = nullptr;
+    ColScatterJob* d_scatter = nullptr;
+    ColScatterOut* d_souts = nullptr;
+    RowInvJob* d_rinv[2] = {nullptr, nullptr};
+    RowInvContrib* d_contribs = nullptr;
+};
+
+struct LevelG {
+    int n, ox, oy, M;
+    double h;
+    int cov_i0, cov_i1, cov_j0, cov_j1;
+};
+
+}  // namespace
+
+struct td_plan {
+    td_context* ctx = nullptr;
+    bool dry = false;          // host-only planning: no spectra, no device memory
+    td_dtype dt = TD_F32;
+    int ratio = 2;
+    int nlevels = 0;
+    std::vector<LevelG> lv;
+    double x0 = 0, y0 = 0, h0 = 0;
+    std::vector<Group> groups;
+    void* ws = nullptr;        // workspace for td_solve, allocated on first use
+    size_t ws_bytes = 0;
+    size_t spectra_bytes = 0;  // resident spectra this plan reads
+    size_t job_bytes = 0;
+    std::vector<std::pair<void*, size_t>> dev_allocs;
+    // per-solve pointer table
+    void** d_ptrs = nullptr;
+    static const int RING = 8;
+    void** h_stage[RING] = {};
+    hipEvent_t stage_ev[RING] = {};
+    bool stage_used[RING] = {};
+    int stage_next = 0;
+    uint64_t id = 0;
+};
+
+namespace {
+
+std::atomic<uint64_t> g_plan_ids{1};
+
+template <typename V>
+td_status upload(td_context* ctx, td_plan* p, const std::vector<V>& v, V** out)
+{
+    *out = nullptr;
+    if (v.empty()) return TD_OK;
+    const size_t b = v.size() * sizeof(V);
+    void* d = nullptr;
+    TD_TRY(ctx->alloc(b, &d));
+    p->dev_allocs.push_back({d, b});
+    p->job_bytes += b;
+    TD_HIP(hipMemcpy(d, v.data(), b, hipMemcpyHostToDevice));
+    *out = (V*)d;
+    return TD_OK;
+}
+
+Group& group_for(std::vector<Group>& groups, int M)
+{
+    for (auto& g : groups)
+        if (g.M == M) return g;
+    groups.push_back(Group());
+    groups.back().M = M;
+    return groups.back();
+}
+
+int ipow(int b, int e)
+{
+    int r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+
+// Kernel spectra of a plan; a dry (host-only) plan gets a stand-in entry
+// whose address is never dereferenced.
+td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out)
+{
+    if (!P->dry) return spectra(P->ctx, M, kind, m, P->dt, out);
+    static SpecEntry fake;
+    const int hp = kind == 1 ? 1 : m / 2;
+    fake.ptr = (void*)(uintptr_t)4096;
+    fake.nphase = hp * hp;
+    fake.bytes = (size_t)hp * hp * 6 * (M / 2 + 1) * (size_t)M * elem_size(P->dt);
+    *out = &fake;
+    return TD_OK;
+}
+
+// Emit every job of a plan (workspace addresses as byte offsets) and the
+// workspace size in complex elements.
+td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
+{
+    td_context* ctx = P->ctx;
+    const int L = P->nlevels, r = P->ratio;
+    const size_t es = elem_size(P->dt);
+    size_t off = 0;  // complex elements
+    auto take = [&](size_t n) {
+        size_t o = off;
+        off += (n + 31) & ~size_t(31);  // 256-byte aligned sub-buffers for FP32
+        return o;
+    };
+    auto ptr = [&](size_t o) -> int64_t { return (int64_t)(o * es); };
+    // ---- workspace layout
+    std::vector<size_t> own_in(L), own_out(L);
+    std::vector<std::vector<size_t>> ph_in(L, std::vector<size_t>(L)), c3_out(L, std::vector<size_t>(L));
+    std::vector<std::vector<int>> ph_nr(L, std::vector<int>(L)), c3_ld(L, std::vector<int>(L));
+    for (int l = 0; l < L; ++l) {
+        const LevelG& g = P->lv[l];
+        own_in[l] = take(3 * (size_t)(g.M / 2 + 1) * g.n);
+        own_out[l] = take(2 * (size_t)(g.M / 2 + 1) * g.n);
+    }
+    for (int t = 0; t < L; ++t)
+        for (int s = t + 1; s < L; ++s) {
+            const int m = ipow(r, s - t);
+            const LevelG &G = P->lv[t], &S = P->lv[s];
+            const int nr = (S.n + m - 1) / m + 1;
+            ph_nr[s][t] = nr;
+            ph_in[s][t] = take((size_t)m * m * 3 * (G.M / 2 + 1) * nr);
+            // coarser source s' = t, finer target t' = s: Case-3 outputs on lattice t
+            const int ld = floor_div(S.oy + S.n - 1, m) - floor_div(S.oy, m) + 1;
+            c3_ld[t][s] = ld;
+            c3_out[t][s] = take((size_t)m * m * 2 * (G.M / 2 + 1) * ld);
+        }
+    *ws_elems = off;
+    if (!emit) return TD_OK;
+
+    P->groups.clear();
+    for (int l = 0; l < L; ++l) {
+        Group& g = group_for(P->groups, P->lv[l].M);
+        for (int pass = 0; pass < 4; ++pass) g.C[pass] = ctx->C(pass, g.M, P->dt);
+    }
+    // ---- pass 1: row FFTs
+    for (int l = 0; l < L; ++l) {
+        const LevelG& G = P->lv[l];
+        Group& g = group_for(P->groups, G.M);
+        const int R = 2 * g.C[P_ROWFWD];
+        const size_t plane = (size_t)(G.M / 2 + 1) * G.n;
+        for (int f = 0; f < 3; ++f)
+            for (int r0 = 0; r0 < G.n; r0 += R) {
+                RowFwdJob j;
+                memset(&j, 0, sizeof(j));
+                j.src_slot = 5 * l + f;
+                j.n_src = G.n;
+                j.m = 1;
+                j.ld = G.n;
+                j.row0 = r0;
+                j.nrow = std::min(R, G.n - r0);
+                j.cov_i0 = G.cov_i0; j.cov_i1 = G.cov_i1; j.cov_j0 = G.cov_j0; j.cov_j1 = G.cov_j1;
+                j.scale = f == 0 ? 1.0 : G.h;
+                j.out = ptr(own_in[l] + f * plane);
+                g.rowfwd.push_back(j);
+            }
+        // polyphase sub-grids of every finer level s, placed on this lattice
+        for (int s = l + 1; s < L; ++s) {
+            const LevelG& S = P->lv[s];
+            const int m = ipow(r, s - l), nr = ph_nr[s][l];
+            for (int ky = 0; ky < m; ++ky)
+                for (int kx = 0; kx < m; ++kx) {
+                    const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
+                    const int lr_hi = floor_div(S.oy + S.n - 1 - ky, m) - G.oy;
+                    const int nrp = lr_hi - lr_lo + 1;
+                    if (nrp <= 0) continue;
+                    const int phase = ky * m + kx;
+                    // every stored row is written (rows past the source are
+                    // zeros), since the column pass reads all nr of them
+                    for (int f = 0; f < 3; ++f)
+                        for (int r0 = 0; r0 < nr; r0 += R) {
+                            RowFwdJob j;
+                            memset(&j, 0, sizeof(j));
+                            j.src_slot = 5 * s + f;
+                            j.n_src = S.n;
+                            j.m = m;
+                            j.row_off = m * G.oy + ky - S.oy;
+                            j.col_off = m * G.ox + kx - S.ox;
+                            j.lr_first = lr_lo;
+                            j.ld = nr;
+                            j.row0 = r0;
+                            j.nrow = std::min(R, nr - r0);
+                            j.cov_i0 = S.cov_i0; j.cov_i1 = S.cov_i1;
+                            j.cov_j0 = S.cov_j0; j.cov_j1 = S.cov_j1;
+                            j.scale = f == 0 ? 1.0 : S.h;
+                            j.out = ptr(ph_in[s][l] + ((size_t)phase * 3 + f) * (G.M / 2 + 1) * nr);
+                            g.rowfwd.push_back(j);
+                        }
+                }
+        }
+    }
+    // ---- pass 2: gather (own level + finer sources) on each lattice
+    for (int t = 0; t < L; ++t) {
+        const LevelG& G = P->lv[t];
+        Group& g = group_for(P->groups, G.M);
+        const SpecEntry* k1 = nullptr;
+        TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
+        const int term0 = (int)g.terms.size();
+        const size_t plane = (size_t)(G.M / 2 + 1) * G.n;
+        {
+            ColTerm tm;
+            memset(&tm, 0, sizeof(tm));
+            for (int f = 0; f < 3; ++f) tm.in[f] = ptr(own_in[t] + f * plane);
+            tm.kern = k1->ptr;
+            tm.in_ld = G.n;
+            tm.in_lr_first = 0;
+            tm.flip = 0;
+            g.terms.push_back(tm);
+        }
+        for (int s = t + 1; s < L; ++s) {
+            const LevelG& S = P->lv[s];
+            const int m = ipow(r, s - t), nr = ph_nr[s][t];
+            const SpecEntry* k2 = nullptr;
+            TD_TRY(plan_spectra(P, G.M, 2, m, &k2));
+            const size_t per_phase = 6 * (size_t)(G.M / 2 + 1) * G.M;
+            for (int ky = 0; ky < m; ++ky)
+                for (int kx = 0; kx < m; ++kx) {
+                    const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
+                    const int lr_hi = floor_div(S.oy + S.n - 1 - ky, m) - G.oy;
+                    if (lr_hi < lr_lo) continue;
+                    const int phase = ky * m + kx;
+                    ColTerm tm;
+                    memset(&tm, 0, sizeof(tm));
+                    const size_t fplane = (size_t)(G.M / 2 + 1) * nr;
+                    for (int f = 0; f < 3; ++f) tm.in[f] = ptr(ph_in[s][t] + ((size_t)phase * 3 + f) * fplane);
+                    const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
+                    tm.kern = (char*)k2->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
+                    tm.flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
+                    tm.in_ld = nr;
+                    tm.in_lr_first = lr_lo;
+                    g.terms.push_back(tm);
+                }
+        }
+        const int nterm = (int)g.terms.size() - term0;
+        const int C = g.C[P_GATHER];
+        for (int kx0 = 0; kx0 < G.M / 2 + 1; kx0 += C) {
+            ColGatherJob j;
+            memset(&j, 0, sizeof(j));
+            j.kx0 = kx0;
+            j.ncol = std::min(C, G.M / 2 + 1 - kx0);
+            j.term0 = term0;
+            j.nterm = nterm;
+            j.out_x = ptr(own_out[t]);
+            j.out_y = ptr(own_out[t] + (size_t)(G.M / 2 + 1) * G.n);
+            j.out_ld = G.n;
+            j.out_lr_first = 0;
+            g.gather.push_back(j);
+        }
+    }
+    // ---- pass 3: scatter (coarser source s onto every finer target)
+    for (int s = 0; s < L; ++s) {
+        if (s == L - 1) break;
+        const LevelG& S = P->lv[s];
+        Group& g = group_for(P->groups, S.M);
+        const int out0 = (int)g.souts.size();
+        const size_t cplane = (size_t)(S.M / 2 + 1);
+        for (int t = s + 1; t < L; ++t) {
+            const LevelG& T = P->lv[t];
+            const int m = ipow(r, t - s), ld = c3_ld[s][t];
+            const SpecEntry* k3 = nullptr;
+            TD_TRY(plan_spectra(P, S.M, 3, m, &k3));
+            const size_t per_phase = 6 * (size_t)(S.M / 2 + 1) * S.M;
+            for (int ky = 0; ky < m; ++ky)
+                for (int kx = 0; kx < m; ++kx) {
+                    const int phase = ky * m + kx;
+                    ColScatterOut o;
+                    memset(&o, 0, sizeof(o));
+                    const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
+                    o.kern = (char*)k3->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
+                    o.flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
+                    o.out_x = ptr(c3_out[s][t] + (size_t)phase * 2 * cplane * ld);
+                    o.out_y = ptr(c3_out[s][t] + ((size_t)phase * 2 + 1) * cplane * ld);
+                    o.out_ld = ld;
+                    o.out_lr_first = floor_div(T.oy, m) - S.oy;
+                    g.souts.push_back(o);
+                }
+        }
+        const int nout = (int)g.souts.size() - out0;
+        const int C = g.C[P_SCATTER];
+        const int chunk = 4;
+        const size_t plane = (size_t)(S.M / 2 + 1) * S.n;
+        for (int kx0 = 0; kx0 < S.M / 2 + 1; kx0 += C)
+            for (int o0 = 0; o0 < nout; o0 += chunk) {
+                ColScatterJob j;
+                memset(&j, 0, sizeof(j));
+                for (int f = 0; f < 3; ++f) j.in[f] = ptr(own_in[s] + f * plane);
+                j.in_ld = S.n;
+                j.in_lr_first = 0;
+                j.kx0 = kx0;
+                j.ncol = std::min(C, S.M / 2 + 1 - kx0);
+                j.out0 = out0 + o0;
+                j.nout = std::min(chunk, nout - o0);
+                g.scatter.push_back(j);
+            }
+    }
+    // ---- pass 4: row inverse, grouped by lattice length
+    for (int t = 0; t < L; ++t) {
+        const LevelG& T = P->lv[t];
+        // contributions: own lattice first, then every coarser source
+        struct Ctb { int M; RowInvContrib c; };
+        std::vector<Ctb> all;
+        {
+            RowInvContrib c;
+            memset(&c, 0, sizeof(c));
+            c.base = ptr(own_out[t]);
+            c.phase_stride = 0;
+            c.comp_stride = (int64_t)(T.M / 2 + 1) * T.n;
+            c.m = 1;
+            c.ld = T.n;
+            c.lr_first = 0;
+            c.ox_s = T.ox;
+            c.oy_s = T.oy;
+            all.push_back({T.M, c});
+        }
+        for (int s = 0; s < t; ++s) {
+            const LevelG& S = P->lv[s];
+            const int m = ipow(r, t - s), ld = c3_ld[s][t];
+            RowInvContrib c;
+            memset(&c, 0, sizeof(c));
+            c.base = ptr(c3_out[s][t]);
+            c.phase_stride = (int64_t)2 * (S.M / 2 + 1) * ld;
+            c.comp_stride = (int64_t)(S.M / 2 + 1) * ld;
+            c.m = m;
+            c.ld = ld;
+            c.lr_first = floor_div(T.oy, m) - S.oy;
+            c.ox_s = S.ox;
+            c.oy_s = S.oy;
+            all.push_back({S.M, c});
+        }
+        std::vector<int> Ms;
+        for (auto& a : all)
+            if (std::find(Ms.begin(), Ms.end(), a.M) == Ms.end()) Ms.push_back(a.M);
+        for (size_t gi = 0; gi < Ms.size(); ++gi) {
+            const int M = Ms[gi];
+            Group& g = group_for(P->groups, M);
+            const int c0 = (int)g.contribs.size();
+            for (auto& a : all)
+                if (a.M == M) g.contribs.push_back(a.c);
+            const int nc = (int)g.contribs.size() - c0;
+            const int C = g.C[P_ROWINV];
+            const int acc = (gi == 0) ? 0 : 1;  // Ms[0] is the own lattice's M
+            // at most 2M target columns per job: 16 outputs per thread
+            const int xchunk = std::min(T.n, 2 * M);
+            for (int y0 = 0; y0 < T.n; y0 += C)
+            for (int x0 = 0; x0 < T.n; x0 += xchunk) {
+                RowInvJob j;
+                memset(&j, 0, sizeof(j));
+                j.n_t = T.n;
+                j.ox_t = T.ox;
+                j.oy_t = T.oy;
+                j.y0 = y0;
+                j.ny = std::min(C, T.n - y0);
+                j.out_slot = 5 * t + 3;
+                j.cov_i0 = T.cov_i0; j.cov_i1 = T.cov_i1; j.cov_j0 = T.cov_j0; j.cov_j1 = T.cov_j1;
+                j.c0 = c0;
+                j.nc = nc;
+                j.accumulate = acc;
+                j.x0 = x0;
+                j.nx = std::min(xchunk, T.n - x0);
+                g.rinv[acc].push_back(j);
+            }
+        }
+    }
+    return TD_OK;
+}
+
+// Host-side bounds proof of every job against the workspace, the kernel
+// spectra, the fields and the launch shape, before anything is uploaded.
+td_status validate_jobs(td_plan* P)
+{
+    const size_t es = elem_size(P->dt);
+    const int64_t ws = (int64_t)P->ws_bytes;
+    auto in_ws = [&](int64_t off, int64_t elems) { return off >= 0 && off + elems * (int64_t)es <= ws; };
+    auto bad = [&](const char* what) { return fail(TD_EINVAL, std::string("plan validation: ") + what); };
+    std::vector<int> nsrc(5 * P->nlevels);
+    for (int l = 0; l < P->nlevels; ++l)
+        for (int f = 0; f < 5; ++f) nsrc[5 * l + f] = P->lv[l].n;
+    for (auto& g : P->groups) {
+        const int M = g.M, H = M / 2 + 1;
+        for (int pass = 0; pass < 4; ++pass) {
+            const int C = g.C[pass];
+            if (C < 1 || C * (M / 8) > 1024 || lds_bytes(pass, M, C, es) > 160 * 1024)
+                return bad("launch shape");
+        }
+        for (auto& j : g.rowfwd) {
+            if (j.src_slot < 0 || j.src_slot >= (int)nsrc.size() || nsrc[j.src_slot] != j.n_src)
+                return bad("row source");
+            if (j.row0 < 0 || j.nrow < 1 || j.nrow > 2 * g.C[P_ROWFWD] || j.row0 + j.nrow > j.ld)
+                return bad("row range");
+            if (!in_ws(j.out, (int64_t)H * j.ld)) return bad("row output");
+        }
+        for (auto& j : g.gather) {
+            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_GATHER] || j.kx0 + j.ncol > H)
+                return bad("gather columns");
+            if (j.out_lr_first < 0 || j.out_lr_first + j.out_ld > M) return bad("gather rows");
+            if (!in_ws(j.out_x, (int64_t)H * j.out_ld) || !in_ws(j.out_y, (int64_t)H * j.out_ld))
+                return bad("gather output");
+            if (j.term0 < 0 || j.term0 + j.nterm > (int)g.terms.size()) return bad("gather terms");
+        }
+        // rows written by the row pass, per output buffer
+        std::map<int64_t, std::vector<char>> written;
+        for (auto& j : g.rowfwd) {
+            auto& w = written[j.out];
+            if ((int)w.size() < j.ld) w.resize(j.ld, 0);
+            for (int r = j.row0; r < j.row0 + j.nrow; ++r) w[r] = 1;
+        }
+        auto covered = [&](int64_t off, int ld) {
+            auto it = written.find(off);
+            if (it == written.end() || (int)it->second.size() < ld) return false;
+            for (int r = 0; r < ld; ++r)
+                if (!it->second[r]) return false;
+            return true;
+        };
+        for (auto& t : g.terms) {
+            for (int f = 0; f < 3; ++f)
+                if (t.in[f] >= 0 && !covered(t.in[f], t.in_ld)) return bad("term reads unwritten rows");
+            for (int f = 0; f < 3; ++f)
+                if (t.in[f] >= 0 && !in_ws(t.in[f], (int64_t)H * t.in_ld)) return bad("term input");
+            if (t.in_lr_first < 0 || t.in_lr_first + t.in_ld > M || !t.kern) return bad("term rows");
+        }
+        for (auto& j : g.scatter) {
+            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_SCATTER] || j.kx0 + j.ncol > H)
+                return bad("scatter columns");
+            for (int f = 0; f < 3; ++f)
+                if (j.in[f] >= 0 && (!in_ws(j.in[f], (int64_t)H * j.in_ld) || !covered(j.in[f], j.in_ld)))
+                    return bad("scatter input");
+            if (j.in_lr_first < 0 || j.in_lr_first + j.in_ld > M) return bad("scatter rows");
+            if (j.out0 < 0 || j.out0 + j.nout > (int)g.souts.size()) return bad("scatter outputs");
+        }
+        for (auto& o : g.souts) {
+            if (o.out_lr_first < 0 || o.out_lr_first + o.out_ld > M || !o.kern) return bad("scatter out rows");
+            if (!in_ws(o.out_x, (int64_t)H * o.out_ld) || !in_ws(o.out_y, (int64_t)H * o.out_ld))
+                return bad("scatter out");
+        }
+        for (int a = 0; a < 2; ++a)
+            for (auto& j : g.rinv[a]) {
+                if (j.y0 < 0 || j.ny < 1 || j.ny > g.C[P_ROWINV] || j.y0 + j.ny > j.n_t) return bad("rinv rows");
+                if (j.out_slot < 0 || j.out_slot + 1 >= (int)nsrc.size()) return bad("rinv slot");
+                if (j.x0 < 0 || j.nx < 1 || j.x0 + j.nx > j.n_t || (long)j.nx > 2L * M)
+                    return bad("rinv columns");
+                if (j.c0 < 0 || j.c0 + j.nc > (int)g.contribs.size()) return bad("rinv contribs");
+                for (int k = 0; k < j.nc; ++k) {
+                    const RowInvContrib& c = g.contribs[j.c0 + k];
+                    // rows and columns reached by this job's targets
+                    for (int rr : {j.y0, j.y0 + j.ny - 1}) {
+                        const int gg = j.oy_t + rr, Jc = floor_div(gg, c.m);
+                        const int sr = Jc - c.oy_s - c.lr_first;
+                        if (sr < 0 || sr >= c.ld) return bad("rinv source row");
+                    }
+                    for (int ii : {j.x0, j.x0 + j.nx - 1}) {
+                        const int lc = floor_div(j.ox_t + ii, c.m) - c.ox_s;
+                        if (lc < 0 || lc >= M) return bad("rinv source col");
+                    }
+                    const int64_t last = c.base + ((int64_t)(c.m * c.m - 1) * c.phase_stride +
+                                                   c.comp_stride + (int64_t)H * c.ld) * (int64_t)es;
+                    if (c.base < 0 || last > ws) return bad("rinv contribution");
+                }
+            }
+    }
+    return TD_OK;
+}
+
+// Level geometry (sizes, offsets, FFT lengths, covered rectangles).
+td_status plan_geometry(td_plan* P, const td_hierarchy* h, td_dtype dt)
+{
+    P->dt = dt;
+    P->ratio = h->ratio;
+    P->nlevels = h->nlevels;
+    P->x0 = h->x0;
+    P->y0 = h->y0;
+    P->h0 = h->h0;
+    P->id = g_plan_ids++;
+    double hh = h->h0;
+    for (int l = 0; l < h->nlevels; ++l) {
+        LevelG g;
+        g.n = h->levels[l].n;
+        g.ox = h->levels[l].ox;
+        g.oy = h->levels[l].oy;
+        g.M = fft_len(g.n);
+        g.h = hh;
+        g.cov_i0 = g.cov_i1 = g.cov_j0 = g.cov_j1 = 0;
+        if (l + 1 < h->nlevels) {
+            const td_level& c = h->levels[l + 1];
+            g.cov_i0 = c.ox / h->ratio - g.ox;
+            g.cov_i1 = g.cov_i0 + c.n / h->ratio;
+            g.cov_j0 = c.oy / h->ratio - g.oy;
+            g.cov_j1 = g.cov_j0 + c.n / h->ratio;
+        }
+        if (dt == TD_F64 && g.M > 2048)
+            return fail(TD_EUNSUPPORTED, "FP64 plans support at most 1024 cells per side");
+        P->lv.push_back(g);
+        hh /= h->ratio;
+    }
+    return TD_OK;
+}
+
+td_status plan_upload(td_plan* P)
+{
+    td_context* ctx = P->ctx;
+    for (auto& g : P->groups) {
+        TD_TRY(upload(ctx, P, g.rowfwd, &g.d_rowfwd));
+        TD_TRY(upload(ctx, P, g.gather, &g.d_gather));
+        TD_TRY(upload(ctx, P, g.terms, &g.d_terms));
+        TD_TRY(upload(ctx, P, g.scatter, &g.d_scatter));
+        TD_TRY(upload(ctx, P, g.souts, &g.d_souts));
+        TD_TRY(upload(ctx, P, g.rinv[0], &g.d_rinv[0]));
+        TD_TRY(upload(ctx, P, g.rinv[1], &g.d_rinv[1]));
+        TD_TRY(upload(ctx, P, g.contribs, &g.d_contribs));
+    }
+    return TD_OK;
+}
+
+void plan_free(td_plan* P)
+{
+    if (!P) return;
+    td_context* ctx = P->ctx;
+    for (auto& a : P->dev_allocs) ctx->release(a.first, a.second);
+    P->dev_allocs.clear();
+    if (P->ws) ctx->release(P->ws, P->ws_bytes);
+    P->ws = nullptr;
+    if (P->d_ptrs) ctx->release(P->d_ptrs, sizeof(void*) * 5 * P->nlevels);
+    P->d_ptrs = nullptr;
+    for (int k = 0; k < td_plan::RING; ++k) {
+        if (P->stage_ev[k]) (void)hipEventDestroy(P->stage_ev[k]);
+        if (P->h_stage[k]) (void)hipHostFree(P->h_stage[k]);
+        P->stage_ev[k] = nullptr;
+        P->h_stage[k] = nullptr;
+    }
+}
+
+// Copy a pointer table to the device through a ring of pinned staging
+// buffers; a slot is reused only after its previous copy has completed.
+struct Stager {
+    static const int RING = 8;
+    void** host[RING] = {};
+    hipEvent_t ev[RING] = {};
+    bool used[RING] = {};
+    int next = 0;
+    size_t cap = 0;
+    td_status init(size_t nptr)
+    {
+        cap = nptr;
+        for (int k = 0; k < RING; ++k) {
+            TD_HIP(hipHostMalloc((void**)&host[k], sizeof(void*) * std::max<size_t>(nptr, 1)));
+            TD_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+        }
+        return TD_OK;
+    }
+    void destroy()
+    {
+        for (int k = 0; k < RING; ++k) {
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+            if (host[k]) (void)hipHostFree(host[k]);
+            ev[k] = nullptr;
+            host[k] = nullptr;
+        }
+    }
+    td_status push(void** dev, const std::vector<void*>& v, hipStream_t st)
+    {
+        const int k = next;
+        next = (next + 1) % RING;
+        if (used[k]) TD_HIP(hipEventSynchronize(ev[k]));
+        memcpy(host[k], v.data(), sizeof(void*) * v.size());
+        TD_HIP(hipMemcpyAsync(dev, host[k], sizeof(void*) * v.size(), hipMemcpyHostToDevice, st));
+        TD_HIP(hipEventRecord(ev[k], st));
+        used[k] = true;
+        return TD_OK;
+    }
+};
+
+}  // namespace
+
+// ===========================================================================
+// launching the four passes for a list of (plan, slot base) members
+// ===========================================================================
+
+namespace {
+
+struct Member {
+    td_plan* plan;
+    int slot_base;
+    char* ws;
+};
+
+template <typename Job>
+void push_seg(std::vector<SegTable<Job>>& tabs, std::vector<int>& totals, const Job* jobs, int n,
+              int slot_base, const void* aux, char* ws)
+{
+    if (n <= 0) return;
+    if (tabs.empty() || tabs.back().nseg == TD_MAX_SEGS) {
+        SegTable<Job> s;
+        memset(&s, 0, sizeof(s));
+        tabs.push_back(s);
+        totals.push_back(0);
+    }
+    SegTable<Job>& s = tabs.back();
+    s.start[s.nseg] = totals.back();
+    s.slot_base[s.nseg] = slot_base;
+    s.jobs[s.nseg] = jobs;
+    s.aux[s.nseg] = aux;
+    s.ws[s.nseg] = ws;
+    s.nseg += 1;
+    totals.back() += n;
+    s.start[s.nseg] = totals.back();
+}
+
+// One launch per (pass, M, <= TD_MAX_SEGS members), in pass order.
+td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>& mem,
+                         void* const* d_ptrs, hipStream_t st)
+{
+    std::vector<int> Ms;
+    for (auto& m : mem)
+        for (auto& g : m.plan->groups)
+            if (std::find(Ms.begin(), Ms.end(), g.M) == Ms.end()) Ms.push_back(g.M);
+    std::sort(Ms.begin(), Ms.end());
+    auto find_group = [](td_plan* p, int M) -> Group* {
+        for (auto& g : p->groups)
+            if (g.M == M) return &g;
+        return nullptr;
+    };
+    const bool f64 = dt == TD_F64;
+    // C per (pass, M) must agree across members; members built with other
+    // tunings are launched in separate groups.
+    for (int pass = 0; pass < 5; ++pass) {
+        for (int M : Ms) {
+            const void* tw = nullptr;
+            TD_TRY(twiddles(ctx, M, dt, &tw));
+            // partition members by C of this pass
+            std::map<int, std::vector<std::pair<Group*, const Member*>>> byC;
+            for (auto& m : mem) {
+                Group* g = find_group(m.plan, M);
+                if (!g) continue;
+                const int pi = pass == 4 ? P_ROWINV : pass;
+                byC[g->C[pi]].push_back({g, &m});
+            }
+            for (auto& kv : byC) {
+                const int C = kv.first;
+                hipError_t e = hipSuccess;
+                if (pass == P_ROWFWD) {
+                    std::vector<SegTable<RowFwdJob>> t;
+                    std::vector<int> n;
+                    for (auto& gs : kv.second)
+                        push_seg(t, n, gs.first->d_rowfwd, (int)gs.first->rowfwd.size(), gs.second->slot_base,
+                                 nullptr, gs.second->ws);
+                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
+                        e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st)
+                                : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st);
+                } else if (pass == P_GATHER) {
+                    std::vector<SegTable<ColGatherJob>> t;
+                    std::vector<int> n;
+                    for (auto& gs : kv.second)
+                        push_seg(t, n, gs.first->d_gather, (int)gs.first->gather.size(),
+                                 gs.second->slot_base, (const void*)gs.first->d_terms, gs.second->ws);
+                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
+                        e = f64 ? launch_col_gather<double>(M, C, n[i], t[i], tw, st)
+                                : launch_col_gather<float>(M, C, n[i], t[i], tw, st);
+                } else if (pass == P_SCATTER) {
+                    std::vector<SegTable<ColScatterJob>> t;
+                    std::vector<int> n;
+                    for (auto& gs : kv.second)
+                        push_seg(t, n, gs.first->d_scatter, (int)gs.first->scatter.size(),
+                                 gs.second->slot_base, (const void*)gs.first->d_souts, gs.second->ws);
+                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
+                        e = f64 ? launch_col_scatter<double>(M, C, n[i], t[i], tw, st)
+                                : launch_col_scatter<float>(M, C, n[i], t[i], tw, st);
+                } else {
+                    const int a = pass == P_ROWINV ? 0 : 1;
+                    std::vector<SegTable<RowInvJob>> t;
+                    std::vector<int> n;
+                    for (auto& gs : kv.second)
+                        push_seg(t, n, gs.first->d_rinv[a], (int)gs.first->rinv[a].size(),
+                                 gs.second->slot_base, (const void*)gs.first->d_contribs,
+                                 gs.second->ws);
+                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
+                        e = f64 ? launch_row_inv<double>(M, C, n[i], t[i], d_ptrs, tw, st)
+                                : launch_row_inv<float>(M, C, n[i], t[i], d_ptrs, tw, st);
+                }
+                if (e != hipSuccess)
+                    return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    return TD_OK;
+}
+
+td_status fill_ptrs(const td_request& q, int nlevels, std::vector<void*>& v, size_t base)
+{
+    if (!q.sigma || !q.fx || !q.fy) return fail(TD_EINVAL, "sigma, fx and fy are required");
+    for (int l = 0; l < nlevels; ++l) {
+        if (!q.sigma[l] || !q.fx[l] || !q.fy[l])
+            return fail(TD_EINVAL, "NULL sigma/fx/fy pointer at level " + std::to_string(l));
+        v[base + 5 * l + 0] = (void*)q.sigma[l];
+        v[base + 5 * l + 1] = q.dsdx ? (void*)q.dsdx[l] : nullptr;
+        v[base + 5 * l + 2] = q.dsdy ? (void*)q.dsdy[l] : nullptr;
+        v[base + 5 * l + 3] = q.fx[l];
+        v[base + 5 * l + 4] = q.fy[l];
+    }
+    return TD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// public: context
+// ===========================================================================
+
+extern "C" td_status td_context_create(int dev, size_t budget, td_context** out)
+{
+    if (!out) return fail(TD_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    TD_HIP(hipGetDeviceCount(&ndev));
+    if (dev < 0 || dev >= ndev) return fail(TD_EINVAL, "no such HIP device");
+    DeviceGuard g(dev);
+    hipDeviceProp_t prop;
+    TD_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos)
+        return fail(TD_EUNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    TD_HIP(prepare_kernels());
+    auto* c = new td_context();
+    c->device = dev;
+    c->budget = budget;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(TD_EDEVICE, hipGetErrorString(e));
+    }
+    *out = c;
+    return TD_OK;
+}
+
+extern "C" td_status td_context_destroy(td_context* c)
+{
+    if (!c) return fail(TD_EINVAL, "NULL context");
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->spectra) c->release(kv.second.ptr, kv.second.bytes);
+    for (auto& kv : c->tw32) (void)hipFree(kv.second);
+    for (auto& kv : c->tw64) (void)hipFree(kv.second);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return TD_OK;
+}
+
+extern "C" td_status td_context_usage(const td_context* c, size_t* in_use, size_t* spectra)
+{
+    if (!c) return fail(TD_EINVAL, "NULL context");
+    if (in_use) *in_use = c->used.load();
+    if (spectra) *spectra = c->spectra_bytes.load();
+    return TD_OK;
+}
+
+// ===========================================================================
+// public: plans and solves
+// ===========================================================================
+
+extern "C" td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_dtype dt,
+                                    td_plan** out)
+{
+    if (!ctx || !out) return fail(TD_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (dt != TD_F32 && dt != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
+    TD_TRY(td_hierarchy_check(h));
+    DeviceGuard dg(ctx->device);
+    std::unique_ptr<td_plan> P(new td_plan());
+    P->ctx = ctx;
+    TD_TRY(plan_geometry(P.get(), h, dt));
+    size_t elems = 0;
+    td_status st = build_jobs(P.get(), &elems, true);
+    P->ws_bytes = elems * elem_size(dt);
+    if (st == TD_OK) st = validate_jobs(P.get());
+    if (st == TD_OK) st = plan_upload(P.get());
+    if (st == TD_OK) st = ctx->alloc(sizeof(void*) * 5 * P->nlevels, (void**)&P->d_ptrs);
+    for (int k = 0; st == TD_OK && k < td_plan::RING; ++k) {
+        hipError_t e = hipHostMalloc((void**)&P->h_stage[k], sizeof(void*) * 5 * P->nlevels);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&P->stage_ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(e));
+    }
+    if (st != TD_OK) {
+        plan_free(P.get());
+        return st;
+    }
+    // spectra bytes this plan reads
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        std::vector<const void*> seen;
+        for (auto& g : P->groups) {
+            for (auto& t : g.terms)
+                if (std::find(seen.begin(), seen.end(), t.kern) == seen.end()) seen.push_back(t.kern);
+            for (auto& o : g.souts)
+                if (std::find(seen.begin(), seen.end(), o.kern) == seen.end()) seen.push_back(o.kern);
+        }
+        size_t b = 0;
+        for (auto& kv : ctx->spectra) {
+            const char* lo = (const char*)kv.second.ptr;
+            for (const void* p : seen)
+                if ((const char*)p >= lo && (const char*)p < lo + kv.second.bytes) {
+                    b += kv.second.bytes;
+                    break;
+                }
+        }
+        P->spectra_bytes = b;
+    }
+    *out = P.release();
+    return TD_OK;
+}
+
+extern "C" td_status td_plan_check(const td_hierarchy* h, td_dtype dt, size_t* workspace_bytes)
+{
+    if (dt != TD_F32 && dt != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
+    TD_TRY(td_hierarchy_check(h));
+    static td_context host_ctx;  // default launch shapes, no device
+    td_plan P;
+    P.ctx = &host_ctx;
+    P.dry = true;
+    TD_TRY(plan_geometry(&P, h, dt));
+    size_t elems = 0;
+    TD_TRY(build_jobs(&P, &elems, true));
+    P.ws_bytes = elems * elem_size(dt);
+    TD_TRY(validate_jobs(&P));
+    if (workspace_bytes) *workspace_bytes = P.ws_bytes;
+    return TD_OK;
+}
+
+extern "C" td_status td_plan_footprint(const td_plan* p, size_t* ws, size_t* spec)
+{
+    if (!p) return fail(TD_EINVAL, "NULL plan");
+    if (ws) *ws = p->ws_bytes + p->job_bytes + sizeof(void*) * 5 * p->nlevels;
+    if (spec) *spec = p->spectra_bytes;
+    return TD_OK;
+}
+
+extern "C" td_status td_plan_destroy(td_plan* p)
+{
+    if (!p) return fail(TD_EINVAL, "NULL plan");
+    DeviceGuard g(p->ctx->device);
+    for (int k = 0; k < td_plan::RING; ++k)
+        if (p->stage_used[k]) (void)hipEventSynchronize(p->stage_ev[k]);
+    plan_free(p);
+    delete p;
+    return TD_OK;
+}
+
+extern "C" td_status td_solve(const td_request* req, void* stream)
+{
+    if (!req || !req->plan) return fail(TD_EINVAL, "NULL request or plan");
+    td_plan* P = req->plan;
+    DeviceGuard g(P->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<void*> v(5 * P->nlevels, nullptr);
+    TD_TRY(fill_ptrs(*req, P->nlevels, v, 0));
+    if (!P->ws) TD_TRY(P->ctx->alloc(P->ws_bytes, &P->ws));
+    const int k = P->stage_next;
+    P->stage_next = (k + 1) % td_plan::RING;
+    if (P->stage_used[k]) TD_HIP(hipEventSynchronize(P->stage_ev[k]));
+    memcpy(P->h_stage[k], v.data(), sizeof(void*) * v.size());
+    TD_HIP(hipMemcpyAsync(P->d_ptrs, P->h_stage[k], sizeof(void*) * v.size(),
+                          hipMemcpyHostToDevice, st));
+    TD_HIP(hipEventRecord(P->stage_ev[k], st));
+    P->stage_used[k] = true;
+    std::vector<Member> mem{{P, 0, (char*)P->ws}};
+    return launch_members(P->ctx, P->dt, mem, P->d_ptrs, st);
+}
+
+// ===========================================================================
+// public: batches
+// ===========================================================================
+
+struct td_batch {
+    td_context* ctx = nullptr;
+    td_dtype dt = TD_F32;
+    std::vector<td_plan*> plans;  // borrowed: must outlive the batch
+    std::vector<Member> mem;
+    size_t nslots = 0;
+    void** d_ptrs = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    Stager stager;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+extern "C" td_status td_batch_create(td_context* ctx, int32_t count, td_plan* const* plans,
+                                     td_batch** out)
+{
+    if (!ctx || !plans || !out || count < 1) return fail(TD_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    DeviceGuard dg(ctx->device);
+    std::unique_ptr<td_batch> B(new td_batch());
+    B->ctx = ctx;
+    B->dt = plans[0] ? plans[0]->dt : TD_F32;
+    std::vector<size_t> ws_off;
+    for (int k = 0; k < count; ++k) {
+        td_plan* p = plans[k];
+        if (!p || p->ctx != ctx || p->dt != B->dt)
+            return fail(TD_EINVAL, "batch members must be plans of one context and dtype");
+        B->plans.push_back(p);
+        ws_off.push_back(B->ws_bytes);
+        B->mem.push_back({p, (int)B->nslots, nullptr});
+        B->nslots += 5 * p->nlevels;
+        B->ws_bytes += (p->ws_bytes + 255) & ~size_t(255);
+    }
+    td_status st = ctx->alloc(B->ws_bytes, &B->ws);
+    if (st == TD_OK) st = ctx->alloc(sizeof(void*) * B->nslots, (void**)&B->d_ptrs);
+    if (st == TD_OK) st = B->stager.init(B->nslots);
+    if (st != TD_OK) {
+        if (B->ws) ctx->release(B->ws, B->ws_bytes);
+        if (B->d_ptrs) ctx->release(B->d_ptrs, sizeof(void*) * B->nslots);
+        B->stager.destroy();
+        return st;
+    }
+    for (size_t k = 0; k < B->mem.size(); ++k) B->mem[k].ws = (char*)B->ws + ws_off[k];
+    *out = B.release();
+    return TD_OK;
+}
+
+extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use_graph,
+                                    void* stream)
+{
+    if (!B || !reqs) return fail(TD_EINVAL, "NULL batch or requests");
+    DeviceGuard dg(B->ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<void*> v(B->nslots, nullptr);
+    for (size_t k = 0; k < B->plans.size(); ++k) {
+        if (reqs[k].plan != B->plans[k]) return fail(TD_EINVAL, "request plan does not match the batch");
+        TD_TRY(fill_ptrs(reqs[k], B->plans[k]->nlevels, v, B->mem[k].slot_base));
+    }
+    if (use_graph && !B->exec) {
+        // Capture once on a private stream; the pointer-table copy stays
+        // outside the graph so every replay reads the current pointers.
+        if (!B->graph_stream) TD_HIP(hipStreamCreateWithFlags(&B->graph_stream, hipStreamNonBlocking));
+        for (auto& m : B->mem)
+            for (auto& g : m.plan->groups) {
+                const void* tw = nullptr;
+                TD_TRY(twiddles(B->ctx, g.M, B->dt, &tw));
+            }
+        TD_HIP(hipStreamBeginCapture(B->graph_stream, hipStreamCaptureModeThreadLocal));
+        td_status s = launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, B->graph_stream);
+        hipGraph_t gph = nullptr;
+        hipError_t e = hipStreamEndCapture(B->graph_stream, &gph);
+        if (s != TD_OK) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return s;
+        }
+        if (e != hipSuccess) return fail(TD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        B->graph = gph;
+        TD_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    }
+    TD_TRY(B->stager.push(B->d_ptrs, v, st));
+    if (!use_graph) return launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, st);
+    TD_HIP(hipGraphLaunch(B->exec, st));
+    return TD_OK;
+}
+
+extern "C" td_status td_batch_footprint(const td_batch* B, size_t* ws)
+{
+    if (!B) return fail(TD_EINVAL, "NULL batch");
+    if (ws) *ws = B->ws_bytes;
+    return TD_OK;
+}
+
+extern "C" td_status td_batch_destroy(td_batch* B)
+{
+    if (!B) return fail(TD_EINVAL, "NULL batch");
+    DeviceGuard dg(B->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->graph_stream) (void)hipStreamDestroy(B->graph_stream);
+    if (B->ws) B->ctx->release(B->ws, B->ws_bytes);
+    if (B->d_ptrs) B->ctx->release(B->d_ptrs, sizeof(void*) * B->nslots);
+    B->stager.destroy();
+    delete B;
+    return TD_OK;
+}
+
+// ===========================================================================
+// public: serving loop
+// ===========================================================================
+
+namespace {
+
+struct Ticket {
+    uint64_t id = 0;
+    td_plan* plan = nullptr;
+    std::vector<void*> ptrs;  // 5 per level: sigma, dsdx, dsdy, fx, fy
+    double t_submit = 0, t_done = 0;
+    int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
+    size_t need = 0;
+};
+
+struct Flight {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void** d_ptrs = nullptr;
+    size_t cap = 0;
+    Stager stager;
+    std::vector<uint64_t> tickets;
+    std::vector<std::pair<void*, size_t>> ws;  // workspace blocks bound to the tickets
+    bool active = false;
+};
+
+}  // namespace
+
+struct td_server {
+    td_context* ctx = nullptr;
+    int max_inflight = 2, max_batch = 16;
+    size_t queue_cap = 1 << 16;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, Ticket> tickets;
+    std::vector<Flight> flights;
+    std::multimap<size_t, void*> pool;  // idle workspace blocks (held, counted as used)
+    std::vector<std::pair<void*, size_t>> pool_all;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_id = 1;
+    uint64_t completed = 0, cancelled = 0, refused = 0, deferred = 0, batches = 0, peak_queue = 0;
+    std::string worker_error;
+};
+
+namespace {
+
+// Workspace for one admitted solve: reuse an idle block of a close size, or
+// allocate against the context's HBM budget.  Returns nullptr when the
+// budget has no room (the request waits).
+void* pool_get(td_server* S, size_t need, size_t* got)
+{
+    auto it = S->pool.lower_bound(need);
+    if (it != S->pool.end() && it->first <= 2 * need + (1 << 20)) {
+        void* p = it->second;
+        *got = it->first;
+        S->pool.erase(it);
+        return p;
+    }
+    void* p = nullptr;
+    if (S->ctx->alloc(need, &p) != TD_OK) {
+        // free idle blocks and retry once
+        for (auto& kv : S->pool) {
+            for (auto a = S->pool_all.begin(); a != S->pool_all.end(); ++a)
+                if (a->first == kv.second) {
+                    S->pool_all.erase(a);
+                    break;
+                }
+            S->ctx->release(kv.second, kv.first);
+        }
+        S->pool.clear();
+        if (S->ctx->alloc(need, &p) != TD_OK) return nullptr;
+    }
+    S->pool_all.push_back({p, need});
+    *got = need;
+    return p;
+}
+
+void server_loop(td_server* S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        // retire finished flights
+        bool progressed = false;
+        for (auto& f : S->flights) {
+            if (!f.active || hipEventQuery(f.done) != hipSuccess) continue;
+            const double t = now_s();
+            for (uint64_t id : f.tickets) {
+                auto it = S->tickets.find(id);
+                if (it != S->tickets.end()) {
+                    it->second.state = 2;
+                    it->second.t_done = t;
+                }
+                S->completed++;
+            }
+            for (auto& w : f.ws) S->pool.insert({w.second, w.first});
+            f.ws.clear();
+            f.tickets.clear();
+            f.active = false;
+            progressed = true;
+        }
+        if (progressed) S->cv_done.notify_all();
+        // continuous batching: every free flight slot takes the requests
+        // that have arrived so far (FIFO, up to max_batch) that fit in HBM
+        Flight* slot = nullptr;
+        for (auto& f : S->flights)
+            if (!f.active) {
+                slot = &f;
+                break;
+            }
+        if (slot && !S->queue.empty()) {
+            std::vector<uint64_t> pick;
+            std::vector<Member> mem;
+            size_t nslots = 0;
+            bool waited = false;
+            for (auto it = S->queue.begin(); it != S->queue.end() && (int)pick.size() < S->max_batch;) {
+                Ticket& T = S->tickets[*it];
+                if (T.state == 3) {
+                    it = S->queue.erase(it);
+                    continue;
+                }
+                if (!mem.empty() && mem[0].plan->dt != T.plan->dt) {
+                    ++it;
+                    continue;
+                }
+                size_t got = 0;
+                void* ws = pool_get(S, T.need, &got);
+                if (!ws) {
+                    waited = true;
+                    ++it;
+                    continue;
+                }
+                slot->ws.push_back({ws, got});
+                mem.push_back({T.plan, (int)nslots, (char*)ws});
+                nslots += 5 * T.plan->nlevels;
+                pick.push_back(*it);
+                it = S->queue.erase(it);
+            }
+            if (waited) S->deferred++;
+            if (!pick.empty()) {
+                std::vector<void*> v(nslots, nullptr);
+                for (size_t k = 0; k < pick.size(); ++k) {
+                    Ticket& T = S->tickets[pick[k]];
+                    T.state = 1;
+                    std::copy(T.ptrs.begin(), T.ptrs.end(), v.begin() + mem[k].slot_base);
+                }
+                td_status st = TD_OK;
+                if (slot->cap < nslots) {
+                    if (slot->d_ptrs) S->ctx->release(slot->d_ptrs, sizeof(void*) * slot->cap);
+                    slot->stager.destroy();
+                    const size_t cap = std::max<size_t>(nslots, 1024);
+                    st = S->ctx->alloc(sizeof(void*) * cap, (void**)&slot->d_ptrs);
+                    if (st == TD_OK) st = slot->stager.init(cap);
+                    slot->cap = st == TD_OK ? cap : 0;
+                }
+                slot->active = true;
+                slot->tickets = pick;
+                S->batches++;
+                const td_dtype dt = mem[0].plan->dt;
+                lk.unlock();
+                if (st == TD_OK) st = slot->stager.push(slot->d_ptrs, v, slot->stream);
+                if (st == TD_OK) st = launch_members(S->ctx, dt, mem, slot->d_ptrs, slot->stream);
+                if (st == TD_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess)
+                    st = fail(TD_EDEVICE, "event record");
+                lk.lock();
+                if (st != TD_OK) S->worker_error = td_last_error();
+                continue;
+            }
+        }
+        bool any_active = false;
+        for (auto& f : S->flights) any_active |= f.active;
+        if (S->stop && S->queue.empty() && !any_active) break;
+        if (any_active)
+            S->cv.wait_for(lk, std::chrono::microseconds(20));
+        else
+            S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+    }
+}
+
+}  // namespace
+
+extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int32_t max_batch,
+                                      td_server** out)
+{
+    if (!ctx || !out || max_inflight < 1 || max_batch < 1 || max_batch > 4096)
+        return fail(TD_EINVAL, "bad server arguments");
+    DeviceGuard dg(ctx->device);
+    std::unique_ptr<td_server> S(new td_server());
+    S->ctx = ctx;
+    S->max_inflight = max_inflight;
+    S->max_batch = max_batch;
+    S->flights.resize(max_inflight);
+    for (auto& f : S->flights) {
+        TD_HIP(hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking));
+        TD_HIP(hipEventCreateWithFlags(&f.done, hipEventDisableTiming));
+    }
+    td_server* raw = S.release();
+    raw->worker = std::thread(server_loop, raw);
+    *out = raw;
+    return TD_OK;
+}
+
+extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32_t queue_if_full,
+                                      uint64_t* ticket)
+{
+    if (!S || !req || !req->plan || !ticket) return fail(TD_EINVAL, "NULL argument");
+    if (req->plan->ctx != S->ctx) return fail(TD_EINVAL, "plan belongs to another context");
+    const td_plan* P = req->plan;
+    Ticket T;
+    T.plan = req->plan;
+    T.ptrs.assign(5 * P->nlevels, nullptr);
+    TD_TRY(fill_ptrs(*req, P->nlevels, T.ptrs, 0));
+    T.need = (P->ws_bytes + 255) & ~size_t(255);
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->ctx->budget && T.need > S->ctx->budget) {
+        S->refused++;
+        return fail(TD_ENOMEM, "request workspace exceeds the HBM budget");
+    }
+    if (S->queue.size() >= S->queue_cap && !queue_if_full) {
+        S->refused++;
+        return fail(TD_EBUSY, "server queue full");
+    }
+    T.id = S->next_id++;
+    T.t_submit = now_s();
+    *ticket = T.id;
+    S->tickets[T.id] = std::move(T);
+    S->queue.push_back(*ticket);
+    S->peak_queue = std::max<uint64_t>(S->peak_queue, S->queue.size());
+    S->cv.notify_all();
+    return TD_OK;
+}
+
+extern "C" td_status td_server_poll(td_server* S, uint64_t ticket, int32_t* done, double* lat)
+{
+    if (!S || !done) return fail(TD_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->worker_error.empty()) return fail(TD_EDEVICE, "server: " + S->worker_error);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) return fail(TD_EINVAL, "unknown ticket");
+    *done = it->second.state == 2 ? 1 : 0;
+    if (lat) *lat = it->second.state == 2 ? it->second.t_done - it->second.t_submit : 0.0;
+    return TD_OK;
+}
+
+extern "C" td_status td_server_drain(td_server* S)
+{
+    if (!S) return fail(TD_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv.notify_all();
+    S->cv_done.wait(lk, [&] {
+        if (!S->worker_error.empty()) return true;
+        if (!S->queue.empty()) return false;
+        for (auto& f : S->flights)
+            if (f.active) return false;
+        return true;
+    });
+    if (!S->worker_error.empty()) return fail(TD_EDEVICE, "server: " + S->worker_error);
+    return TD_OK;
+}
+
+extern "C" td_status td_server_cancel(td_server* S, uint64_t ticket)
+{
+    if (!S) return fail(TD_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end() || it->second.state != 0)
+        return fail(TD_EINVAL, "ticket unknown or already started");
+    it->second.state = 3;
+    S->cancelled++;
+    S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), ticket), S->queue.end());
+    S->cv_done.notify_all();
+    return TD_OK;
+}
+
+extern "C" td_status td_server_stats(const td_server* S, uint64_t* completed, uint64_t* cancelled,
+                                     uint64_t* refused, uint64_t* deferred, uint64_t* batches,
+                                     uint64_t* peak_queue)
+{
+    if (!S) return fail(TD_EINVAL, "NULL server");
+    auto* s = const_cast<td_server*>(S);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (completed) *completed = s->completed;
+    if (cancelled) *cancelled = s->cancelled;
+    if (refused) *refused = s->refused;
+    if (deferred) *deferred = s->deferred;
+    if (batches) *batches = s->batches;
+    if (peak_queue) *peak_queue = s->peak_queue;
+    return TD_OK;
+}
+
+extern "C" td_status td_server_destroy(td_server* S)
+{
+    if (!S) return fail(TD_EINVAL, "NULL server");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    DeviceGuard dg(S->ctx->device);
+    for (auto& f : S->flights) {
+        if (f.stream) (void)hipStreamSynchronize(f.stream);
+        if (f.d_ptrs) S->ctx->release(f.d_ptrs, sizeof(void*) * f.cap);
+        f.stager.destroy();
+        if (f.done) (void)hipEventDestroy(f.done);
+        if (f.stream) (void)hipStreamDestroy(f.stream);
+    }
+    for (auto& a : S->pool_all) S->ctx->release(a.first, a.second);
+    delete S;
+    return TD_OK;
+}
+
+// ===========================================================================
+// public: autotuner
+// ===========================================================================
+
+namespace {
+
+std::string arch_name(int dev)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+// Minimal reader/writer for the tuning database: one JSON object per line,
+// {"arch":"gfx950","dtype":0,"pass":1,"M":512,"C":2,"us":12.3}
+void db_load(td_context* ctx, const char* path, const std::string& arch)
+{
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        auto num = [&](const char* key, double* v) {
+            size_t p = line.find(std::string("\"") + key + "\":");
+            if (p == std::string::npos) return false;
+            *v = atof(line.c_str() + p + strlen(key) + 3);
+            return true;
+        };
+        double dt, pass, M, C;
+        if (line.find("\"arch\":\"" + arch + "\"") == std::string::npos) continue;
+        if (num("dtype", &dt) && num("pass", &pass) && num("M", &M) && num("C", &C))
+            ctx->tune[std::make_tuple((int)pass, (int)M, (int)dt)] = (int)C;
+    }
+}
+
+}  // namespace
+
+extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, const char* db_path)
+{
+    if (!ctx || max_M < 16) return fail(TD_EINVAL, "bad autotune arguments");
+    DeviceGuard dg(ctx->device);
+    const std::string arch = arch_name(ctx->device);
+    if (db_path) {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        db_load(ctx, db_path, arch);
+        bool all = true;
+        for (int M = 64; M <= max_M; M *= 2)
+            for (int pass = 0; pass < 4; ++pass)
+                all &= ctx->tune.count(std::make_tuple(pass, M, (int)dt)) > 0;
+        if (all) return TD_OK;
+    }
+    std::ofstream db;
+    if (db_path) db.open(db_path, std::ios::app);
+    hipEvent_t e0, e1;
+    TD_HIP(hipEventCreate(&e0));
+    TD_HIP(hipEventCreate(&e1));
+    td_status result = TD_OK;
+    for (int M = 64; M <= max_M && result == TD_OK; M *= 2) {
+        // a two-level hierarchy whose lattices have length M exercises all passes
+        const int n = M / 2;
+        td_level lv[2] = {{n, 0, 0}, {n, n / 2, n / 2}};
+        td_hierarchy h{-1.0, -1.0, 2.0 / n, 2, 2, lv};
+        const size_t es = dt == TD_F64 ? 8 : 4;
+        void* bufs[10] = {};
+        for (int k = 0; k < 10 && result == TD_OK; ++k) {
+            result = ctx->alloc((size_t)n * n * es, &bufs[k]);
+            if (result == TD_OK) (void)hipMemset(bufs[k], 0, (size_t)n * n * es);
+        }
+        for (int pass = 0; pass < 4 && result == TD_OK; ++pass) {
+            int bestC = -1;
+            double best = 1e30;
+            for (int C = 1; C * (M / 8) <= 1024; C *= 2) {
+                if (lds_bytes(pass, M, C, elem_size(dt)) > 160 * 1024) break;
+                {
+                    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+                    ctx->tune[std::make_tuple(pass, M, (int)dt)] = C;
+                }
+                td_plan* p = nullptr;
+                if (td_plan_create(ctx, &h, dt, &p) != TD_OK) continue;
+                const void* sg[2] = {bufs[0], bufs[1]};
+                const void* dx[2] = {bufs[2], bufs[3]};
+                const void* dy[2] = {bufs[4], bufs[5]};
+                void* fx[2] = {bufs[6], bufs[7]};
+                void* fy[2] = {bufs[8], bufs[9]};
+                td_request q{p, sg, dx, dy, fx, fy};
+                td_status s = TD_OK;
+                for (int w = 0; w < 3 && s == TD_OK; ++w) s = td_solve(&q, ctx->stream);
+                (void)hipEventRecord(e0, ctx->stream);
+                const int reps = 10;
+                for (int w = 0; w < reps && s == TD_OK; ++w) s = td_solve(&q, ctx->stream);
+                (void)hipEventRecord(e1, ctx->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                td_plan_destroy(p);
+                if (s != TD_OK) continue;
+                const double us = 1000.0 * ms / reps;
+                if (us < best) {
+                    best = us;
+                    bestC = C;
+                }
+            }
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            if (bestC < 0) {
+                ctx->tune.erase(std::make_tuple(pass, M, (int)dt));
+                continue;
+            }
+            ctx->tune[std::make_tuple(pass, M, (int)dt)] = bestC;
+            if (db.is_open())
+                db << "{\"arch\":\"" << arch << "\",\"dtype\":" << (int)dt << ",\"pass\":" << pass
+                   << ",\"M\":" << M << ",\"C\":" << bestC << ",\"us\":" << best << "}\n";
+        }
+        for (int k = 0; k < 10; ++k)
+            if (bufs[k]) ctx->release(bufs[k], (size_t)n * n * es);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return result;
+}
+
+// ===========================================================================
+// public: diagnostics
+// ===========================================================================
+
+extern "C" td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m,
+                                     int32_t kx, int32_t ky, double* out_host)
+{
+    if (!ctx || !out_host) return fail(TD_EINVAL, "NULL argument");
+    if (M < 16 || M > 4096 || (M & (M - 1))) return fail(TD_EINVAL, "M must be a power of two in 16..4096");
+    if (kind < 1 || kind > 3) return fail(TD_EINVAL, "kind must be 1, 2 or 3");
+    if (kind == 1) m = 1;
+    if (m < 1 || kx < 0 || ky < 0 || kx >= m || ky >= m) return fail(TD_EINVAL, "bad m or phase");
+    if (kind != 1 && (m % 2)) return fail(TD_EUNSUPPORTED, "m must be even");
+    DeviceGuard dg(ctx->device);
+    const size_t bytes = 6 * (size_t)M * M * sizeof(double);
+    void* d = nullptr;
+    TD_TRY(ctx->alloc(bytes, &d));
+    TableJob j;
+    memset(&j, 0, sizeof(j));
+    j.M = M;
+    j.kind = kind;
+    j.m = m;
+    j.kx = kx;
+    j.ky = ky;
+    j.out = (double*)d;
+    hipError_t e = launch_table(j, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(out_host, d, bytes, hipMemcpyDeviceToHost);
+    ctx->release(d, bytes);
+    if (e != hipSuccess) return fail(TD_EDEVICE, hipGetErrorString(e));
+    return TD_OK;
+}
+
+extern "C" const char* td_status_string(td_status s)
+{
+    switch (s) {
+        case TD_OK: return "TD_OK";
+        case TD_EINVAL: return "TD_EINVAL";
+        case TD_EALIGN: return "TD_EALIGN";
+        case TD_ENEST: return "TD_ENEST";
+        case TD_ENOMEM: return "TD_ENOMEM";
+        case TD_EDEVICE: return "TD_EDEVICE";
+        case TD_EBUSY: return "TD_EBUSY";
+        case TD_EUNSUPPORTED: return "TD_EUNSUPPORTED";
+    }
+    return "TD_UNKNOWN";
+}
+
+extern "C" const char* td_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* td_version(void) { return "thindisk-mi355x 0.1 (gfx950)"; }

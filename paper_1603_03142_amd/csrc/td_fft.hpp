@@ -1,0 +1,166 @@
+// Batched LDS-resident Stockham FFTs for gfx950.
+//
+// A workgroup transforms C independent sequences of length M (a power of two,
+// 16 <= M <= 4096) that sit contiguously in LDS (sequence f at buf + f*M).
+// The workgroup has exactly C*(M/8) threads; in every pass each thread holds
+// eight complex values in registers: one radix-8 butterfly, two radix-4
+// butterflies or four radix-2 butterflies.  Every pass reads all operands,
+// synchronises, and writes them back permuted (Stockham autosort), so a
+// single LDS buffer per sequence suffices and the result is in natural order.
+//
+// Forward: X[k] = sum_n x[n] exp(-2 pi i k n / M); inverse uses +i and is
+// unnormalised.  Twiddles come from a table tw[k] = exp(-2 pi i k / M),
+// k < M, computed on the host in long double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace td {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> rot_i(cpx<T> a)
+{
+    return INV ? cpx<T>{-a.im, a.re} : cpx<T>{a.im, -a.re};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cpx<T>* v)
+{
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cpx<T>* v)
+{
+    cpx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
+    cpx<T> s13 = v[1] + v[3], d13 = rot_i<T, INV>(v[1] - v[3]);
+    v[0] = s02 + s13;
+    v[2] = s02 - s13;
+    v[1] = d02 + d13;
+    v[3] = d02 - d13;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cpx<T>* v)
+{
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<T, INV>(e);
+    dft4<T, INV>(o);
+    const T h = (T)0.70710678118654752440084436210484903928;
+    // o[k] *= w8^k,  w8 = exp(-+ i pi/4)
+    o[1] = INV ? cpx<T>{h * (o[1].re - o[1].im), h * (o[1].re + o[1].im)}
+               : cpx<T>{h * (o[1].re + o[1].im), h * (o[1].im - o[1].re)};
+    o[2] = rot_i<T, INV>(o[2]);
+    o[3] = INV ? cpx<T>{-h * (o[3].re + o[3].im), h * (o[3].re - o[3].im)}
+               : cpx<T>{h * (o[3].im - o[3].re), -h * (o[3].re + o[3].im)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = e[k] + o[k];
+        v[k + 4] = e[k] - o[k];
+    }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cpx<T>* v)
+{
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 4) dft4<T, INV>(v);
+    else dft8<T, INV>(v);
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// One Stockham pass of radix R at span NS on sequence x (length M), for the
+// calling thread's `lane` in [0, M/8).
+template <typename T, int M, int R, int NS, bool INV>
+__device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
+{
+    constexpr int B = 8 / R;          // butterflies per thread
+    constexpr int STRIDE = M / R;     // distance between butterfly inputs
+    constexpr int TWS = M / (NS * R); // twiddle table stride
+    cpx<T> v[B][R];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        const int j = lane + q * (M / 8);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = x[j + r * STRIDE];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        const int j = lane + q * (M / 8);
+        const int k = (NS == 1) ? 0 : (j % NS);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cpx<T> w = tw[r * k * TWS];
+                v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+            }
+        }
+        dftR<T, R, INV>(v[q]);
+        const int base = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[base + r * NS] = v[q][r];
+    }
+    __syncthreads();
+}
+
+template <typename T, int M, int NS, bool INV>
+__device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
+{
+    if constexpr (NS < M) {
+        stockham_pass<T, M, 8, NS, INV>(x, tw, lane);
+        radix8_passes<T, M, NS * 8, INV>(x, tw, lane);
+    }
+}
+
+// Transform sequence `f = threadIdx.x / (M/8)` of the C sequences at buf.
+// Must be called by every thread of the workgroup (it synchronises).
+template <typename T, int M, bool INV>
+__device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ tw)
+{
+    static_assert(M >= 16 && (M & (M - 1)) == 0, "M must be a power of two >= 16");
+    const int f = threadIdx.x / (M / 8);
+    const int lane = threadIdx.x % (M / 8);
+    cpx<T>* x = buf + (size_t)f * M;
+    constexpr int REM = ilog2(M) % 3;
+    if constexpr (REM == 1) {
+        stockham_pass<T, M, 2, 1, INV>(x, tw, lane);
+        radix8_passes<T, M, 2, INV>(x, tw, lane);
+    } else if constexpr (REM == 2) {
+        stockham_pass<T, M, 4, 1, INV>(x, tw, lane);
+        radix8_passes<T, M, 4, INV>(x, tw, lane);
+    } else {
+        radix8_passes<T, M, 1, INV>(x, tw, lane);
+    }
+}
+
+}  // namespace td

@@ -1,0 +1,131 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+host-only logic (hierarchy validation and snapping) checked without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "thindisk.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(td_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    assert "td_solve" in names and "td_plan_create" in names and "td_server_submit" in names
+    assert len(names) >= 20
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1603_03142_amd import _binding
+    L = _binding.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+    assert sorted(_binding.EXPORTS) == declared()
+    assert b"gfx950" in L.td_version()
+
+
+def _check(levels, ratio=2, h0=2 / 16):
+    from paper_1603_03142_amd import _binding as B
+    arr = (B.td_level * len(levels))(*[B.td_level(*lv) for lv in levels])
+    h = B.td_hierarchy(-1.0, -1.0, h0, ratio, len(levels), ctypes.cast(arr, ctypes.POINTER(B.td_level)))
+    return B.lib().td_hierarchy_check(ctypes.byref(h))
+
+
+def test_hierarchy_validation_codes():
+    from paper_1603_03142_amd import _binding as B
+    assert _check([(16, 0, 0)]) == B.TD_OK
+    assert _check([(16, 0, 0), (16, 8, 8)]) == B.TD_OK
+    assert _check([(16, 0, 0), (16, 8, 8), (8, 20, 22)]) == B.TD_OK
+    assert _check([(16, 0, 0), (16, 7, 8)]) == B.TD_EALIGN          # odd offset
+    assert _check([(16, 0, 0), (15, 8, 8)]) == B.TD_EALIGN          # odd width
+    assert _check([(16, 0, 0), (16, 18, 8)]) == B.TD_ENEST          # sticks out
+    assert _check([(16, 0, 0), (34, 0, 0)]) == B.TD_ENEST           # wider than parent
+    assert _check([(16, 2, 0)]) == B.TD_EINVAL                      # level-0 offset
+    assert _check([(16, 0, 0)], ratio=3) == B.TD_EUNSUPPORTED
+    assert _check([(0, 0, 0)]) == B.TD_EINVAL
+    assert _check([(2048, 0, 0)]) == B.TD_OK
+    assert _check([(2049, 0, 0)]) == B.TD_EINVAL                    # beyond TD_MAX_N
+    assert _check([(16, 0, 0), (16, 56, 8)], ratio=4) == B.TD_ENEST
+    assert _check([(16, 0, 0), (16, 16, 24)], ratio=4) == B.TD_OK
+    assert _check([(8, 0, 0)] * 9) == B.TD_EINVAL                   # too many levels
+    msg = B.lib().td_last_error().decode()
+    assert "nlevels" in msg
+
+
+def test_snap_matches_python_generator():
+    """td_hierarchy_snap and synth.snap_offsets implement the same rounding."""
+    import synth
+    from paper_1603_03142_amd import _binding as B
+    h0 = 2.0 / 512
+    want = synth.snap_offsets(-1.0, -1.0, h0, 2, [512] * 4, [(0.3, 0.0)] * 3)
+    lv = (B.td_level * 4)(*[B.td_level(512, 0, 0) for _ in range(4)])
+    h = B.td_hierarchy(-1.0, -1.0, h0, 2, 4, ctypes.cast(lv, ctypes.POINTER(B.td_level)))
+    cx = (ctypes.c_double * 3)(0.3, 0.3, 0.3)
+    cy = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    assert B.lib().td_hierarchy_snap(ctypes.byref(h), lv, cx, cy) == B.TD_OK
+    got = [(lv[i].n, lv[i].ox, lv[i].oy) for i in range(4)]
+    assert got == want == [(512, 0, 0), (512, 410, 256), (512, 1076, 768), (512, 2406, 1792)]
+    assert B.lib().td_hierarchy_check(ctypes.byref(h)) == B.TD_OK
+
+
+def test_status_strings():
+    from paper_1603_03142_amd import _binding as B
+    for k, name in B._STATUS.items():
+        assert B.lib().td_status_string(k).decode() == name
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    from paper_1603_03142_amd import _binding as B
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(ImportError):
+        B.lib()
+
+
+def _random_hierarchy(rng):
+    import synth
+    ratio = int(rng.choice([2, 4]))
+    nlev = int(rng.integers(1, 5 if ratio == 2 else 4))
+    n0 = int(rng.integers(1, 70))
+    lv = [(n0, 0, 0)]
+    for _ in range(1, nlev):
+        pn, pox, poy = lv[-1]
+        if pn < 1:
+            break
+        w = int(rng.integers(1, pn + 1))          # parent cells covered
+        n = w * ratio
+        if n > 2048:
+            break
+        kx = int(rng.integers(0, pn - w + 1))
+        ky = int(rng.integers(0, pn - w + 1))
+        lv.append((n, ratio * (pox + kx), ratio * (poy + ky)))
+    return synth.nested_hierarchy(-1.0, -1.0, 2.0 / n0, ratio, lv)
+
+
+def test_plan_check_random_hierarchies():
+    """Host-side proof of every job's bounds and row coverage on random
+    nested hierarchies (ragged sizes, ratios 2 and 4, 1-4 levels)."""
+    import numpy as np
+    import paper_1603_03142_amd as td
+    rng = np.random.default_rng(12)
+    for _ in range(150):
+        h = _random_hierarchy(rng)
+        for dt in ("f32", "f64"):
+            assert td.check_plan(h, dt) > 0
+
+
+def test_plan_check_workloads():
+    import paper_1603_03142_amd as td
+    import synth
+    for f in (synth.config1, synth.config2, synth.config3):
+        h, _ = f()
+        assert td.check_plan(h, "f32") > 0
+    for h, _ in synth.config4(count=16):
+        assert td.check_plan(h, "f32") > 0

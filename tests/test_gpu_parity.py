@@ -1,0 +1,131 @@
+"""GPU path vs the oracle, element by element, through the C ABI.
+
+Tolerances (rel-L2 over active cells, Fx and Fy together): FP64 path 1e-12,
+FP32 path 1e-5.  Covered cells must be exactly 0.  Inputs are seeded
+synthetic fields from ``synth``; expected values come only from ``oracle``.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import (covered_are_zero, gpu_solve, rand_fields, rel_l2, rel_l2_full,
+                         sampled)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1603_03142_amd as td
+    c = td.Context(0)
+    yield c
+    c.close()
+
+
+# ---------------------------------------------------------------------------
+# kernel tables (FP64 on the GPU) vs the oracle's cell integrals
+# ---------------------------------------------------------------------------
+
+TABLE_CASES = [(16, 1, 1, 0, 0), (32, 1, 1, 0, 0), (16, 2, 2, 0, 0), (16, 2, 2, 1, 1),
+               (32, 2, 4, 1, 3), (16, 3, 2, 0, 1), (32, 3, 4, 3, 2), (16, 3, 2, 1, 1)]
+
+
+@pytest.mark.parametrize("M,kind,m,kx,ky", TABLE_CASES)
+def test_kernel_table_vs_oracle(ctx, M, kind, m, kx, ky):
+    got = ctx.kernel_table(M, kind, m, kx, ky)
+    want = np.zeros_like(got)
+    for ny in range(M):
+        for nx in range(M):
+            if nx == M // 2 or ny == M // 2:
+                continue
+            sx = nx if nx < M // 2 else nx - M
+            sy = ny if ny < M // 2 else ny - M
+            if kind == 1:
+                ua, va, w = -sx - 0.5, -sy - 0.5, 1.0
+            elif kind == 2:
+                ua, va, w = -m * sx + kx - m / 2, -m * sy + ky - m / 2, 1.0
+            else:
+                ua, va, w = -m * sx - kx - 0.5, -m * sy - ky - 0.5, float(m)
+            c = oracle.cell_integrals(ua, ua + w, va, va + w)
+            if kind == 3:
+                c[[1, 2, 4, 5]] /= m
+            want[:, ny, nx] = c
+    assert np.all(np.isfinite(got))
+    scale = np.abs(want).max()
+    # a few ulp of the largest entry; the oracle itself is long double
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-14 * scale)
+
+
+# ---------------------------------------------------------------------------
+# whole solves, full field
+# ---------------------------------------------------------------------------
+
+def H(levels, ratio=2, n0=None, x0=-1.0, y0=-1.0):
+    n0 = n0 or levels[0][0]
+    return synth.nested_hierarchy(x0, y0, 2.0 / n0, ratio, levels)
+
+
+HIERS = {
+    "1x1": H([(1, 0, 0)]),
+    "1x5": H([(5, 0, 0)]),
+    "1x37": H([(37, 0, 0)]),
+    "1x64": H([(64, 0, 0)]),
+    "2lev_20_12": H([(20, 0, 0), (12, 10, 16)]),
+    "2lev_centred_32": H([(32, 0, 0), (32, 16, 16)]),
+    "2lev_tiny_child": H([(9, 0, 0), (2, 4, 14)]),
+    "3lev_ragged": H([(24, 0, 0), (18, 8, 20), (10, 30, 48)]),
+    "3lev_corner": H([(16, 0, 0), (16, 16, 0), (8, 56, 0)]),
+    "ratio4_2lev": H([(16, 0, 0), (16, 16, 24)], ratio=4),
+    "ratio4_3lev": H([(12, 0, 0), (16, 12, 8), (8, 80, 44)], ratio=4),
+    "4lev": H([(16, 0, 0), (16, 8, 8), (16, 24, 20), (8, 60, 52)]),
+    # m = 16 pair whose target spans more columns than 2M of the coarse lattice
+    "ratio4_deep": H([(6, 0, 0), (20, 4, 4), (44, 44, 44)], ratio=4),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name", sorted(HIERS))
+def test_full_field_parity(ctx, name, dtype):
+    hier = HIERS[name]
+    sig, dx, dy = rand_fields(hier, seed=hash(name) % 1000)
+    ox, oy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, dtype)
+    err = rel_l2_full(hier, gx, gy, ox, oy)
+    print(f"{name} {dtype} rel-L2 {err:.3e}")
+    assert err <= TOL[dtype]
+    assert covered_are_zero(hier, gx, gy)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_no_slopes(ctx, dtype):
+    hier = HIERS["3lev_ragged"]
+    sig, _, _ = rand_fields(hier, seed=11, slopes=False)
+    ox, oy = oracle.forces(hier, sig)
+    gx, gy = gpu_solve(ctx, hier, sig, None, None, dtype)
+    assert rel_l2_full(hier, gx, gy, ox, oy) <= TOL[dtype]
+
+
+def test_config1_maclaurin(ctx):
+    """64x64 level, Maclaurin disk R = 0.8, FP64: whole field vs the oracle."""
+    hier, fn = synth.config1()
+    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    ox, oy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, "f64")
+    err = rel_l2_full(hier, gx, gy, ox, oy)
+    print(f"config1 f64 rel-L2 {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_determinism(ctx):
+    hier = HIERS["3lev_ragged"]
+    sig, dx, dy = rand_fields(hier, seed=5)
+    plan = ctx.plan(hier, "f32")
+    a = gpu_solve(ctx, hier, sig, dx, dy, "f32", plan)
+    b = gpu_solve(ctx, hier, sig, dx, dy, "f32", plan)
+    for k in range(len(hier.patches)):
+        assert np.array_equal(a[0][k], b[0][k]) and np.array_equal(a[1][k], b[1][k])
