@@ -210,6 +210,23 @@ td_status td_server_destroy(td_server* s);
 td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m, int32_t kx,
                           int32_t ky, double* out_host);
 
+/* The five passes of a solve, in launch order. */
+#define TD_NPASS 5   /* row_fwd, col_gather, col_scatter, row_inv, row_inv_accumulate */
+
+/* Per-pass timing.  While enabled, every solve enqueued outside graph
+ * capture records a HIP event pair around each pass on the solve's stream.
+ * td_timing_read waits for the recorded events, writes the summed
+ * milliseconds and the number of timed pass launches per pass (arrays of
+ * TD_NPASS, either may be NULL) since the previous read, and clears them. */
+td_status td_timing_enable(td_context* ctx, int enable);
+td_status td_timing_read(td_context* ctx, double* ms, int64_t* launches);
+
+/* Algorithmic HBM bytes one solve of the plan moves in each pass (array of
+ * TD_NPASS): every source value and workspace spectrum read once per use
+ * its pass makes of it, every kernel-spectrum column read once per use,
+ * every output written once. */
+td_status td_plan_traffic(const td_plan* plan, double* bytes);
+
 const char* td_status_string(td_status s);
 const char* td_last_error(void);
 /* Library version string. */

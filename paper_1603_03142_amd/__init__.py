@@ -91,6 +91,18 @@ class Context:
         B.check(lib().td_autotune(self.handle, _DT[dtype], max_M,
                                   db_path.encode() if db_path else None), "td_autotune")
 
+    PASSES = ("row_fwd", "col_gather", "col_scatter", "row_inv", "row_inv_acc")
+
+    def timing(self, enable: bool = True):
+        B.check(lib().td_timing_enable(self.handle, 1 if enable else 0), "td_timing_enable")
+
+    def timing_read(self):
+        """{pass: (milliseconds, launches)} since the previous read."""
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_int64 * 5)()
+        B.check(lib().td_timing_read(self.handle, ms, n), "td_timing_read")
+        return {p: (ms[i], n[i]) for i, p in enumerate(self.PASSES)}
+
     def kernel_table(self, M: int, kind: int, m: int = 1, kx: int = 0, ky: int = 0):
         import numpy as np
         out = np.zeros((6, M, M))
@@ -142,6 +154,12 @@ class Plan:
         B.check(lib().td_plan_footprint(self.handle, ctypes.byref(a), ctypes.byref(b)),
                 "td_plan_footprint")
         return a.value, b.value
+
+    def traffic(self):
+        """{pass: algorithmic HBM bytes per solve}."""
+        b = (ctypes.c_double * 5)()
+        B.check(lib().td_plan_traffic(self.handle, b), "td_plan_traffic")
+        return {p: b[i] for i, p in enumerate(Context.PASSES)}
 
     def close(self):
         if getattr(self, "handle", None):

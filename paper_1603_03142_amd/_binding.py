@@ -23,7 +23,7 @@ EXPORTS = [
     "td_context_create", "td_context_destroy", "td_context_usage", "td_hierarchy_check",
     "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_footprint", "td_plan_destroy", "td_solve",
     "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_destroy",
-    "td_autotune", "td_server_create", "td_server_submit", "td_server_poll", "td_server_drain",
+    "td_autotune", "td_timing_enable", "td_timing_read", "td_plan_traffic", "td_server_create", "td_server_submit", "td_server_poll", "td_server_drain",
     "td_server_cancel", "td_server_stats", "td_server_destroy", "td_kernel_table",
     "td_status_string", "td_last_error", "td_version",
 ]
@@ -105,6 +105,10 @@ def lib():
             "td_kernel_table": ([VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)], S),
+            "td_timing_enable": ([VP, ctypes.c_int], S),
+            "td_timing_read": ([VP, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int64)], S),
+            "td_plan_traffic": ([VP, ctypes.POINTER(ctypes.c_double)], S),
             "td_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "td_last_error": ([], ctypes.c_char_p),
             "td_version": ([], ctypes.c_char_p),

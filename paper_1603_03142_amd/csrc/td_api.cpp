@@ -106,6 +106,24 @@ struct td_context {
     std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> C
     hipStream_t stream = nullptr;                                 // plan-time work
     std::vector<void*> allocs;
+    // per-pass timing (diagnostics)
+    bool timing = false;
+    struct Timed { int pass; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> ev_pool;
+    double t_ms[5] = {0, 0, 0, 0, 0};
+    int64_t t_n[5] = {0, 0, 0, 0, 0};
+    hipEvent_t get_event()
+    {
+        hipEvent_t e = nullptr;
+        if (!ev_pool.empty()) {
+            e = ev_pool.back();
+            ev_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
 
     td_status alloc(size_t bytes, void** out)
     {
@@ -1000,9 +1018,28 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
         return nullptr;
     };
     const bool f64 = dt == TD_F64;
+    bool timed = false;
+    if (ctx->timing) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        timed = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+    }
     // C per (pass, M) must agree across members; members built with other
     // tunings are launched in separate groups.
     for (int pass = 0; pass < 5; ++pass) {
+        hipEvent_t ev_a = nullptr, ev_b = nullptr;
+        bool any = false;
+        for (auto& m : mem)
+            for (auto& g : m.plan->groups) {
+                const size_t nj = pass == 0 ? g.rowfwd.size() : pass == 1 ? g.gather.size()
+                                : pass == 2 ? g.scatter.size() : g.rinv[pass == 3 ? 0 : 1].size();
+                any |= nj > 0;
+            }
+        if (timed && any) {
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            ev_a = ctx->get_event();
+            ev_b = ctx->get_event();
+            if (ev_a) (void)hipEventRecord(ev_a, st);
+        }
         for (int M : Ms) {
             const void* tw = nullptr;
             TD_TRY(twiddles(ctx, M, dt, &tw));
@@ -1060,6 +1097,11 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                     return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
             }
         }
+        if (ev_a && ev_b) {
+            (void)hipEventRecord(ev_b, st);
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            ctx->timed.push_back({pass, ev_a, ev_b});
+        }
     }
     return TD_OK;
 }
@@ -1115,6 +1157,11 @@ extern "C" td_status td_context_destroy(td_context* c)
     if (!c) return fail(TD_EINVAL, "NULL context");
     DeviceGuard g(c->device);
     (void)hipDeviceSynchronize();
+    for (auto& t : c->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     for (auto& kv : c->spectra) c->release(kv.second.ptr, kv.second.bytes);
     for (auto& kv : c->tw32) (void)hipFree(kv.second);
     for (auto& kv : c->tw64) (void)hipFree(kv.second);
@@ -1819,6 +1866,89 @@ extern "C" td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, i
     if (e == hipSuccess) e = hipMemcpy(out_host, d, bytes, hipMemcpyDeviceToHost);
     ctx->release(d, bytes);
     if (e != hipSuccess) return fail(TD_EDEVICE, hipGetErrorString(e));
+    return TD_OK;
+}
+
+extern "C" td_status td_timing_enable(td_context* ctx, int enable)
+{
+    if (!ctx) return fail(TD_EINVAL, "NULL context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->timing = enable != 0;
+    return TD_OK;
+}
+
+extern "C" td_status td_timing_read(td_context* ctx, double* ms, int64_t* launches)
+{
+    if (!ctx) return fail(TD_EINVAL, "NULL context");
+    DeviceGuard dg(ctx->device);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    for (auto& t : ctx->timed) {
+        TD_HIP(hipEventSynchronize(t.b));
+        float e = 0;
+        TD_HIP(hipEventElapsedTime(&e, t.a, t.b));
+        ctx->t_ms[t.pass] += e;
+        ctx->t_n[t.pass] += 1;
+        ctx->ev_pool.push_back(t.a);
+        ctx->ev_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    for (int p = 0; p < 5; ++p) {
+        if (ms) ms[p] = ctx->t_ms[p];
+        if (launches) launches[p] = ctx->t_n[p];
+        ctx->t_ms[p] = 0;
+        ctx->t_n[p] = 0;
+    }
+    return TD_OK;
+}
+
+extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
+{
+    if (!P || !bytes) return fail(TD_EINVAL, "NULL argument");
+    const double cs = (double)elem_size(P->dt), rs = cs / 2;
+    for (int p = 0; p < 5; ++p) bytes[p] = 0;
+    for (auto& g : P->groups) {
+        const int M = g.M, H = M / 2 + 1;
+        for (auto& j : g.rowfwd) {
+            // source values in range (rows x columns), spectrum rows written
+            int cols = 0;
+            for (int lc = 0; lc < M; ++lc) {
+                const int c = j.m * lc + j.col_off;
+                cols += (c >= 0 && c < j.n_src) ? 1 : 0;
+            }
+            int rows = 0;
+            for (int r = j.row0; r < j.row0 + j.nrow; ++r) {
+                const int sr = j.m * (j.lr_first + r) + j.row_off;
+                rows += (sr >= 0 && sr < j.n_src) ? 1 : 0;
+            }
+            bytes[0] += (double)rows * cols * rs + (double)H * j.nrow * cs;
+        }
+        for (auto& j : g.gather) {
+            for (int t = 0; t < j.nterm; ++t) {
+                const ColTerm& tm = g.terms[j.term0 + t];
+                int nf = 0;
+                for (int f = 0; f < 3; ++f) nf += tm.in[f] >= 0;
+                bytes[1] += (double)j.ncol * (nf * tm.in_ld + 2.0 * nf * M) * cs;
+            }
+            bytes[1] += 2.0 * j.ncol * j.out_ld * cs;
+        }
+        for (auto& j : g.scatter) {
+            int nf = 0;
+            for (int f = 0; f < 3; ++f) nf += j.in[f] >= 0;
+            bytes[2] += (double)j.ncol * nf * j.in_ld * cs;
+            for (int o = 0; o < j.nout; ++o) {
+                const ColScatterOut& so = g.souts[j.out0 + o];
+                bytes[2] += (double)j.ncol * (2.0 * nf * M + 2.0 * so.out_ld) * cs;
+            }
+        }
+        for (int a = 0; a < 2; ++a)
+            for (auto& j : g.rinv[a]) {
+                for (int k = 0; k < j.nc; ++k) {
+                    const RowInvContrib& c = g.contribs[j.c0 + k];
+                    bytes[3 + a] += (double)c.m * j.ny * H * 2 * cs;
+                }
+                bytes[3 + a] += (double)j.ny * j.nx * 2 * rs * (a ? 2 : 1);
+            }
+    }
     return TD_OK;
 }
 
