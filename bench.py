@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--mode", default="eager", choices=["eager", "graph"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tune", metavar="DB", default=None,
+                    help="autotune launch shapes first (JSON-lines database path)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -71,6 +73,11 @@ def main():
     S, DX, DY = dev(sig), dev(dx), dev(dy)
 
     ctx = td.Context(0)
+    tune_s = None
+    if args.tune:
+        t0 = time.perf_counter()
+        ctx.autotune(args.dtype, max(p.n for p in hier.patches) * 2, args.tune)
+        tune_s = round(time.perf_counter() - t0, 2)
     t0 = time.perf_counter()
     plan = ctx.plan(hier, args.dtype)
     plan_s = time.perf_counter() - t0
@@ -161,7 +168,7 @@ def main():
         "config": {"workload": args.workload, "levels": len(hier.patches),
                    "cells_per_level": [p.n for p in hier.patches], "ratio": hier.ratio,
                    "cells_per_solve": cells, "mode": args.mode,
-                   "plan_build_s": round(plan_s, 3)},
+                   "plan_build_s": round(plan_s, 3), "autotune_s": tune_s},
         "roofline": roof,
         "cpu_baseline": cpu,
         "rel_l2_vs_oracle_sampled": acc,

@@ -211,7 +211,7 @@ td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m, i
                           int32_t ky, double* out_host);
 
 /* The five passes of a solve, in launch order. */
-#define TD_NPASS 5   /* row_fwd, col_gather, col_scatter, row_inv, row_inv_accumulate */
+#define TD_NPASS 5   /* row_fwd, col_fwd, col_mac, row_inv, row_inv_accumulate */
 
 /* Per-pass timing.  While enabled, every solve enqueued outside graph
  * capture records a HIP event pair around each pass on the solve's stream.

@@ -91,7 +91,7 @@ class Context:
         B.check(lib().td_autotune(self.handle, _DT[dtype], max_M,
                                   db_path.encode() if db_path else None), "td_autotune")
 
-    PASSES = ("row_fwd", "col_gather", "col_scatter", "row_inv", "row_inv_acc")
+    PASSES = ("row_fwd", "col_fwd", "col_mac", "row_inv", "row_inv_acc")
 
     def timing(self, enable: bool = True):
         B.check(lib().td_timing_enable(self.handle, 1 if enable else 0), "td_timing_enable")

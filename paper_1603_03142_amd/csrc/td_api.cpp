@@ -67,14 +67,35 @@ int fft_len(int n)
 
 size_t elem_size(td_dtype dt) { return dt == TD_F64 ? 16 : 8; }  // complex element
 
-enum Pass { P_ROWFWD = 0, P_GATHER = 1, P_SCATTER = 2, P_ROWINV = 3 };
+enum Pass { P_ROWFWD = 0, P_COLFWD = 1, P_COLMAC = 2, P_ROWINV = 3 };
 
-// Default sequences per workgroup: about 256 threads, LDS <= 64 KiB.
-int default_C(int pass, int M, td_dtype dt)
+// Kernel feeding output component c (0: Fx, 1: Fy) from field f (sigma,
+// dsdx, dsdy): I0, Ixx, Ixy for Fx and J0, Jyx, Jyy for Fy.
+const int kKernOfHost[2][3] = {{0, 1, 2}, {3, 5, 4}};
+
+// Launch shape of a pass: C sequences (row passes) or C columns x G slots
+// (column passes), packed as C | G << 16.
+int shape_C(int v) { return v & 0xffff; }
+int shape_G(int v) { return std::max(1, v >> 16); }
+int pack_shape(int C, int G) { return C | (G << 16); }
+
+// Default launch shapes: 512 threads for the column passes and the row
+// inverse (col_mac: up to 8 outputs of a column at once; row_inv: up to 4
+// contributions of a row at once), 256 for the row FFTs; LDS <= 64 KiB.
+int default_shape(int pass, int M, td_dtype dt)
 {
-    int C = std::max(1, 2048 / M);
-    while (C > 1 && lds_bytes(pass, M, C, elem_size(dt)) > 64 * 1024) C /= 2;
-    return C;
+    const size_t es = elem_size(dt);
+    if (pass == P_ROWFWD) {
+        int S = std::max(1, 2048 / M);
+        while (S > 1 && lds_bytes(pass, M, S, es) > 64 * 1024) S /= 2;
+        return pack_shape(S, 1);
+    }
+    int S = std::max(1, 4096 / M);
+    int G = pass == P_COLFWD ? 1 : std::min(pass == P_ROWINV ? 4 : 8, S);
+    int C = std::max(1, S / G);
+    while (C > 1 && lds_bytes(pass, M, C, es, G) > 64 * 1024) C /= 2;
+    while (G > 1 && lds_bytes(pass, M, C, es, G) > 64 * 1024) G /= 2;
+    return pack_shape(C, G);
 }
 
 double now_s()
@@ -103,7 +124,7 @@ struct td_context {
     std::recursive_mutex mu;
     std::map<int, void*> tw32, tw64;
     std::map<std::tuple<int, int, int, int>, SpecEntry> spectra;  // (M, kind, m, dtype)
-    std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> C
+    std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> shape
     hipStream_t stream = nullptr;                                 // plan-time work
     std::vector<void*> allocs;
     // per-pass timing (diagnostics)
@@ -143,11 +164,11 @@ struct td_context {
             used -= bytes;
         }
     }
-    int C(int pass, int M, td_dtype dt)
+    int shape(int pass, int M, td_dtype dt)
     {
         std::lock_guard<std::recursive_mutex> lk(mu);
         auto it = tune.find(std::make_tuple(pass, M, (int)dt));
-        return it != tune.end() ? it->second : default_C(pass, M, dt);
+        return it != tune.end() ? it->second : default_shape(pass, M, dt);
     }
 };
 
@@ -235,9 +256,10 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
     const int nphase = hp * hp;
     const size_t NCOL = M / 2 + 1;
     const size_t per_phase = 6 * NCOL * (size_t)M;
+    const bool quarter = kind == 1;  // one real per frequency, ky <= M/2
     SpecEntry e;
     e.nphase = nphase;
-    e.bytes = per_phase * nphase * elem_size(dt);
+    e.bytes = quarter ? 6 * NCOL * NCOL * elem_size(dt) / 2 : per_phase * nphase * elem_size(dt);
     TD_TRY(ctx->alloc(e.bytes, &e.ptr));
     // FP64 scratch: the six real tables, their row transforms, pointer table.
     void *table = nullptr, *rows = nullptr, *dptr = nullptr;
@@ -250,7 +272,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
     if (st == TD_OK) st = twiddles(ctx, M, TD_F64, &tw64);
     RowFwdJob* djobs = nullptr;
     std::vector<RowFwdJob> jobs;
-    const int C = std::max(1, std::min(ctx->C(P_ROWFWD, M, TD_F64), 1024 / (M / 8)));
+    const int C = std::max(1, std::min(shape_C(default_shape(P_ROWFWD, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
     if (st == TD_OK) {
         void* hp_ptr[6];
         for (int X = 0; X < 6; ++X) hp_ptr[X] = (char*)table + X * (size_t)M * M * sizeof(double);
@@ -291,11 +313,11 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
             he = launch_row_fwd<double>(M, C, (int)jobs.size(),
                                         single_seg<RowFwdJob>(djobs, (int)jobs.size(), 0, nullptr, (char*)rows),
                                         (const void* const*)dptr, tw64, ctx->stream);
-        const int Cs = std::max(1, std::min(default_C(P_ROWINV, M, TD_F64), 1024 / (M / 8)));
+        const int Cs = std::max(1, std::min(shape_C(default_shape(P_ROWINV, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
         void* dst = (char*)e.ptr + (size_t)p * per_phase * elem_size(dt);
         if (he == hipSuccess)
-            he = dt == TD_F64 ? launch_spec_col<double>(M, Cs, rows, dst, tw64, ctx->stream)
-                              : launch_spec_col<float>(M, Cs, rows, dst, tw64, ctx->stream);
+            he = dt == TD_F64 ? launch_spec_col<double>(M, Cs, rows, dst, tw64, quarter, ctx->stream)
+                              : launch_spec_col<float>(M, Cs, rows, dst, tw64, quarter, ctx->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
         if (he != hipSuccess) st = fail(TD_EDEVICE, std::string("kernel-table build: ") + hipGetErrorString(he));
     }
@@ -390,20 +412,22 @@ namespace {
 // Jobs of one transform length M, on the host and on the device.
 struct Group {
     int M = 0;
-    int C[4] = {1, 1, 1, 1};
+    int C[4] = {1, 1, 1, 1};   // sequences / columns per workgroup
+    int G[4] = {1, 1, 1, 1};   // slots per column (column passes)
     std::vector<RowFwdJob> rowfwd;
-    std::vector<ColGatherJob> gather;
-    std::vector<ColTerm> terms;
-    std::vector<ColScatterJob> scatter;
-    std::vector<ColScatterOut> souts;
+    std::vector<ColFwdJob> colfwd;
+    std::vector<ColMacJob> colmac;
+    std::vector<MacOut> macouts;
+    std::vector<MacTerm> macterms;
     std::vector<RowInvJob> rinv[2];  // [0] write, [1] accumulate
     std::vector<RowInvContrib> contribs;
     // device copies
     RowFwdJob* d_rowfwd = nullptr;
-    ColGatherJob* d_gather = nullptr;
-    ColTerm* d_terms = nullptr;
-    ColScatterJob* d_scatter = nullptr;
-    ColScatterOut* d_souts = nullptr;
+    ColFwdJob* d_colfwd = nullptr;
+    ColMacJob* d_colmac = nullptr;
+    MacOut* d_macouts = nullptr;
+    MacTerm* d_macterms = nullptr;
+    void* d_mactabs = nullptr;  // {d_macouts, d_macterms}
     RowInvJob* d_rinv[2] = {nullptr, nullptr};
     RowInvContrib* d_contribs = nullptr;
 };
@@ -468,6 +492,17 @@ Group& group_for(std::vector<Group>& groups, int M)
     return groups.back();
 }
 
+// Enumerate the m*m polyphase phases so that the four mirror images of
+// each stored phase (sx, sy) in [0, m/2)^2 come one after another.
+void mirror_order(int m, int i, int* kx, int* ky)
+{
+    const int h = m / 2;
+    const int base = i / 4, mir = i % 4;
+    const int sx = base % h, sy = base / h;
+    *kx = (mir & 1) ? m - 1 - sx : sx;
+    *ky = (mir & 2) ? m - 1 - sy : sy;
+}
+
 int ipow(int b, int e)
 {
     int r = 1;
@@ -491,6 +526,16 @@ td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out
 
 // Emit every job of a plan (workspace addresses as byte offsets) and the
 // workspace size in complex elements.
+//
+// Workspace per lattice t (level t's zero-padded M x M grid):
+//   own_in[t]      3 row-pass planes [M/2+1][n_t] of level t's fields
+//   own_sp[t]      3 spectra [M/2+1][M] of them (col_fwd)
+//   ph_in[s][t]    per finer level s: m^2 phases x 3 row-pass planes
+//                  [M/2+1][nr] of the polyphase sub-grids on lattice t
+//   ph_sp[s][t]    their spectra [M/2+1][M]
+//   own_out[t]     Fx, Fy column outputs [M/2+1][n_t]
+//   c3_out[t][s]   per finer level s: m^2 phases x (Fx, Fy) outputs
+//                  [M/2+1][ld] on lattice t for target level s
 td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
 {
     td_context* ctx = P->ctx;
@@ -504,25 +549,30 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     };
     auto ptr = [&](size_t o) -> int64_t { return (int64_t)(o * es); };
     // ---- workspace layout
-    std::vector<size_t> own_in(L), own_out(L);
-    std::vector<std::vector<size_t>> ph_in(L, std::vector<size_t>(L)), c3_out(L, std::vector<size_t>(L));
+    std::vector<size_t> own_in(L), own_sp(L), own_out(L);
+    std::vector<std::vector<size_t>> ph_in(L, std::vector<size_t>(L)), ph_sp(L, std::vector<size_t>(L)),
+        c3_out(L, std::vector<size_t>(L));
     std::vector<std::vector<int>> ph_nr(L, std::vector<int>(L)), c3_ld(L, std::vector<int>(L));
     for (int l = 0; l < L; ++l) {
         const LevelG& g = P->lv[l];
-        own_in[l] = take(3 * (size_t)(g.M / 2 + 1) * g.n);
-        own_out[l] = take(2 * (size_t)(g.M / 2 + 1) * g.n);
+        const size_t H = g.M / 2 + 1;
+        own_in[l] = take(3 * H * g.n);
+        own_sp[l] = take(3 * H * g.M);
+        own_out[l] = take(2 * H * g.n);
     }
     for (int t = 0; t < L; ++t)
         for (int s = t + 1; s < L; ++s) {
             const int m = ipow(r, s - t);
             const LevelG &G = P->lv[t], &S = P->lv[s];
+            const size_t H = G.M / 2 + 1;
             const int nr = (S.n + m - 1) / m + 1;
             ph_nr[s][t] = nr;
-            ph_in[s][t] = take((size_t)m * m * 3 * (G.M / 2 + 1) * nr);
-            // coarser source s' = t, finer target t' = s: Case-3 outputs on lattice t
+            ph_in[s][t] = take((size_t)m * m * 3 * H * nr);
+            ph_sp[s][t] = take((size_t)m * m * 3 * H * G.M);
+            // coarser source t, finer target s: Case-3 outputs on lattice t
             const int ld = floor_div(S.oy + S.n - 1, m) - floor_div(S.oy, m) + 1;
             c3_ld[t][s] = ld;
-            c3_out[t][s] = take((size_t)m * m * 2 * (G.M / 2 + 1) * ld);
+            c3_out[t][s] = take((size_t)m * m * 2 * H * ld);
         }
     *ws_elems = off;
     if (!emit) return TD_OK;
@@ -530,15 +580,34 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     P->groups.clear();
     for (int l = 0; l < L; ++l) {
         Group& g = group_for(P->groups, P->lv[l].M);
-        for (int pass = 0; pass < 4; ++pass) g.C[pass] = ctx->C(pass, g.M, P->dt);
+        for (int pass = 0; pass < 4; ++pass) {
+            const int v = ctx->shape(pass, g.M, P->dt);
+            g.C[pass] = shape_C(v);
+            g.G[pass] = shape_G(v);
+        }
     }
-    // ---- pass 1: row FFTs
+    // column FFT jobs of one input plane set
+    auto add_colfwd = [&](Group& g, size_t in, size_t out, int ld, int lr_first) {
+        const int H = g.M / 2 + 1, C = g.C[P_COLFWD];
+        for (int kx0 = 0; kx0 < H; kx0 += C) {
+            ColFwdJob j;
+            memset(&j, 0, sizeof(j));
+            j.in = ptr(in);
+            j.out = ptr(out);
+            j.ld = ld;
+            j.lr_first = lr_first;
+            j.kx0 = kx0;
+            j.ncol = std::min(C, H - kx0);
+            g.colfwd.push_back(j);
+        }
+    };
+    // ---- passes 1 and 2: row FFTs and column FFTs of every input
     for (int l = 0; l < L; ++l) {
         const LevelG& G = P->lv[l];
         Group& g = group_for(P->groups, G.M);
         const int R = 2 * g.C[P_ROWFWD];
-        const size_t plane = (size_t)(G.M / 2 + 1) * G.n;
-        for (int f = 0; f < 3; ++f)
+        const size_t H = G.M / 2 + 1, plane = H * G.n;
+        for (int f = 0; f < 3; ++f) {
             for (int r0 = 0; r0 < G.n; r0 += R) {
                 RowFwdJob j;
                 memset(&j, 0, sizeof(j));
@@ -553,6 +622,8 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 j.out = ptr(own_in[l] + f * plane);
                 g.rowfwd.push_back(j);
             }
+            add_colfwd(g, own_in[l] + f * plane, own_sp[l] + f * H * G.M, G.n, 0);
+        }
         // polyphase sub-grids of every finer level s, placed on this lattice
         for (int s = l + 1; s < L; ++s) {
             const LevelG& S = P->lv[s];
@@ -561,12 +632,12 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 for (int kx = 0; kx < m; ++kx) {
                     const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
                     const int lr_hi = floor_div(S.oy + S.n - 1 - ky, m) - G.oy;
-                    const int nrp = lr_hi - lr_lo + 1;
-                    if (nrp <= 0) continue;
+                    if (lr_hi < lr_lo) continue;
                     const int phase = ky * m + kx;
                     // every stored row is written (rows past the source are
                     // zeros), since the column pass reads all nr of them
-                    for (int f = 0; f < 3; ++f)
+                    for (int f = 0; f < 3; ++f) {
+                        const size_t in = ph_in[s][l] + ((size_t)phase * 3 + f) * H * nr;
                         for (int r0 = 0; r0 < nr; r0 += R) {
                             RowFwdJob j;
                             memset(&j, 0, sizeof(j));
@@ -582,115 +653,122 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                             j.cov_i0 = S.cov_i0; j.cov_i1 = S.cov_i1;
                             j.cov_j0 = S.cov_j0; j.cov_j1 = S.cov_j1;
                             j.scale = f == 0 ? 1.0 : S.h;
-                            j.out = ptr(ph_in[s][l] + ((size_t)phase * 3 + f) * (G.M / 2 + 1) * nr);
+                            j.out = ptr(in);
                             g.rowfwd.push_back(j);
                         }
+                        add_colfwd(g, in, ph_sp[s][l] + ((size_t)phase * 3 + f) * H * G.M, nr, lr_lo);
+                    }
                 }
         }
     }
-    // ---- pass 2: gather (own level + finer sources) on each lattice
+    // ---- pass 3: products and inverse column FFTs, per lattice
     for (int t = 0; t < L; ++t) {
         const LevelG& G = P->lv[t];
         Group& g = group_for(P->groups, G.M);
-        const SpecEntry* k1 = nullptr;
-        TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
-        const int term0 = (int)g.terms.size();
-        const size_t plane = (size_t)(G.M / 2 + 1) * G.n;
+        const size_t H = G.M / 2 + 1;
+        const int out0 = (int)g.macouts.size();
+        // (a) the level's own force: same-level kernels on its own fields,
+        // Case-2 phase kernels on every finer level's sub-grids
         {
-            ColTerm tm;
-            memset(&tm, 0, sizeof(tm));
-            for (int f = 0; f < 3; ++f) tm.in[f] = ptr(own_in[t] + f * plane);
-            tm.kern = k1->ptr;
-            tm.in_ld = G.n;
-            tm.in_lr_first = 0;
-            tm.flip = 0;
-            g.terms.push_back(tm);
-        }
-        for (int s = t + 1; s < L; ++s) {
-            const LevelG& S = P->lv[s];
-            const int m = ipow(r, s - t), nr = ph_nr[s][t];
-            const SpecEntry* k2 = nullptr;
-            TD_TRY(plan_spectra(P, G.M, 2, m, &k2));
-            const size_t per_phase = 6 * (size_t)(G.M / 2 + 1) * G.M;
-            for (int ky = 0; ky < m; ++ky)
-                for (int kx = 0; kx < m; ++kx) {
+            const SpecEntry* k1 = nullptr;
+            TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
+            std::vector<MacTerm> tm;  // terms of Fx; Fy uses the paired kernels
+            std::vector<MacTerm> tmy;
+            for (int f = 0; f < 3; ++f) {
+                tm.push_back({ptr(own_sp[t] + f * H * G.M), k1->ptr, kKernOfHost[0][f], 4});
+                tmy.push_back({ptr(own_sp[t] + f * H * G.M), k1->ptr, kKernOfHost[1][f], 4});
+            }
+            for (int s = t + 1; s < L; ++s) {
+                const LevelG& S = P->lv[s];
+                const int m = ipow(r, s - t);
+                const SpecEntry* k2 = nullptr;
+                TD_TRY(plan_spectra(P, G.M, 2, m, &k2));
+                const size_t per_phase = 6 * H * G.M;
+                // mirror images of one stored phase are adjacent
+                for (int pi = 0; pi < m * m; ++pi) {
+                    int kx, ky;
+                    mirror_order(m, pi, &kx, &ky);
                     const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
                     const int lr_hi = floor_div(S.oy + S.n - 1 - ky, m) - G.oy;
                     if (lr_hi < lr_lo) continue;
                     const int phase = ky * m + kx;
-                    ColTerm tm;
-                    memset(&tm, 0, sizeof(tm));
-                    const size_t fplane = (size_t)(G.M / 2 + 1) * nr;
-                    for (int f = 0; f < 3; ++f) tm.in[f] = ptr(ph_in[s][t] + ((size_t)phase * 3 + f) * fplane);
                     const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
-                    tm.kern = (char*)k2->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
-                    tm.flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
-                    tm.in_ld = nr;
-                    tm.in_lr_first = lr_lo;
-                    g.terms.push_back(tm);
+                    const void* kern = (char*)k2->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
+                    const int flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
+                    for (int f = 0; f < 3; ++f) {
+                        const int64_t in = ptr(ph_sp[s][t] + ((size_t)phase * 3 + f) * H * G.M);
+                        tm.push_back({in, kern, kKernOfHost[0][f], flip});
+                        tmy.push_back({in, kern, kKernOfHost[1][f], flip});
+                    }
                 }
+            }
+            for (int comp = 0; comp < 2; ++comp) {
+                MacOut o;
+                memset(&o, 0, sizeof(o));
+                o.out = ptr(own_out[t] + comp * H * G.n);
+                o.term0 = (int)g.macterms.size();
+                const auto& v = comp == 0 ? tm : tmy;
+                o.nterm = (int)v.size();
+                g.macterms.insert(g.macterms.end(), v.begin(), v.end());
+                o.out_ld = G.n;
+                o.out_lr_first = 0;
+                g.macouts.push_back(o);
+            }
         }
-        const int nterm = (int)g.terms.size() - term0;
-        const int C = g.C[P_GATHER];
-        for (int kx0 = 0; kx0 < G.M / 2 + 1; kx0 += C) {
-            ColGatherJob j;
+        // (b) Case-3 phases of this (coarser) level onto every finer target
+        for (int s = t + 1; s < L; ++s) {
+            const LevelG& T = P->lv[s];
+            const int m = ipow(r, s - t), ld = c3_ld[t][s];
+            const SpecEntry* k3 = nullptr;
+            TD_TRY(plan_spectra(P, G.M, 3, m, &k3));
+            const size_t per_phase = 6 * H * G.M;
+            for (int pi = 0; pi < m * m; ++pi) {
+                int kx, ky;
+                mirror_order(m, pi, &kx, &ky);
+                const int phase = ky * m + kx;
+                const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
+                const void* kern = (char*)k3->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
+                const int flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
+                for (int comp = 0; comp < 2; ++comp) {
+                    MacOut o;
+                    memset(&o, 0, sizeof(o));
+                    o.out = ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld);
+                    o.term0 = (int)g.macterms.size();
+                    o.nterm = 3;
+                    for (int f = 0; f < 3; ++f)
+                        g.macterms.push_back({ptr(own_sp[t] + f * H * G.M), kern, kKernOfHost[comp][f], flip});
+                    o.out_ld = ld;
+                    o.out_lr_first = floor_div(T.oy, m) - G.oy;
+                    g.macouts.push_back(o);
+                }
+            }
+        }
+        const int nout = (int)g.macouts.size() - out0;
+        const int C = g.C[P_COLMAC], Gs = g.G[P_COLMAC];
+        // the level's own Fx, Fy (outputs out0, out0 + 1) carry many terms:
+        // they get all slots of a column, split evenly; the Case-3 outputs
+        // (three terms each) take one slot apiece
+        const int own_split = std::max(1, Gs / 2);
+        for (int kx0 = 0; kx0 < (int)H; kx0 += C) {
+            ColMacJob j;
             memset(&j, 0, sizeof(j));
             j.kx0 = kx0;
-            j.ncol = std::min(C, G.M / 2 + 1 - kx0);
-            j.term0 = term0;
-            j.nterm = nterm;
-            j.out_x = ptr(own_out[t]);
-            j.out_y = ptr(own_out[t] + (size_t)(G.M / 2 + 1) * G.n);
-            j.out_ld = G.n;
-            j.out_lr_first = 0;
-            g.gather.push_back(j);
-        }
-    }
-    // ---- pass 3: scatter (coarser source s onto every finer target)
-    for (int s = 0; s < L; ++s) {
-        if (s == L - 1) break;
-        const LevelG& S = P->lv[s];
-        Group& g = group_for(P->groups, S.M);
-        const int out0 = (int)g.souts.size();
-        const size_t cplane = (size_t)(S.M / 2 + 1);
-        for (int t = s + 1; t < L; ++t) {
-            const LevelG& T = P->lv[t];
-            const int m = ipow(r, t - s), ld = c3_ld[s][t];
-            const SpecEntry* k3 = nullptr;
-            TD_TRY(plan_spectra(P, S.M, 3, m, &k3));
-            const size_t per_phase = 6 * (size_t)(S.M / 2 + 1) * S.M;
-            for (int ky = 0; ky < m; ++ky)
-                for (int kx = 0; kx < m; ++kx) {
-                    const int phase = ky * m + kx;
-                    ColScatterOut o;
-                    memset(&o, 0, sizeof(o));
-                    const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
-                    o.kern = (char*)k3->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
-                    o.flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
-                    o.out_x = ptr(c3_out[s][t] + (size_t)phase * 2 * cplane * ld);
-                    o.out_y = ptr(c3_out[s][t] + ((size_t)phase * 2 + 1) * cplane * ld);
-                    o.out_ld = ld;
-                    o.out_lr_first = floor_div(T.oy, m) - S.oy;
-                    g.souts.push_back(o);
-                }
-        }
-        const int nout = (int)g.souts.size() - out0;
-        const int C = g.C[P_SCATTER];
-        const int chunk = 4;
-        const size_t plane = (size_t)(S.M / 2 + 1) * S.n;
-        for (int kx0 = 0; kx0 < S.M / 2 + 1; kx0 += C)
-            for (int o0 = 0; o0 < nout; o0 += chunk) {
-                ColScatterJob j;
-                memset(&j, 0, sizeof(j));
-                for (int f = 0; f < 3; ++f) j.in[f] = ptr(own_in[s] + f * plane);
-                j.in_ld = S.n;
-                j.in_lr_first = 0;
-                j.kx0 = kx0;
-                j.ncol = std::min(C, S.M / 2 + 1 - kx0);
-                j.out0 = out0 + o0;
-                j.nout = std::min(chunk, nout - o0);
-                g.scatter.push_back(j);
+            j.ncol = std::min(C, (int)H - kx0);
+            j.out0 = out0;
+            j.nout = std::min(2, Gs);
+            j.split = Gs >= 2 ? own_split : 1;
+            g.colmac.push_back(j);
+            if (Gs < 2) {
+                j.out0 = out0 + 1;
+                g.colmac.push_back(j);
             }
+            for (int o0 = out0 + 2; o0 < out0 + nout; o0 += Gs) {
+                j.out0 = o0;
+                j.nout = std::min(Gs, out0 + nout - o0);
+                j.split = 1;
+                g.colmac.push_back(j);
+            }
+        }
     }
     // ---- pass 4: row inverse, grouped by lattice length
     for (int t = 0; t < L; ++t) {
@@ -764,7 +842,8 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
 }
 
 // Host-side bounds proof of every job against the workspace, the kernel
-// spectra, the fields and the launch shape, before anything is uploaded.
+// spectra, the fields and the launch shape, and of the data flow: every
+// workspace row a pass reads was written by the pass before.
 td_status validate_jobs(td_plan* P)
 {
     const size_t es = elem_size(P->dt);
@@ -777,60 +856,68 @@ td_status validate_jobs(td_plan* P)
     for (auto& g : P->groups) {
         const int M = g.M, H = M / 2 + 1;
         for (int pass = 0; pass < 4; ++pass) {
-            const int C = g.C[pass];
-            if (C < 1 || C * (M / 8) > 1024 || lds_bytes(pass, M, C, es) > 160 * 1024)
+            const int C = g.C[pass], Gs = g.G[pass];
+            if (C < 1 || Gs < 1 || Gs > 16 || C * Gs * (M / 8) > TD_MAX_THREADS ||
+                lds_bytes(pass, M, C, es, Gs) > TD_MAX_DYN_LDS)
                 return bad("launch shape");
         }
+        // pass 1: rows written per row-pass plane
+        std::map<int64_t, std::vector<char>> rows_written;
         for (auto& j : g.rowfwd) {
             if (j.src_slot < 0 || j.src_slot >= (int)nsrc.size() || nsrc[j.src_slot] != j.n_src)
                 return bad("row source");
             if (j.row0 < 0 || j.nrow < 1 || j.nrow > 2 * g.C[P_ROWFWD] || j.row0 + j.nrow > j.ld)
                 return bad("row range");
             if (!in_ws(j.out, (int64_t)H * j.ld)) return bad("row output");
-        }
-        for (auto& j : g.gather) {
-            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_GATHER] || j.kx0 + j.ncol > H)
-                return bad("gather columns");
-            if (j.out_lr_first < 0 || j.out_lr_first + j.out_ld > M) return bad("gather rows");
-            if (!in_ws(j.out_x, (int64_t)H * j.out_ld) || !in_ws(j.out_y, (int64_t)H * j.out_ld))
-                return bad("gather output");
-            if (j.term0 < 0 || j.term0 + j.nterm > (int)g.terms.size()) return bad("gather terms");
-        }
-        // rows written by the row pass, per output buffer
-        std::map<int64_t, std::vector<char>> written;
-        for (auto& j : g.rowfwd) {
-            auto& w = written[j.out];
+            auto& w = rows_written[j.out];
             if ((int)w.size() < j.ld) w.resize(j.ld, 0);
             for (int r = j.row0; r < j.row0 + j.nrow; ++r) w[r] = 1;
         }
-        auto covered = [&](int64_t off, int ld) {
-            auto it = written.find(off);
-            if (it == written.end() || (int)it->second.size() < ld) return false;
-            for (int r = 0; r < ld; ++r)
-                if (!it->second[r]) return false;
-            return true;
-        };
-        for (auto& t : g.terms) {
-            for (int f = 0; f < 3; ++f)
-                if (t.in[f] >= 0 && !covered(t.in[f], t.in_ld)) return bad("term reads unwritten rows");
-            for (int f = 0; f < 3; ++f)
-                if (t.in[f] >= 0 && !in_ws(t.in[f], (int64_t)H * t.in_ld)) return bad("term input");
-            if (t.in_lr_first < 0 || t.in_lr_first + t.in_ld > M || !t.kern) return bad("term rows");
+        // pass 2: columns written per spectrum plane
+        std::map<int64_t, std::vector<char>> cols_written;
+        for (auto& j : g.colfwd) {
+            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_COLFWD] || j.kx0 + j.ncol > H)
+                return bad("col_fwd columns");
+            if (j.lr_first < 0 || j.lr_first + j.ld > M) return bad("col_fwd rows");
+            if (!in_ws(j.in, (int64_t)H * j.ld) || !in_ws(j.out, (int64_t)H * M)) return bad("col_fwd planes");
+            auto it = rows_written.find(j.in);
+            if (it == rows_written.end() || (int)it->second.size() < j.ld) return bad("col_fwd reads unwritten rows");
+            for (int r = 0; r < j.ld; ++r)
+                if (!it->second[r]) return bad("col_fwd reads unwritten rows");
+            auto& w = cols_written[j.out];
+            if ((int)w.size() < H) w.resize(H, 0);
+            for (int c = j.kx0; c < j.kx0 + j.ncol; ++c) w[c] = 1;
         }
-        for (auto& j : g.scatter) {
-            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_SCATTER] || j.kx0 + j.ncol > H)
-                return bad("scatter columns");
-            for (int f = 0; f < 3; ++f)
-                if (j.in[f] >= 0 && (!in_ws(j.in[f], (int64_t)H * j.in_ld) || !covered(j.in[f], j.in_ld)))
-                    return bad("scatter input");
-            if (j.in_lr_first < 0 || j.in_lr_first + j.in_ld > M) return bad("scatter rows");
-            if (j.out0 < 0 || j.out0 + j.nout > (int)g.souts.size()) return bad("scatter outputs");
+        // pass 3: outputs, terms, and columns written per output plane
+        std::map<int64_t, std::pair<int, std::vector<char>>> out_written;  // ld, columns
+        for (auto& o : g.macouts) {
+            if (o.out_lr_first < 0 || o.out_lr_first + o.out_ld > M) return bad("col_mac rows");
+            if (!in_ws(o.out, (int64_t)H * o.out_ld)) return bad("col_mac output");
+            if (o.term0 < 0 || o.nterm < 1 || o.term0 + o.nterm > (int)g.macterms.size())
+                return bad("col_mac terms");
+            for (int t = o.term0; t < o.term0 + o.nterm; ++t) {
+                const MacTerm& tm = g.macterms[t];
+                if (tm.X < 0 || tm.X > 5 || !tm.kern || tm.flip < 0 || tm.flip > 4) return bad("col_mac kernel");
+                auto it = cols_written.find(tm.in);
+                if (it == cols_written.end() || (int)it->second.size() < H) return bad("col_mac reads unwritten spectra");
+                for (int c = 0; c < H; ++c)
+                    if (!it->second[c]) return bad("col_mac reads unwritten spectra");
+            }
         }
-        for (auto& o : g.souts) {
-            if (o.out_lr_first < 0 || o.out_lr_first + o.out_ld > M || !o.kern) return bad("scatter out rows");
-            if (!in_ws(o.out_x, (int64_t)H * o.out_ld) || !in_ws(o.out_y, (int64_t)H * o.out_ld))
-                return bad("scatter out");
+        for (auto& j : g.colmac) {
+            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_COLMAC] || j.kx0 + j.ncol > H)
+                return bad("col_mac columns");
+            if (j.out0 < 0 || j.nout < 1 || j.split < 1 || j.nout * j.split > g.G[P_COLMAC] ||
+                j.out0 + j.nout > (int)g.macouts.size())
+                return bad("col_mac outputs");
+            for (int k = j.out0; k < j.out0 + j.nout; ++k) {
+                auto& w = out_written[g.macouts[k].out];
+                w.first = g.macouts[k].out_ld;
+                if ((int)w.second.size() < H) w.second.resize(H, 0);
+                for (int c = j.kx0; c < j.kx0 + j.ncol; ++c) w.second[c] = 1;
+            }
         }
+        // pass 4
         for (int a = 0; a < 2; ++a)
             for (auto& j : g.rinv[a]) {
                 if (j.y0 < 0 || j.ny < 1 || j.ny > g.C[P_ROWINV] || j.y0 + j.ny > j.n_t) return bad("rinv rows");
@@ -853,6 +940,15 @@ td_status validate_jobs(td_plan* P)
                     const int64_t last = c.base + ((int64_t)(c.m * c.m - 1) * c.phase_stride +
                                                    c.comp_stride + (int64_t)H * c.ld) * (int64_t)es;
                     if (c.base < 0 || last > ws) return bad("rinv contribution");
+                    // every phase / component plane it reads was written in full
+                    for (int p = 0; p < c.m * c.m; ++p)
+                        for (int comp = 0; comp < 2; ++comp) {
+                            const int64_t plane = c.base + ((int64_t)p * c.phase_stride + comp * c.comp_stride) * (int64_t)es;
+                            auto it = out_written.find(plane);
+                            if (it == out_written.end() || it->second.first != c.ld) return bad("rinv reads unwritten outputs");
+                            for (int cc = 0; cc < H; ++cc)
+                                if (!it->second.second[cc]) return bad("rinv reads unwritten outputs");
+                        }
                 }
             }
     }
@@ -898,10 +994,16 @@ td_status plan_upload(td_plan* P)
     td_context* ctx = P->ctx;
     for (auto& g : P->groups) {
         TD_TRY(upload(ctx, P, g.rowfwd, &g.d_rowfwd));
-        TD_TRY(upload(ctx, P, g.gather, &g.d_gather));
-        TD_TRY(upload(ctx, P, g.terms, &g.d_terms));
-        TD_TRY(upload(ctx, P, g.scatter, &g.d_scatter));
-        TD_TRY(upload(ctx, P, g.souts, &g.d_souts));
+        TD_TRY(upload(ctx, P, g.colfwd, &g.d_colfwd));
+        TD_TRY(upload(ctx, P, g.colmac, &g.d_colmac));
+        TD_TRY(upload(ctx, P, g.macouts, &g.d_macouts));
+        TD_TRY(upload(ctx, P, g.macterms, &g.d_macterms));
+        {
+            const std::vector<const void*> tabs{g.d_macouts, g.d_macterms};
+            const void** d = nullptr;
+            TD_TRY(upload(ctx, P, tabs, &d));
+            g.d_mactabs = (void*)d;
+        }
         TD_TRY(upload(ctx, P, g.rinv[0], &g.d_rinv[0]));
         TD_TRY(upload(ctx, P, g.rinv[1], &g.d_rinv[1]));
         TD_TRY(upload(ctx, P, g.contribs, &g.d_contribs));
@@ -1030,8 +1132,8 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
         bool any = false;
         for (auto& m : mem)
             for (auto& g : m.plan->groups) {
-                const size_t nj = pass == 0 ? g.rowfwd.size() : pass == 1 ? g.gather.size()
-                                : pass == 2 ? g.scatter.size() : g.rinv[pass == 3 ? 0 : 1].size();
+                const size_t nj = pass == 0 ? g.rowfwd.size() : pass == 1 ? g.colfwd.size()
+                                : pass == 2 ? g.colmac.size() : g.rinv[pass == 3 ? 0 : 1].size();
                 any |= nj > 0;
             }
         if (timed && any) {
@@ -1049,10 +1151,10 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                 Group* g = find_group(m.plan, M);
                 if (!g) continue;
                 const int pi = pass == 4 ? P_ROWINV : pass;
-                byC[g->C[pi]].push_back({g, &m});
+                byC[pack_shape(g->C[pi], g->G[pi])].push_back({g, &m});
             }
             for (auto& kv : byC) {
-                const int C = kv.first;
+                const int C = shape_C(kv.first), Gs = shape_G(kv.first);
                 hipError_t e = hipSuccess;
                 if (pass == P_ROWFWD) {
                     std::vector<SegTable<RowFwdJob>> t;
@@ -1063,24 +1165,24 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
                         e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st)
                                 : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st);
-                } else if (pass == P_GATHER) {
-                    std::vector<SegTable<ColGatherJob>> t;
+                } else if (pass == P_COLFWD) {
+                    std::vector<SegTable<ColFwdJob>> t;
                     std::vector<int> n;
                     for (auto& gs : kv.second)
-                        push_seg(t, n, gs.first->d_gather, (int)gs.first->gather.size(),
-                                 gs.second->slot_base, (const void*)gs.first->d_terms, gs.second->ws);
+                        push_seg(t, n, gs.first->d_colfwd, (int)gs.first->colfwd.size(),
+                                 gs.second->slot_base, nullptr, gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_col_gather<double>(M, C, n[i], t[i], tw, st)
-                                : launch_col_gather<float>(M, C, n[i], t[i], tw, st);
-                } else if (pass == P_SCATTER) {
-                    std::vector<SegTable<ColScatterJob>> t;
+                        e = f64 ? launch_col_fwd<double>(M, C, n[i], t[i], tw, st)
+                                : launch_col_fwd<float>(M, C, n[i], t[i], tw, st);
+                } else if (pass == P_COLMAC) {
+                    std::vector<SegTable<ColMacJob>> t;
                     std::vector<int> n;
                     for (auto& gs : kv.second)
-                        push_seg(t, n, gs.first->d_scatter, (int)gs.first->scatter.size(),
-                                 gs.second->slot_base, (const void*)gs.first->d_souts, gs.second->ws);
+                        push_seg(t, n, gs.first->d_colmac, (int)gs.first->colmac.size(),
+                                 gs.second->slot_base, (const void*)gs.first->d_mactabs, gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_col_scatter<double>(M, C, n[i], t[i], tw, st)
-                                : launch_col_scatter<float>(M, C, n[i], t[i], tw, st);
+                        e = f64 ? launch_col_mac<double>(M, C, Gs, n[i], t[i], tw, st)
+                                : launch_col_mac<float>(M, C, Gs, n[i], t[i], tw, st);
                 } else {
                     const int a = pass == P_ROWINV ? 0 : 1;
                     std::vector<SegTable<RowInvJob>> t;
@@ -1090,8 +1192,8 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                                  gs.second->slot_base, (const void*)gs.first->d_contribs,
                                  gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_row_inv<double>(M, C, n[i], t[i], d_ptrs, tw, st)
-                                : launch_row_inv<float>(M, C, n[i], t[i], d_ptrs, tw, st);
+                        e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, tw, st)
+                                : launch_row_inv<float>(M, C, Gs, n[i], t[i], d_ptrs, tw, st);
                 }
                 if (e != hipSuccess)
                     return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
@@ -1213,10 +1315,8 @@ extern "C" td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_d
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         std::vector<const void*> seen;
         for (auto& g : P->groups) {
-            for (auto& t : g.terms)
+            for (auto& t : g.macterms)
                 if (std::find(seen.begin(), seen.end(), t.kern) == seen.end()) seen.push_back(t.kern);
-            for (auto& o : g.souts)
-                if (std::find(seen.begin(), seen.end(), o.kern) == seen.end()) seen.push_back(o.kern);
         }
         size_t b = 0;
         for (auto& kv : ctx->spectra) {
@@ -1744,10 +1844,11 @@ void db_load(td_context* ctx, const char* path, const std::string& arch)
             *v = atof(line.c_str() + p + strlen(key) + 3);
             return true;
         };
-        double dt, pass, M, C;
+        double dt, pass, M, C, G = 1;
         if (line.find("\"arch\":\"" + arch + "\"") == std::string::npos) continue;
+        num("G", &G);
         if (num("dtype", &dt) && num("pass", &pass) && num("M", &M) && num("C", &C))
-            ctx->tune[std::make_tuple((int)pass, (int)M, (int)dt)] = (int)C;
+            ctx->tune[std::make_tuple((int)pass, (int)M, (int)dt)] = pack_shape((int)C, (int)G);
     }
 }
 
@@ -1787,8 +1888,13 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
         for (int pass = 0; pass < 4 && result == TD_OK; ++pass) {
             int bestC = -1;
             double best = 1e30;
-            for (int C = 1; C * (M / 8) <= 1024; C *= 2) {
-                if (lds_bytes(pass, M, C, elem_size(dt)) > 160 * 1024) break;
+            std::vector<int> cands;
+            for (int C = 1; C * (M / 8) <= TD_MAX_THREADS; C *= 2)
+                for (int Gs = 1; Gs <= ((pass == P_ROWFWD || pass == P_COLFWD) ? 1 : 16); Gs *= 2)
+                    if (C * Gs * (M / 8) <= TD_MAX_THREADS &&
+                        lds_bytes(pass, M, C, elem_size(dt), Gs) <= TD_MAX_DYN_LDS)
+                        cands.push_back(pack_shape(C, Gs));
+            for (int C : cands) {
                 {
                     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
                     ctx->tune[std::make_tuple(pass, M, (int)dt)] = C;
@@ -1826,7 +1932,8 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
             ctx->tune[std::make_tuple(pass, M, (int)dt)] = bestC;
             if (db.is_open())
                 db << "{\"arch\":\"" << arch << "\",\"dtype\":" << (int)dt << ",\"pass\":" << pass
-                   << ",\"M\":" << M << ",\"C\":" << bestC << ",\"us\":" << best << "}\n";
+                   << ",\"M\":" << M << ",\"C\":" << shape_C(bestC) << ",\"G\":" << shape_G(bestC)
+                   << ",\"us\":" << best << "}\n";
         }
         for (int k = 0; k < 10; ++k)
             if (bufs[k]) ctx->release(bufs[k], (size_t)n * n * es);
@@ -1922,22 +2029,28 @@ extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
             }
             bytes[0] += (double)rows * cols * rs + (double)H * j.nrow * cs;
         }
-        for (auto& j : g.gather) {
-            for (int t = 0; t < j.nterm; ++t) {
-                const ColTerm& tm = g.terms[j.term0 + t];
-                int nf = 0;
-                for (int f = 0; f < 3; ++f) nf += tm.in[f] >= 0;
-                bytes[1] += (double)j.ncol * (nf * tm.in_ld + 2.0 * nf * M) * cs;
-            }
-            bytes[1] += 2.0 * j.ncol * j.out_ld * cs;
-        }
-        for (auto& j : g.scatter) {
-            int nf = 0;
-            for (int f = 0; f < 3; ++f) nf += j.in[f] >= 0;
-            bytes[2] += (double)j.ncol * nf * j.in_ld * cs;
-            for (int o = 0; o < j.nout; ++o) {
-                const ColScatterOut& so = g.souts[j.out0 + o];
-                bytes[2] += (double)j.ncol * (2.0 * nf * M + 2.0 * so.out_ld) * cs;
+        for (auto& j : g.colfwd) bytes[1] += (double)j.ncol * (j.ld + M) * cs;
+        // col_mac: per column and output, every input spectrum column and the
+        // stored kernel column it multiplies (kernel columns shared by the
+        // outputs of one workgroup -- mirror images, Fx / Fy pairs -- once)
+        for (auto& j : g.colmac) {
+            std::vector<std::pair<const void*, int>> seen_k;
+            std::vector<int64_t> seen_in;
+            for (int k = j.out0; k < j.out0 + j.nout; ++k) {
+                const MacOut& o = g.macouts[k];
+                bytes[2] += (double)j.ncol * o.out_ld * cs;
+                for (int t = o.term0; t < o.term0 + o.nterm; ++t) {
+                    const MacTerm& tm = g.macterms[t];
+                    if (std::find(seen_in.begin(), seen_in.end(), tm.in) == seen_in.end()) {
+                        seen_in.push_back(tm.in);
+                        bytes[2] += (double)j.ncol * M * cs;
+                    }
+                    const auto key = std::make_pair(tm.kern, tm.X);
+                    if (std::find(seen_k.begin(), seen_k.end(), key) == seen_k.end()) {
+                        seen_k.push_back(key);
+                        bytes[2] += (double)j.ncol * ((tm.flip & 4) ? H * rs : M * cs);
+                    }
+                }
             }
         }
         for (int a = 0; a < 2; ++a)

@@ -11,11 +11,19 @@
 // Forward: X[k] = sum_n x[n] exp(-2 pi i k n / M); inverse uses +i and is
 // unnormalised.  Twiddles come from a table tw[k] = exp(-2 pi i k / M),
 // k < M, computed on the host in long double.
+//
+// LDS layout: element i of a sequence is stored at lds_pos(i) = i + i/8 and
+// sequences are lds_stride(M) = M + M/8 elements apart.  The extra element
+// per eight spreads the strided Stockham stores (spans 1 and 8) over the
+// LDS banks: at most two lanes of a wavefront share a bank.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace td {
+
+__host__ __device__ constexpr int lds_stride(int M) { return M + M / 8; }
+__device__ __forceinline__ int lds_pos(int i) { return i + (i >> 3); }
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cpx {
@@ -111,7 +119,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
     for (int q = 0; q < B; ++q) {
         const int j = lane + q * (M / 8);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = x[j + r * STRIDE];
+        for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos(j + r * STRIDE)];
     }
     __syncthreads();
 #pragma unroll
@@ -128,7 +136,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
         dftR<T, R, INV>(v[q]);
         const int base = (j / NS) * NS * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[base + r * NS] = v[q][r];
+        for (int r = 0; r < R; ++r) x[lds_pos(base + r * NS)] = v[q][r];
     }
     __syncthreads();
 }
@@ -142,15 +150,16 @@ __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restric
     }
 }
 
-// Transform sequence `f = threadIdx.x / (M/8)` of the C sequences at buf.
-// Must be called by every thread of the workgroup (it synchronises).
+// Transform sequence `f = threadIdx.x / (M/8)` of the C sequences at buf
+// (padded layout).  Must be called by every thread of the workgroup (it
+// synchronises).
 template <typename T, int M, bool INV>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ tw)
 {
     static_assert(M >= 16 && (M & (M - 1)) == 0, "M must be a power of two >= 16");
     const int f = threadIdx.x / (M / 8);
     const int lane = threadIdx.x % (M / 8);
-    cpx<T>* x = buf + (size_t)f * M;
+    cpx<T>* x = buf + (size_t)f * lds_stride(M);
     constexpr int REM = ilog2(M) % 3;
     if constexpr (REM == 1) {
         stockham_pass<T, M, 2, 1, INV>(x, tw, lane);

@@ -1,25 +1,19 @@
 // Work descriptors shared by the host planner and the device passes.
 //
 // A solve is four passes over lists of jobs (one workgroup per job):
-//   1. row_fwd     zero-padded real-to-complex row FFTs of every source field
-//                  (own level and polyphase sub-grids of finer levels),
-//                  written transposed: spectrum column kx holds the rows.
-//   2. col_gather  per spectral column: column FFT of each input, multiply
-//                  by the kernel spectra, sum, inverse column FFT -- the
-//                  same-level and finer-source (Case 2') contributions to a
-//                  level's own force.
-//   3. col_scatter per spectral column: column FFT of a level's fields once,
-//                  then one product and inverse column FFT per polyphase
-//                  output of every finer target level (Case 3').
-//   4. row_inv     complex-to-real row FFTs of the force spectra, window
-//                  extraction, phase interleave, sum over source levels,
-//                  covered-cell masking.
-// Geometry is in "lattice" coordinates: the zero-padded M x M grid of one
-// level's patch.  Intermediate spectra live in a workspace whose base comes
-// with each launch segment: jobs hold byte offsets into it (so a plan can be
-// bound to any workspace).  Kernel spectra are resident and addressed by
-// absolute pointers; field pointers are looked up in a per-solve pointer
-// table by slot.
+//   1. row_fwd  zero-padded real-to-complex row FFTs of every source field
+//               (own level and polyphase sub-grids of finer levels), written
+//               transposed: spectrum column kx holds the rows.
+//   2. col_fwd  forward FFT of every spectrum column, zero-padded to the
+//               lattice length M: the full 2-D spectrum of every input.
+//   3. col_mac  per spectral column and output: the sum over inputs of input
+//               spectrum x kernel spectrum, then the inverse column FFT.
+//               Outputs are a level's own force (same-level and finer-source
+//               inputs, Case 2') and the polyphase outputs of a coarser
+//               source onto a finer target (Case 3').
+//   4. row_inv  complex-to-real row FFTs of the force spectra, window
+//               extraction, phase interleave, sum over source levels,
+//               covered-cell masking.
 #pragma once
 #include <stdint.h>
 
@@ -41,39 +35,39 @@ struct RowFwdJob {
     int64_t out;        // workspace byte offset: complex [M/2+1][ld]
 };
 
-struct ColTerm {
-    int64_t in[3];      // workspace offsets: complex [M/2+1][in_ld] per field (sigma, dsdx, dsdy)
-    const void* kern;   // stored kernel spectra of the phase: [6][M/2+1][M] complex
-    int32_t in_ld;
-    int32_t in_lr_first;
-    int32_t flip;       // bit 0: x-mirror of the stored phase, bit 1: y-mirror
-    int32_t pad;
+// Forward column FFT of the C columns [kx0, kx0 + ncol) of one input plane.
+struct ColFwdJob {
+    int64_t in;          // workspace offset: complex [M/2+1][ld] (row pass output)
+    int64_t out;         // workspace offset: complex [M/2+1][M] (2-D spectrum)
+    int32_t ld;          // stored rows of the input plane
+    int32_t lr_first;    // lattice row of stored row 0
+    int32_t kx0, ncol;
 };
 
-struct ColGatherJob {
-    int32_t kx0, ncol;   // spectral columns [kx0, kx0+ncol)
+// One product of an output: input spectrum x stored kernel spectrum X.
+struct MacTerm {
+    int64_t in;          // workspace offset: complex [M/2+1][M]
+    const void* kern;    // stored kernel spectra (see kern_at)
+    int32_t X;           // kernel index 0..5: I0, Ixx, Ixy, J0, Jyy, Jyx
+    int32_t flip;        // mirror / layout bits of the stored spectrum
+};
+
+// One output column family: sum of its terms, inverse column FFT, rows
+// [out_lr_first, out_lr_first + out_ld) written to [M/2+1][out_ld].
+struct MacOut {
+    int64_t out;         // workspace offset
     int32_t term0, nterm;
-    int64_t out_x;       // workspace offsets: complex [M/2+1][out_ld]
-    int64_t out_y;
-    int32_t out_ld;
-    int32_t out_lr_first;
+    int32_t out_ld, out_lr_first;
 };
 
-struct ColScatterOut {
-    const void* kern;
-    int64_t out_x;       // workspace offsets
-    int64_t out_y;
-    int32_t flip;
-    int32_t out_ld;
-    int32_t out_lr_first;
-    int32_t pad;
-};
-
-struct ColScatterJob {
-    int64_t in[3];       // workspace offsets
-    int32_t in_ld, in_lr_first;
+// Columns [kx0, kx0 + ncol) x outputs [out0, out0 + nout); each output's
+// terms are split over `split` slots (nout * split <= slots per column),
+// whose partial sums are reduced before the inverse FFT.
+struct ColMacJob {
     int32_t kx0, ncol;
     int32_t out0, nout;
+    int32_t split;
+    int32_t pad;
 };
 
 struct RowInvContrib {

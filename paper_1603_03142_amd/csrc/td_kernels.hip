@@ -117,6 +117,15 @@ __global__ void k_table(TableJob J)
     for (int X = 0; X < 6; ++X) J.out[X * plane + idx] = v[X];
 }
 
+
+// Copy the twiddle table (M entries) into LDS; every pass of a workgroup's
+// FFTs then reads it from there.
+template <typename T, int M>
+__device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src)
+{
+    for (int i = threadIdx.x; i < M; i += blockDim.x) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 // Pass 1: zero-padded real row FFTs, transposed write
 // ---------------------------------------------------------------------------
@@ -135,9 +144,9 @@ __device__ __forceinline__ T fetch_src(const T* __restrict__ src, const RowFwdJo
 // C = blockDim/(M/8) complex sequences; sequence p carries stored rows
 // row0 + 2p (real part) and row0 + 2p + 1 (imaginary part).
 template <typename T, int M>
-__global__ void __launch_bounds__(1024) k_row_fwd(SegTable<RowFwdJob> segs,
+__global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> segs,
                                                   const void* const* __restrict__ ptrs,
-                                                  const cpx<T>* __restrict__ tw)
+                                                  const cpx<T>* __restrict__ tw_g)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -146,6 +155,9 @@ __global__ void __launch_bounds__(1024) k_row_fwd(SegTable<RowFwdJob> segs,
     char* ws;
     const RowFwdJob J = segs.find(blockIdx.x, &slot_base, &aux, &ws);
     const int C = blockDim.x / (M / 8);
+    constexpr int SP = lds_stride(M);
+    cpx<T>* tw = buf + C * SP;
+    stage_twiddles<T, M>(tw, tw_g);
     const T* src = reinterpret_cast<const T*>(ptrs[slot_base + J.src_slot]);
     const int rend = J.row0 + J.nrow;
     for (int idx = threadIdx.x; idx < C * M; idx += blockDim.x) {
@@ -156,7 +168,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd(SegTable<RowFwdJob> segs,
             if (s0 < rend) a = fetch_src(src, J, J.lr_first + s0, lc);
             if (s0 + 1 < rend) b = fetch_src(src, J, J.lr_first + s0 + 1, lc);
         }
-        buf[idx] = cpx<T>{a, b};
+        buf[p * SP + lds_pos(lc)] = cpx<T>{a, b};
     }
     __syncthreads();
     fft_lds<T, M, false>(buf, tw);
@@ -166,8 +178,8 @@ __global__ void __launch_bounds__(1024) k_row_fwd(SegTable<RowFwdJob> segs,
         const int r = idx % R, kx = idx / R;
         if (r >= J.nrow) continue;
         const int p = r >> 1;
-        const cpx<T> z = buf[p * M + kx];
-        const cpx<T> zc = conj(buf[p * M + ((M - kx) & (M - 1))]);
+        const cpx<T> z = buf[p * SP + lds_pos(kx)];
+        const cpx<T> zc = conj(buf[p * SP + lds_pos((M - kx) & (M - 1))]);
         cpx<T> X;
         if ((r & 1) == 0) {
             X = cpx<T>{(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
@@ -191,10 +203,30 @@ __device__ __constant__ int kSignY[6] = {1, 1, -1, -1, 1, -1};
 // dsdx, dsdy).
 __device__ __constant__ int kKernOf[2][3] = {{0, 1, 2}, {3, 5, 4}};
 
+// Stored spectrum of kernel X at (kx, ky).
+//  flip bit 2: a same-level kernel, symmetric under both mirrors, stored as
+//    one real R per frequency for ky in [0, M/2]: the spectrum is R when
+//    s_x s_y = +1 and i R otherwise, and S(kx, ky) = s_y S(kx, M - ky);
+//  otherwise a polyphase phase stored complex for all ky; bits 0 / 1 select
+//    its x- / y-mirror image: S'(kx, ky) = s_x conj S(kx, -ky),
+//    s_y S(kx, -ky), or s_x s_y conj S(kx, ky).
 template <typename T, int M>
-__device__ __forceinline__ cpx<T> kern_at(const cpx<T>* __restrict__ K, int X, int kx, int ky,
+__device__ __forceinline__ cpx<T> kern_at(const void* __restrict__ Kv, int X, int kx, int ky,
                                           int flip)
 {
+    if (flip & 4) {
+        constexpr int H = M / 2 + 1;
+        const T* R = reinterpret_cast<const T*>(Kv);
+        int k = ky;
+        T sg = 1;
+        if (ky > M / 2) {
+            k = M - ky;
+            sg = (T)kSignY[X];
+        }
+        const T v = sg * R[((size_t)X * H + kx) * H + k];
+        return (kSignX[X] * kSignY[X] > 0) ? cpx<T>{v, 0} : cpx<T>{0, v};
+    }
+    const cpx<T>* K = reinterpret_cast<const cpx<T>*>(Kv);
     const int kyy = (flip == 1 || flip == 2) ? ((M - ky) & (M - 1)) : ky;
     cpx<T> s = K[((size_t)X * (M / 2 + 1) + kx) * M + kyy];
     if (flip & 1) s.im = -s.im;
@@ -206,127 +238,135 @@ __device__ __forceinline__ cpx<T> kern_at(const cpx<T>* __restrict__ K, int X, i
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: column FFT, kernel products summed over inputs, inverse column FFT
+// Pass 2: forward column FFTs of every input plane
 // ---------------------------------------------------------------------------
+// One slot per spectral column: the stored rows (zero elsewhere) are
+// transformed along the column and written as the column's M frequencies.
 
 template <typename T, int M>
-__global__ void __launch_bounds__(1024) k_col_gather(SegTable<ColGatherJob> segs,
-                                                     const cpx<T>* __restrict__ tw)
+__global__ void __launch_bounds__(TD_MAX_THREADS) k_col_fwd(SegTable<ColFwdJob> segs,
+                                                            const cpx<T>* __restrict__ tw_g)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int C = blockDim.x / (M / 8);
-    cpx<T>* ax = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* ay = ax + C * M;
-    cpx<T>* in = ay + C * M;
+    constexpr int TPS = M / 8;
+    constexpr int SP = lds_stride(M);
+    const int S = blockDim.x / TPS;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* tw = A + S * SP;
+    stage_twiddles<T, M>(tw, tw_g);
     int slot_unused;
     const void* aux;
     char* ws;
-    const ColGatherJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
-    const ColTerm* __restrict__ terms = reinterpret_cast<const ColTerm*>(aux);
-    for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
-        ax[i] = cpx<T>{0, 0};
-        ay[i] = cpx<T>{0, 0};
+    const ColFwdJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
+    const int slot = threadIdx.x / TPS, lane = threadIdx.x % TPS;
+    const bool col_ok = slot < J.ncol;
+    const int kx = J.kx0 + slot;
+    cpx<T>* a = A + slot * SP;
+    const cpx<T>* src = reinterpret_cast<const cpx<T>*>(ws + J.in) + (size_t)kx * J.ld;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int ky = lane + q * TPS, sr = ky - J.lr_first;
+        a[lds_pos(ky)] = (col_ok && sr >= 0 && sr < J.ld) ? src[sr] : cpx<T>{0, 0};
     }
-    for (int t = 0; t < J.nterm; ++t) {
-        const ColTerm Tm = terms[J.term0 + t];
-        const cpx<T>* K = reinterpret_cast<const cpx<T>*>(Tm.kern);
-        for (int f = 0; f < 3; ++f) {
-            if (Tm.in[f] < 0) continue;
-            const cpx<T>* src = reinterpret_cast<const cpx<T>*>(ws + Tm.in[f]);
-            for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
-                const int c = i / M, ky = i % M;
-                const int s = ky - Tm.in_lr_first;
-                cpx<T> v{0, 0};
-                if (c < J.ncol && s >= 0 && s < Tm.in_ld)
-                    v = src[(size_t)(J.kx0 + c) * Tm.in_ld + s];
-                in[i] = v;
-            }
-            __syncthreads();
-            fft_lds<T, M, false>(in, tw);
-            const int Xx = kKernOf[0][f], Xy = kKernOf[1][f];
-            for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
-                const int c = i / M, ky = i % M;
-                if (c >= J.ncol) continue;
-                const int kx = J.kx0 + c;
-                const cpx<T> b = in[i];
-                ax[i] = ax[i] + cmul(kern_at<T, M>(K, Xx, kx, ky, Tm.flip), b);
-                ay[i] = ay[i] + cmul(kern_at<T, M>(K, Xy, kx, ky, Tm.flip), b);
-            }
-            __syncthreads();
-        }
-    }
-    fft_lds<T, M, true>(ax, tw);
-    fft_lds<T, M, true>(ay, tw);
-    cpx<T>* ox = reinterpret_cast<cpx<T>*>(ws + J.out_x);
-    cpx<T>* oy = reinterpret_cast<cpx<T>*>(ws + J.out_y);
-    for (int i = threadIdx.x; i < C * J.out_ld; i += blockDim.x) {
-        const int c = i / J.out_ld, s = i % J.out_ld;
-        if (c >= J.ncol) continue;
-        const size_t o = (size_t)(J.kx0 + c) * J.out_ld + s;
-        ox[o] = ax[c * M + J.out_lr_first + s];
-        oy[o] = ay[c * M + J.out_lr_first + s];
+    __syncthreads();
+    fft_lds<T, M, false>(A, tw);
+    if (col_ok) {
+        cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + J.out) + (size_t)kx * M;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[lane + q * TPS] = a[lds_pos(lane + q * TPS)];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Pass 3: one input, many polyphase outputs (coarser source, finer target)
+// Pass 3: kernel-spectrum products summed over inputs, inverse column FFT
 // ---------------------------------------------------------------------------
+// Slot (c, g) of a workgroup works on column kx0 + c for output
+// out0 + g / split, terms k, k + split, k + 2 split, ... (k = g % split):
+// every thread accumulates its eight frequencies over those terms (a
+// barrier-free stream of independent loads, the next term's descriptor
+// loaded ahead).  The split partial sums of an output are added in LDS into
+// its first slot, whose inverse column FFT then yields the output rows.
+
+struct MacTables {
+    const MacOut* outs;
+    const MacTerm* terms;
+};
 
 template <typename T, int M>
-__global__ void __launch_bounds__(1024) k_col_scatter(SegTable<ColScatterJob> segs,
-                                                      const cpx<T>* __restrict__ tw)
+__global__ void __launch_bounds__(TD_MAX_THREADS) k_col_mac(SegTable<ColMacJob> segs,
+                                                            const cpx<T>* __restrict__ tw_g, int G)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int C = blockDim.x / (M / 8);
-    cpx<T>* in0 = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* acc = in0 + 3 * C * M;
+    constexpr int TPS = M / 8;
+    constexpr int SP = lds_stride(M);
+    const int S = blockDim.x / TPS;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* tw = A + S * SP;
+    stage_twiddles<T, M>(tw, tw_g);
     int slot_unused;
     const void* aux;
     char* ws;
-    const ColScatterJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
-    const ColScatterOut* __restrict__ outs = reinterpret_cast<const ColScatterOut*>(aux);
-    bool present[3];
-    for (int f = 0; f < 3; ++f) {
-        present[f] = J.in[f] >= 0;
-        cpx<T>* dst = in0 + f * C * M;
-        const cpx<T>* src = present[f] ? reinterpret_cast<const cpx<T>*>(ws + J.in[f]) : nullptr;
-        for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
-            const int c = i / M, ky = i % M;
-            const int s = ky - J.in_lr_first;
-            cpx<T> v{0, 0};
-            if (src && c < J.ncol && s >= 0 && s < J.in_ld) v = src[(size_t)(J.kx0 + c) * J.in_ld + s];
-            dst[i] = v;
+    const ColMacJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
+    const MacTables tabs = *reinterpret_cast<const MacTables*>(aux);
+    const int slot = threadIdx.x / TPS, lane = threadIdx.x % TPS;
+    const int c = slot / G, g = slot % G;
+    const int o = g / J.split, k = g % J.split;
+    const int kx = J.kx0 + c;
+    const bool act = c < J.ncol && o < J.nout;
+    cpx<T>* a = A + slot * SP;
+    cpx<T> acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
+    MacOut O{0, 0, 0, 0, 0};
+    if (act) {
+        O = tabs.outs[J.out0 + o];
+        const MacTerm* __restrict__ tl = tabs.terms + O.term0;
+        int t = k;
+        MacTerm cur;
+        if (t < O.nterm) cur = tl[t];
+        while (t < O.nterm) {
+            const int tn = t + J.split;
+            MacTerm nxt = cur;
+            if (tn < O.nterm) nxt = tl[tn];
+            const cpx<T>* in = reinterpret_cast<const cpx<T>*>(ws + cur.in) + (size_t)kx * M;
+            cpx<T> vi[8], kv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int ky = lane + q * TPS;
+                vi[q] = in[ky];
+                kv[q] = kern_at<T, M>(cur.kern, cur.X, kx, ky, cur.flip);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = acc[q] + cmul(kv[q], vi[q]);
+            cur = nxt;
+            t = tn;
         }
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = acc[q];
     __syncthreads();
-    for (int f = 0; f < 3; ++f)
-        if (present[f]) fft_lds<T, M, false>(in0 + f * C * M, tw);
-    for (int o = 0; o < J.nout; ++o) {
-        const ColScatterOut O = outs[J.out0 + o];
-        const cpx<T>* K = reinterpret_cast<const cpx<T>*>(O.kern);
-        for (int comp = 0; comp < 2; ++comp) {
-            for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
-                const int c = i / M, ky = i % M;
-                cpx<T> a{0, 0};
-                if (c < J.ncol) {
-                    const int kx = J.kx0 + c;
-                    for (int f = 0; f < 3; ++f)
-                        if (present[f])
-                            a = a + cmul(kern_at<T, M>(K, kKernOf[comp][f], kx, ky, O.flip),
-                                         in0[f * C * M + i]);
-                }
-                acc[i] = a;
+    if (J.split > 1) {
+        // reduce the split partial sums into slot k = 0 of each output
+        if (act && k == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = lds_pos(lane + q * TPS);
+                cpx<T> sum = acc[q];
+                for (int h = 1; h < J.split; ++h) sum = sum + A[(slot + h) * SP + p];
+                acc[q] = sum;
             }
-            __syncthreads();
-            fft_lds<T, M, true>(acc, tw);
-            cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + (comp == 0 ? O.out_x : O.out_y));
-            for (int i = threadIdx.x; i < C * O.out_ld; i += blockDim.x) {
-                const int c = i / O.out_ld, s = i % O.out_ld;
-                if (c >= J.ncol) continue;
-                dst[(size_t)(J.kx0 + c) * O.out_ld + s] = acc[c * M + O.out_lr_first + s];
-            }
-            __syncthreads();
         }
+        __syncthreads();
+        if (act && k == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = acc[q];
+        }
+        __syncthreads();
+    }
+    fft_lds<T, M, true>(A, tw);
+    if (act && k == 0) {
+        cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + O.out) + (size_t)kx * O.out_ld;
+        for (int sr = lane; sr < O.out_ld; sr += TPS) dst[sr] = a[lds_pos(O.out_lr_first + sr)];
     }
 }
 
@@ -340,62 +380,97 @@ __device__ __forceinline__ int floor_div(int a, int b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+// A workgroup owns C target rows; each row's items -- (contribution, x-phase)
+// pairs, one complex-to-real row transform each -- run G at a time in the
+// row's G slots.  Spectra are read transposed ([kx][row]), rows fastest.
+// Every thread accumulates the outputs it owns in registers.
 template <typename T, int M>
-__global__ void __launch_bounds__(1024) k_row_inv(SegTable<RowInvJob> segs,
+__global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> segs,
                                                   void* const* __restrict__ ptrs,
-                                                  const cpx<T>* __restrict__ tw)
+                                                  const cpx<T>* __restrict__ tw_g, int G)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int C = blockDim.x / (M / 8);  // rows of this job
+    constexpr int TPS = M / 8;
+    constexpr int H = M / 2 + 1;
+    constexpr int SP = lds_stride(M);
+    const int S = blockDim.x / TPS;
+    const int C = S / G;  // rows of this workgroup
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* tw = A + S * SP;
+    __shared__ int it_m[16], it_kxp[16], it_oxs[16];
+    stage_twiddles<T, M>(tw, tw_g);
     int slot_base;
     const void* aux;
     char* ws;
     const RowInvJob J = segs.find(blockIdx.x, &slot_base, &aux, &ws);
     const RowInvContrib* __restrict__ contribs = reinterpret_cast<const RowInvContrib*>(aux);
-    constexpr int NQ = 16;  // up to C * 2M outputs over C * (M/8) threads (target n <= 2M)
+    int nitems = 0;
+    for (int k = 0; k < J.nc; ++k) nitems += contribs[J.c0 + k].m;
+    constexpr int NQ = 16;  // outputs per thread: C*nx <= C*2M = 16 * (C*M/8)
     T accx[NQ], accy[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) { accx[q] = 0; accy[q] = 0; }
     const int nout = J.ny * J.nx;
-    for (int k = 0; k < J.nc; ++k) {
-        const RowInvContrib Q = contribs[J.c0 + k];
-        const cpx<T>* base = reinterpret_cast<const cpx<T>*>(ws + Q.base);
-        for (int kxp = 0; kxp < Q.m; ++kxp) {
-            for (int i = threadIdx.x; i < C * (M / 2 + 1); i += blockDim.x) {
-                const int r = i % C, kx = i / C;
-                cpx<T> z{0, 0}, zr{0, 0};
-                if (r < J.ny) {
-                    const int g = J.oy_t + J.y0 + r;
-                    const int Jc = floor_div(g, Q.m);
-                    const int kyp = g - Jc * Q.m;
-                    const int sr = Jc - Q.oy_s - Q.lr_first;
-                    const cpx<T>* P = base + (size_t)(kyp * Q.m + kxp) * Q.phase_stride;
-                    cpx<T> X = P[(size_t)kx * Q.ld + sr];
-                    cpx<T> Y = P[Q.comp_stride + (size_t)kx * Q.ld + sr];
-                    if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
-                    z = cpx<T>{X.re - Y.im, X.im + Y.re};
-                    zr = cpx<T>{X.re + Y.im, Y.re - X.im};
-                }
-                buf[r * M + kx] = z;
-                if (kx > 0 && kx < M / 2) buf[r * M + M - kx] = zr;
+    for (int r0 = 0; r0 < nitems; r0 += G) {
+        // item descriptors of this round (identical for every row)
+        if (threadIdx.x < G) {
+            const int it = r0 + threadIdx.x;
+            int m = 1, kxp = -1, oxs = 0;
+            if (it < nitems) {
+                int k = 0, rem = it;
+                while (rem >= contribs[J.c0 + k].m) rem -= contribs[J.c0 + k].m, ++k;
+                m = contribs[J.c0 + k].m;
+                kxp = rem;
+                oxs = contribs[J.c0 + k].ox_s;
             }
-            __syncthreads();
-            fft_lds<T, M, true>(buf, tw);
+            it_m[threadIdx.x] = m;
+            it_kxp[threadIdx.x] = kxp;
+            it_oxs[threadIdx.x] = oxs;
+        }
+        // load: element e -> (slot g, frequency kx, row c), rows fastest
+        for (int e = threadIdx.x; e < G * H * C; e += blockDim.x) {
+            const int cc = e % C, kx = (e / C) % H, gg = e / (C * H);
+            const int it = r0 + gg;
+            cpx<T> z{0, 0}, zr{0, 0};
+            if (it < nitems && cc < J.ny) {
+                int k = 0, rem = it;
+                while (rem >= contribs[J.c0 + k].m) rem -= contribs[J.c0 + k].m, ++k;
+                const RowInvContrib& Q = contribs[J.c0 + k];
+                const int gy = J.oy_t + J.y0 + cc;
+                const int Jc = floor_div(gy, Q.m);
+                const int kyp = gy - Jc * Q.m;
+                const int sr = Jc - Q.oy_s - Q.lr_first;
+                const cpx<T>* P = reinterpret_cast<const cpx<T>*>(ws + Q.base) +
+                                  (size_t)(kyp * Q.m + rem) * Q.phase_stride;
+                cpx<T> X = P[(size_t)kx * Q.ld + sr];
+                cpx<T> Y = P[Q.comp_stride + (size_t)kx * Q.ld + sr];
+                if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
+                z = cpx<T>{X.re - Y.im, X.im + Y.re};
+                zr = cpx<T>{X.re + Y.im, Y.re - X.im};
+            }
+            cpx<T>* row = A + (cc * G + gg) * SP;
+            row[lds_pos(kx)] = z;
+            if (kx > 0 && kx < M / 2) row[lds_pos(M - kx)] = zr;
+        }
+        __syncthreads();
+        fft_lds<T, M, true>(A, tw);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int idx = threadIdx.x + q * blockDim.x;
-                if (idx >= nout) continue;
-                const int r = idx / J.nx, ii = J.x0 + idx % J.nx;
-                const int g = J.ox_t + ii;
-                const int Ic = floor_div(g, Q.m);
-                if (g - Ic * Q.m != kxp) continue;
-                const cpx<T> v = buf[r * M + (Ic - Q.ox_s)];
+        for (int q = 0; q < NQ; ++q) {
+            const int idx = threadIdx.x + q * blockDim.x;
+            if (idx >= nout) continue;
+            const int r = idx / J.nx, ii = J.x0 + idx % J.nx;
+            const int gx = J.ox_t + ii;
+            for (int gg = 0; gg < G; ++gg) {
+                const int m = it_m[gg], kxp = it_kxp[gg];
+                if (kxp < 0) break;
+                const int Ic = floor_div(gx, m);
+                if (gx - Ic * m != kxp) continue;
+                const cpx<T> v = A[(r * G + gg) * SP + lds_pos(Ic - it_oxs[gg])];
                 accx[q] += v.re;
                 accy[q] += v.im;
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
     T* fx = reinterpret_cast<T*>(ptrs[slot_base + J.out_slot]);
     T* fy = reinterpret_cast<T*>(ptrs[slot_base + J.out_slot + 1]);
@@ -423,13 +498,18 @@ __global__ void __launch_bounds__(1024) k_row_inv(SegTable<RowInvJob> segs,
 // ---------------------------------------------------------------------------
 
 template <typename TO, int M>
-__global__ void __launch_bounds__(1024) k_spec_col(const cpx<double>* __restrict__ rows,
-                                                   cpx<TO>* __restrict__ out,
-                                                   const cpx<double>* __restrict__ tw)
+__global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* __restrict__ rows,
+                                                   void* __restrict__ out_v,
+                                                   const cpx<double>* __restrict__ tw_g, int quarter)
 {
+    cpx<TO>* out = reinterpret_cast<cpx<TO>*>(out_v);
+    TO* outq = reinterpret_cast<TO*>(out_v);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<double>* buf = reinterpret_cast<cpx<double>*>(smem_raw);
     const int C = blockDim.x / (M / 8);
+    constexpr int SP = lds_stride(M);
+    cpx<double>* tw = buf + C * SP;
+    stage_twiddles<double, M>(tw, tw_g);
     constexpr int NCOL = M / 2 + 1;
     const int per_x = (NCOL + C - 1) / C;
     const int X = blockIdx.x / per_x;
@@ -438,7 +518,7 @@ __global__ void __launch_bounds__(1024) k_spec_col(const cpx<double>* __restrict
         const int c = i / M, ky = i % M;
         cpx<double> v{0, 0};
         if (kx0 + c < NCOL) v = rows[((size_t)X * NCOL + kx0 + c) * M + ky];
-        buf[i] = v;
+        buf[c * SP + lds_pos(ky)] = v;
     }
     __syncthreads();
     fft_lds<double, M, false>(buf, tw);
@@ -446,8 +526,14 @@ __global__ void __launch_bounds__(1024) k_spec_col(const cpx<double>* __restrict
     for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
         const int c = i / M, ky = i % M;
         if (kx0 + c >= NCOL) continue;
-        const cpx<double> v = buf[i];
-        out[((size_t)X * NCOL + kx0 + c) * M + ky] = cpx<TO>{(TO)(v.re * sc), (TO)(v.im * sc)};
+        const cpx<double> v = buf[c * SP + lds_pos(ky)];
+        if (!quarter) {
+            out[((size_t)X * NCOL + kx0 + c) * M + ky] = cpx<TO>{(TO)(v.re * sc), (TO)(v.im * sc)};
+        } else if (ky <= M / 2) {
+            // same-level kernel: real (s_x s_y = +1) or imaginary spectrum
+            const double r = (kSignX[X] * kSignY[X] > 0) ? v.re : v.im;
+            outq[((size_t)X * NCOL + kx0 + c) * NCOL + ky] = (TO)(r * sc);
+        }
     }
 }
 
@@ -471,7 +557,7 @@ hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& s
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * (M / 8);
-    const size_t smem = (size_t)C * M * sizeof(cpx<T>);
+    const size_t smem = lds_bytes(0, M, C, sizeof(cpx<T>));
     SegTable<RowFwdJob> s = segs;
     const void* const* p = ptrs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
@@ -485,17 +571,17 @@ hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& s
 }
 
 template <typename T>
-hipError_t launch_col_gather(int M, int C, int blocks, const SegTable<ColGatherJob>& segs,
-                             const void* tw, hipStream_t st)
+hipError_t launch_col_fwd(int M, int C, int blocks, const SegTable<ColFwdJob>& segs, const void* tw,
+                          hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * (M / 8);
-    const size_t smem = (size_t)3 * C * M * sizeof(cpx<T>);
-    SegTable<ColGatherJob> s = segs;
+    const size_t smem = lds_bytes(1, M, C, sizeof(cpx<T>));
+    SegTable<ColFwdJob> s = segs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
     void* args[] = {&s, &t};
     switch (M) {
-#define X(MM) case MM: return launch_common(k_col_gather<T, MM>, blocks, threads, smem, st, args);
+#define X(MM) case MM: return launch_common(k_col_fwd<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -503,17 +589,18 @@ hipError_t launch_col_gather(int M, int C, int blocks, const SegTable<ColGatherJ
 }
 
 template <typename T>
-hipError_t launch_col_scatter(int M, int C, int blocks, const SegTable<ColScatterJob>& segs,
-                              const void* tw, hipStream_t st)
+hipError_t launch_col_mac(int M, int C, int G, int blocks, const SegTable<ColMacJob>& segs,
+                          const void* tw, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
-    const int threads = C * (M / 8);
-    const size_t smem = (size_t)4 * C * M * sizeof(cpx<T>);
-    SegTable<ColScatterJob> s = segs;
+    const int threads = C * G * (M / 8);
+    const size_t smem = lds_bytes(2, M, C, sizeof(cpx<T>), G);
+    SegTable<ColMacJob> s = segs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
-    void* args[] = {&s, &t};
+    int g = G;
+    void* args[] = {&s, &t, &g};
     switch (M) {
-#define X(MM) case MM: return launch_common(k_col_scatter<T, MM>, blocks, threads, smem, st, args);
+#define X(MM) case MM: return launch_common(k_col_mac<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -521,16 +608,17 @@ hipError_t launch_col_scatter(int M, int C, int blocks, const SegTable<ColScatte
 }
 
 template <typename T>
-hipError_t launch_row_inv(int M, int C, int blocks, const SegTable<RowInvJob>& segs,
+hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
                           void* const* ptrs, const void* tw, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
-    const int threads = C * (M / 8);
-    const size_t smem = (size_t)C * M * sizeof(cpx<T>);
+    const int threads = C * G * (M / 8);
+    const size_t smem = lds_bytes(3, M, C, sizeof(cpx<T>), G);
     SegTable<RowInvJob> s = segs;
     void* const* p = ptrs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
-    void* args[] = {&s, &p, &t};
+    int g = G;
+    void* args[] = {&s, &p, &t, &g};
     switch (M) {
 #define X(MM) case MM: return launch_common(k_row_inv<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
@@ -541,16 +629,17 @@ hipError_t launch_row_inv(int M, int C, int blocks, const SegTable<RowInvJob>& s
 
 template <typename TO>
 hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void* tw64,
-                           hipStream_t st)
+                           int quarter, hipStream_t st)
 {
     const int threads = C * (M / 8);
     const int per_x = (M / 2 + 1 + C - 1) / C;
     const int blocks = 6 * per_x;
-    const size_t smem = (size_t)C * M * sizeof(cpx<double>);
+    const size_t smem = ((size_t)C * lds_stride(M) + M) * sizeof(cpx<double>);
     const cpx<double>* r = reinterpret_cast<const cpx<double>*>(rows);
-    cpx<TO>* o = reinterpret_cast<cpx<TO>*>(out);
+    void* o = out;
     const cpx<double>* t = reinterpret_cast<const cpx<double>*>(tw64);
-    void* args[] = {&r, &o, &t};
+    int q = quarter;
+    void* args[] = {&r, &o, &t, &q};
     switch (M) {
 #define X(MM) case MM: return launch_common(k_spec_col<TO, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
@@ -572,32 +661,33 @@ template hipError_t launch_row_fwd<float>(int, int, int, const SegTable<RowFwdJo
                                           const void* const*, const void*, hipStream_t);
 template hipError_t launch_row_fwd<double>(int, int, int, const SegTable<RowFwdJob>&,
                                            const void* const*, const void*, hipStream_t);
-template hipError_t launch_col_gather<float>(int, int, int, const SegTable<ColGatherJob>&,
-                                             const void*, hipStream_t);
-template hipError_t launch_col_gather<double>(int, int, int, const SegTable<ColGatherJob>&,
-                                              const void*, hipStream_t);
-template hipError_t launch_col_scatter<float>(int, int, int, const SegTable<ColScatterJob>&,
-                                              const void*, hipStream_t);
-template hipError_t launch_col_scatter<double>(int, int, int, const SegTable<ColScatterJob>&,
-                                               const void*, hipStream_t);
-template hipError_t launch_row_inv<float>(int, int, int, const SegTable<RowInvJob>&,
-                                          void* const*, const void*, hipStream_t);
-template hipError_t launch_row_inv<double>(int, int, int, const SegTable<RowInvJob>&,
-                                           void* const*, const void*, hipStream_t);
-template hipError_t launch_spec_col<float>(int, int, const void*, void*, const void*,
+template hipError_t launch_col_fwd<float>(int, int, int, const SegTable<ColFwdJob>&, const void*,
+                                          hipStream_t);
+template hipError_t launch_col_fwd<double>(int, int, int, const SegTable<ColFwdJob>&, const void*,
                                            hipStream_t);
-template hipError_t launch_spec_col<double>(int, int, const void*, void*, const void*,
+template hipError_t launch_col_mac<float>(int, int, int, int, const SegTable<ColMacJob>&,
+                                          const void*, hipStream_t);
+template hipError_t launch_col_mac<double>(int, int, int, int, const SegTable<ColMacJob>&,
+                                           const void*, hipStream_t);
+template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
+                                          void* const*, const void*, hipStream_t);
+template hipError_t launch_row_inv<double>(int, int, int, int, const SegTable<RowInvJob>&,
+                                           void* const*, const void*, hipStream_t);
+template hipError_t launch_spec_col<float>(int, int, const void*, void*, const void*, int,
+                                           hipStream_t);
+template hipError_t launch_spec_col<double>(int, int, const void*, void*, const void*, int,
                                             hipStream_t);
 
-// Raise the dynamic-LDS limit of every instantiation to the CU's 160 KiB.
+// Raise the dynamic-LDS limit of every instantiation to the CU's 160 KiB,
+// less a margin for what a kernel declares statically.
 hipError_t prepare_kernels()
 {
-    const int lim = 160 * 1024;
+    const int lim = (int)TD_MAX_DYN_LDS;
     hipError_t e = hipSuccess;
 #define SETA(k) if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 #define X(MM) SETA((k_row_fwd<float, MM>)) SETA((k_row_fwd<double, MM>)) \
-    SETA((k_col_gather<float, MM>)) SETA((k_col_gather<double, MM>)) \
-    SETA((k_col_scatter<float, MM>)) SETA((k_col_scatter<double, MM>)) \
+    SETA((k_col_fwd<float, MM>)) SETA((k_col_fwd<double, MM>)) \
+    SETA((k_col_mac<float, MM>)) SETA((k_col_mac<double, MM>)) \
     SETA((k_row_inv<float, MM>)) SETA((k_row_inv<double, MM>)) \
     SETA((k_spec_col<float, MM>)) SETA((k_spec_col<double, MM>))
     TD_FOR_EACH_M(X)

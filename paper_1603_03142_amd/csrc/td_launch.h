@@ -42,28 +42,38 @@ template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
                           const void* const* ptrs, const void* tw, hipStream_t st);
 template <typename T>
-hipError_t launch_col_gather(int M, int C, int blocks, const SegTable<ColGatherJob>& segs,
-                             const void* tw, hipStream_t st);
+hipError_t launch_col_fwd(int M, int C, int blocks, const SegTable<ColFwdJob>& segs, const void* tw,
+                          hipStream_t st);
 template <typename T>
-hipError_t launch_col_scatter(int M, int C, int blocks, const SegTable<ColScatterJob>& segs,
-                              const void* tw, hipStream_t st);
+hipError_t launch_col_mac(int M, int C, int G, int blocks, const SegTable<ColMacJob>& segs,
+                          const void* tw, hipStream_t st);
 template <typename T>
-hipError_t launch_row_inv(int M, int C, int blocks, const SegTable<RowInvJob>& segs,
+hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
                           void* const* ptrs, const void* tw, hipStream_t st);
 template <typename TO>
 hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void* tw64,
-                           hipStream_t st);
+                           int quarter, hipStream_t st);
 hipError_t launch_table(const TableJob& job, hipStream_t st);
 
 // Lift the dynamic-LDS cap of every pass instantiation (call once per device).
 hipError_t prepare_kernels();
 
-// Dynamic LDS of one workgroup of each pass (C sequences of length M).
-inline size_t lds_bytes(int pass, int M, int C, size_t elem)
+// Largest workgroup of any pass.  The launch bound lets the compiler give
+// every thread up to 256 VGPRs (two waves per SIMD), so the per-thread
+// FFT operands and partial sums stay in registers.
+#define TD_MAX_THREADS 512
+
+// Largest dynamic LDS a workgroup may request: 160 KiB less a margin for
+// the kernels' static LDS.
+#define TD_MAX_DYN_LDS (160u * 1024u - 512u)
+
+// Dynamic LDS of one workgroup of each pass: C sequences (row passes,
+// col_fwd) or C columns / rows x G slots, each padded to lds_stride(M), plus
+// the twiddle table (M entries).
+inline size_t lds_bytes(int pass, int M, int C, size_t elem, int G = 1)
 {
-    // pass 0 row_fwd: 1 buffer; 1 gather: 3; 2 scatter: 4; 3 row_inv: 1
-    static const int nbuf[4] = {1, 3, 4, 1};
-    return (size_t)nbuf[pass] * C * M * elem;
+    const size_t SP = (size_t)M + M / 8;
+    return ((size_t)C * G * SP + M) * elem;
 }
 
 }  // namespace td
