@@ -1,0 +1,253 @@
+"""Batches, graph replays, the serving loop, full-size workloads and the
+largest size, through the C ABI.
+
+Batch and graph solves run the same jobs as single solves and must agree
+bit for bit; served results must agree with solo results within the FP32
+tolerance (they agree bit for bit as well, since a request's jobs do not
+depend on its neighbours).  Full-size parity is checked on sampled targets
+against the oracle.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import gpu_solve, rand_fields, rel_l2, rel_l2_full, sampled, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1603_03142_amd as td
+    c = td.Context(0)
+    yield c
+    c.close()
+
+
+def _mix(seed=21, count=6, sizes=(24, 40, 64)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.choice(sizes))
+        lv = [(n, 0, 0)]
+        for _ in range(int(rng.integers(0, 3))):
+            pn, pox, poy = lv[-1]
+            w = int(rng.integers(2, pn // 2 + 1))
+            kx, ky = (int(v) for v in rng.integers(0, pn - w + 1, 2))
+            lv.append((2 * w, 2 * (pox + kx), 2 * (poy + ky)))
+        out.append(synth.nested_hierarchy(-1.0, -1.0, 2.0 / n, 2, lv))
+    return out
+
+
+def _dev_fields(hier, seed, dtype):
+    import torch
+    td_ = torch.float32 if dtype == "f32" else torch.float64
+    s, x, y = rand_fields(hier, seed)
+    return (to_dev(s, td_), to_dev(x, td_), to_dev(y, td_)), (s, x, y)
+
+
+def _host(outs):
+    """[(fx list, fy list)] of tensors -> the same structure of numpy arrays."""
+    return [tuple([t.double().cpu().numpy() for t in lst] for lst in pair) for pair in outs]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_single_solves(ctx, use_graph):
+    import torch
+    import paper_1603_03142_amd as td
+    hiers = _mix()
+    plans = [ctx.plan(h, "f32") for h in hiers]
+    fields = [_dev_fields(h, 100 + k, "f32")[0] for k, h in enumerate(hiers)]
+    single = []
+    for p, f in zip(plans, fields):
+        fx, fy = p.solve(*f)
+        single.append((fx, fy))
+    torch.cuda.synchronize()
+    batch = td.Batch(ctx, plans)
+    res = batch.solve(fields, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for (ax, ay), (bx, by) in zip(_host(single), _host(res)):
+        for a, b in zip(ax + ay, bx + by):
+            assert np.array_equal(a, b)
+    batch.close()
+
+
+def test_graph_replays_track_inputs(ctx):
+    """A captured batch replayed several times, with other GPU work and new
+    inputs between replays, matches an eager solve of every replay's inputs."""
+    import torch
+    import paper_1603_03142_amd as td
+    hiers = _mix(seed=7, count=3)
+    plans = [ctx.plan(h, "f32") for h in hiers]
+    batch = td.Batch(ctx, plans)
+    outs = [p.outputs() for p in plans]
+    for rep in range(4):
+        fields = [_dev_fields(h, 1000 * rep + k, "f32")[0] for k, h in enumerate(hiers)]
+        batch.solve(fields, outs=outs, use_graph=True)
+        junk = torch.randn(1 << 20, device="cuda")
+        (junk * 2).sum().item()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        got = _host(outs)
+        for k, (p, f) in enumerate(zip(plans, fields)):
+            fx, fy = p.solve(*f)
+            torch.cuda.synchronize()
+            want = _host([(fx, fy)])[0]
+            for a, b in zip(got[k][0] + got[k][1], want[0] + want[1]):
+                assert np.array_equal(a, b), f"replay {rep} member {k}"
+    batch.close()
+
+
+def test_server_alone_equals_in_mix(ctx):
+    import torch
+    import paper_1603_03142_amd as td
+    hiers = _mix(seed=3, count=12)
+    plans = [ctx.plan(h, "f32") for h in hiers]
+    fields = [_dev_fields(h, 300 + k, "f32")[0] for k, h in enumerate(hiers)]
+    srv = td.Server(ctx, max_inflight=3, max_batch=8)
+    # alone
+    t, fx, fy = srv.submit(plans[0], *fields[0])
+    srv.drain()
+    done, lat = srv.poll(t)
+    assert done and lat > 0
+    alone = _host([(fx, fy)])[0]
+    # in a mix: the same request among the others, several times over
+    tickets = []
+    for rep in range(3):
+        for k in range(len(plans)):
+            tickets.append((k, *srv.submit(plans[k], *fields[k])))
+    srv.drain()
+    lats = []
+    for k, tk, fx, fy in tickets:
+        done, lat = srv.poll(tk)
+        assert done
+        lats.append(lat)
+        if k == 0:
+            mix = _host([(fx, fy)])[0]
+            num = sum(((a - b) ** 2).sum() for a, b in zip(mix[0] + mix[1], alone[0] + alone[1]))
+            den = sum((b ** 2).sum() for b in alone[0] + alone[1])
+            assert math.sqrt(num / den) <= 1e-5
+    st = srv.stats()
+    assert st["completed"] == 1 + 3 * len(plans)
+    assert st["batches"] >= 2
+    srv.close()
+
+
+def test_server_cancel_and_budget(ctx):
+    import paper_1603_03142_amd as td
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / 128, 2, [(128, 0, 0), (128, 64, 64)])
+    plan = ctx.plan(hier, "f32")
+    f = _dev_fields(hier, 5, "f32")[0]
+    srv = td.Server(ctx, max_inflight=1, max_batch=1)
+    tickets = [srv.submit(plan, *f)[0] for _ in range(6)]
+    cancelled = 0
+    try:
+        srv.cancel(tickets[-1])
+        cancelled = 1
+    except td.TdError as e:       # already started: allowed, reported as EINVAL
+        assert e.status == 1
+    srv.drain()
+    st = srv.stats()
+    assert st["cancelled"] == cancelled
+    assert st["completed"] == 6 - cancelled
+    srv.close()
+    # a context whose budget cannot hold a request's workspace refuses it
+    small = td.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(td.TdError) as ei:
+        small.plan(synth.nested_hierarchy(-1.0, -1.0, 2.0 / 256, 2, [(256, 0, 0)]), "f32")
+    assert ei.value.status == 4  # TD_ENOMEM
+    small.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_config2_sampled(ctx, dtype, tol):
+    """Two nested 256^2 levels, Maclaurin + clump: 256 sampled targets."""
+    hier, fn = synth.config2()
+    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, dtype)
+    tg = synth.sample_targets(hier, 256, seed=11)
+    ox, oy = oracle.forces(hier, sig, dx, dy, tg)
+    sx, sy = sampled(hier, gx, gy, tg)
+    err = rel_l2(sx, sy, ox, oy)
+    print(f"config2 {dtype} sampled rel-L2 {err:.3e}")
+    assert err <= tol
+
+
+def test_config3_sampled_f32(ctx):
+    """Four nested 512^2 levels snapped near (0.3, 0), D2 disk x lognormal:
+    sampled targets, FP32 FFTs with FP64-built spectra."""
+    hier, fn = synth.config3()
+    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, "f32")
+    tg = synth.sample_targets(hier, 48, seed=12)
+    ox, oy = oracle.forces(hier, sig, dx, dy, tg)
+    sx, sy = sampled(hier, gx, gy, tg)
+    err = rel_l2(sx, sy, ox, oy)
+    print(f"config3 f32 sampled rel-L2 {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_fp32_vs_fp64_full_field(ctx):
+    hier, fn = synth.config2()
+    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    ax, ay = gpu_solve(ctx, hier, sig, dx, dy, "f64")
+    bx, by = gpu_solve(ctx, hier, sig, dx, dy, "f32")
+    err = rel_l2_full(hier, bx, by, ax, ay)
+    print(f"config2 f32 vs f64 rel-L2 {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_largest_level_f32(ctx):
+    """One 2048^2 level (transform length 4096): sampled targets."""
+    n = 2048
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / n, 2, [(n, 0, 0)])
+    fn = synth.disk_dn(2, 0.9)
+    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, "f32")
+    tg = synth.sample_targets(hier, 12, seed=13)
+    ox, oy = oracle.forces(hier, sig, dx, dy, tg)
+    sx, sy = sampled(hier, gx, gy, tg)
+    assert rel_l2(sx, sy, ox, oy) <= 1e-5
+
+
+def test_autotuned_plans_keep_parity(tmp_path):
+    import paper_1603_03142_amd as td
+    c = td.Context(0)
+    db = str(tmp_path / "tune.jsonl")
+    c.autotune("f64", 128, db)
+    assert open(db).read().count('"pass"') >= 4
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / 40, 2, [(40, 0, 0), (32, 20, 12)])
+    sig, dx, dy = rand_fields(hier, 9)
+    ox, oy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = gpu_solve(c, hier, sig, dx, dy, "f64")
+    assert rel_l2_full(hier, gx, gy, ox, oy) <= 1e-12
+    c2 = td.Context(0)
+    c2.autotune("f64", 128, db)  # read back from the database
+    gx2, gy2 = gpu_solve(c2, hier, sig, dx, dy, "f64")
+    assert all(np.array_equal(a, b) for a, b in zip(gx + gy, gx2 + gy2))
+    c.close()
+    c2.close()
+
+
+def test_timing_and_traffic(ctx):
+    import torch
+    hier, fn = synth.config1()
+    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    plan = ctx.plan(hier, "f32")
+    f = (to_dev(sig, torch.float32), to_dev(dx, torch.float32), to_dev(dy, torch.float32))
+    ctx.timing(True)
+    ctx.timing_read()
+    for _ in range(3):
+        plan.solve(*f)
+    torch.cuda.synchronize()
+    t = ctx.timing_read()
+    ctx.timing(False)
+    for p in ("row_fwd", "col_fwd", "col_mac", "row_inv"):
+        assert t[p][1] == 3 and t[p][0] > 0
+    tr = plan.traffic()
+    assert all(tr[p] > 0 for p in ("row_fwd", "col_fwd", "col_mac", "row_inv"))
+    ws, spec = plan.footprint()
+    assert ws > 0 and spec > 0
