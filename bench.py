@@ -11,8 +11,14 @@ Inputs are resident in HBM before the timed region; kernel spectra are
 resident (plan built beforehand).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
-                  [--workload two-level-256|single-64|four-level-512]
-                  [--mode eager|graph] [--no-cpu]
+                  [--workload two-level-256|single-64|four-level-512|batch-64|serve]
+                  [--mode eager|graph] [--no-cpu] [--tune DB]
+
+Other workloads: batch-64 = 64 independent disks (base N in {64..512}, 1-3
+nested levels, random aligned refinement, generalized Maclaurin sigma) solved
+by one batched launch set per step; serve = Poisson arrivals (mean rate
+--rate) of mixed hierarchies (base N in {128..1024}, 1-5 levels) into the
+serving loop, reporting p50/p99 latency beside throughput.
 """
 import argparse
 import json
@@ -40,6 +46,127 @@ def workload(name):
     return hier, fn
 
 
+def run_batch(args, td, torch, synth):
+    """64 independent hierarchies per step, one batched launch set."""
+    import numpy as np
+    disks = synth.config4(seed=4, count=64)
+    ctx = td.Context(0)
+    if args.tune:
+        ctx.autotune(args.dtype, 1024, args.tune)
+    tdt = torch.float32 if args.dtype == "f32" else torch.float64
+    plans, fields = [], []
+    for hier, fn in disks:
+        s, x, y = synth.sample_fields(hier, fn, "central")
+        dev = lambda arrs: [torch.as_tensor(a, dtype=tdt, device="cuda") for a in arrs]
+        plans.append(ctx.plan(hier, args.dtype))
+        fields.append((dev(s), dev(x), dev(y)))
+    batch = td.Batch(ctx, plans)
+    outs = [p.outputs() for p in plans]
+    use_graph = args.mode == "graph"
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        batch.solve(fields, outs, use_graph=use_graph, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.solve(fields, outs, use_graph=use_graph, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = sum(p.cells for p in plans)
+    return {
+        "metric": "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle",
+        "value": cells * args.steps / el, "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "batch-64", "hierarchies": len(plans), "cells_per_step": cells,
+                   "mode": args.mode, "workspace_bytes": batch.footprint()},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
+def run_serve(args, td, torch, synth):
+    """Poisson arrivals of mixed hierarchies into the serving loop."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(5))
+    reqs = synth.config5_requests(seed=5, rate=args.rate, duration=args.duration)
+    ctx = td.Context(0, hbm_budget=int(args.budget_gb * (1 << 30)))
+    if args.tune:
+        ctx.autotune(args.dtype, 2048, args.tune)
+    tdt = torch.float32 if args.dtype == "f32" else torch.float64
+    # request types: distinct hierarchies planned once (kernel spectra and job
+    # lists resident); every arrival draws one type
+    ntypes = args.types
+    types = []
+    log = lambda msg: print(f"[serve] {msg}", file=sys.stderr, flush=True)
+    tp = time.perf_counter()
+    for k in range(ntypes):
+        _, hier, (order, alpha, fseed) = reqs[k % len(reqs)]
+        fn = synth.request_sigma(order, alpha, fseed, hier.h0)
+        s, x, y = synth.sample_fields(hier, fn, "central")
+        dev = lambda arrs: [torch.as_tensor(a, dtype=tdt, device="cuda") for a in arrs]
+        plan = ctx.plan(hier, args.dtype)
+        outs = [plan.outputs() for _ in range(2)]
+        types.append((plan, (dev(s), dev(x), dev(y)), outs))
+        log(f"planned type {k}: levels {len(hier.patches)} n {hier.patches[0].n} "
+            f"workspace {plan.footprint()[0] / 2**30:.2f} GiB ({time.perf_counter() - tp:.1f} s)")
+    srv = td.Server(ctx, max_inflight=args.inflight, max_batch=args.max_batch)
+    # warm-up: each type once
+    for plan, f, outs in types:
+        srv.submit(plan, *f, *outs[0])
+        srv.drain()
+    log(f"warm-up done ({time.perf_counter() - tp:.1f} s)")
+    torch.cuda.synchronize()
+    arrivals = [t for t, _, _ in reqs]
+    pick = rng.integers(0, ntypes, len(arrivals))
+    tickets = []
+    t0 = time.perf_counter()
+    for k, ta in enumerate(arrivals):
+        while time.perf_counter() - t0 < ta:
+            pass
+        plan, f, outs = types[pick[k]]
+        tk, _, _ = srv.submit(plan, *f, *outs[k % 2])
+        tickets.append((tk, plan.cells))
+    log(f"{len(tickets)} requests submitted ({time.perf_counter() - t0:.2f} s)")
+    last = time.perf_counter()
+    while True:
+        n_done = sum(srv.poll(tk)[0] for tk, _ in tickets[::max(1, len(tickets) // 200)])
+        if n_done == len(tickets[::max(1, len(tickets) // 200)]):
+            break
+        if time.perf_counter() - last > 5:
+            log(f"draining: {srv.stats()['completed']} completed "
+                f"({time.perf_counter() - t0:.1f} s)")
+            last = time.perf_counter()
+        time.sleep(0.01)
+    srv.drain()
+    el = time.perf_counter() - t0
+    lats = []
+    cells = 0
+    for tk, c in tickets:
+        done, lat = srv.poll(tk)
+        assert done
+        lats.append(lat)
+        cells += c
+    st = srv.stats()
+    lats = np.array(lats)
+    srv.close()
+    return {
+        "metric": "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency",
+        "value": cells / el, "unit": "cells/s", "n_gpus": 1, "steps": len(tickets),
+        "warmup": ntypes, "ms_per_step": 1000 * el / len(tickets), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "serve", "offered_rate": args.rate, "duration_s": args.duration,
+                   "request_types": ntypes, "max_inflight": args.inflight,
+                   "max_batch": args.max_batch, "hbm_budget_gb": args.budget_gb},
+        "serving": {"requests": len(tickets), "wall_s": el,
+                    "sustained_req_per_s": len(tickets) / el,
+                    "p50_ms": float(np.percentile(lats, 50) * 1e3),
+                    "p99_ms": float(np.percentile(lats, 99) * 1e3),
+                    "mean_ms": float(lats.mean() * 1e3), **st},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +179,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tune", metavar="DB", default=None,
                     help="autotune launch shapes first (JSON-lines database path)")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean arrivals per s")
+    ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals")
+    ap.add_argument("--types", type=int, default=48, help="serve: distinct request hierarchies")
+    ap.add_argument("--inflight", type=int, default=4, help="serve: concurrent batches")
+    ap.add_argument("--max-batch", type=int, default=16, help="serve: requests per batch")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget (GiB)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -66,6 +199,10 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload in ("batch-64", "serve"):
+        out = (run_batch if args.workload == "batch-64" else run_serve)(args, td, torch, synth)
+        print(json.dumps(out), flush=True)
+        return
     hier, fn = workload(args.workload)
     sig, dx, dy = synth.sample_fields(hier, fn, "central")
     tdt = torch.float32 if args.dtype == "f32" else torch.float64

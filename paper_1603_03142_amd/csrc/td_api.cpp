@@ -917,7 +917,8 @@ td_status validate_jobs(td_plan* P)
                 for (int c = j.kx0; c < j.kx0 + j.ncol; ++c) w.second[c] = 1;
             }
         }
-        // pass 4
+        // pass 4 (each contribution's input planes are proven once)
+        std::vector<char> contrib_ok(g.contribs.size(), 0);
         for (int a = 0; a < 2; ++a)
             for (auto& j : g.rinv[a]) {
                 if (j.y0 < 0 || j.ny < 1 || j.ny > g.C[P_ROWINV] || j.y0 + j.ny > j.n_t) return bad("rinv rows");
@@ -940,6 +941,8 @@ td_status validate_jobs(td_plan* P)
                     const int64_t last = c.base + ((int64_t)(c.m * c.m - 1) * c.phase_stride +
                                                    c.comp_stride + (int64_t)H * c.ld) * (int64_t)es;
                     if (c.base < 0 || last > ws) return bad("rinv contribution");
+                    if (contrib_ok[j.c0 + k]) continue;
+                    contrib_ok[j.c0 + k] = 1;
                     // every phase / component plane it reads was written in full
                     for (int p = 0; p < c.m * c.m; ++p)
                         for (int comp = 0; comp < 2; ++comp) {

@@ -155,6 +155,13 @@ class LognormalField:
     def __call__(self, x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
+        if x.ndim == 2 and x.shape == y.shape and np.all(x == x[:1]) and np.all(y == y[:, :1]):
+            # tensor-product grid (rows of x equal, columns of y equal):
+            # cos(a + b + c) = Re(e^{ia} e^{ib} e^{ic}) turns the mode sum
+            # into one complex matrix product
+            ex = np.exp(1j * (np.outer(x[0], self.w[:, 0]) + self.b))
+            ey = np.exp(1j * np.outer(y[:, 0], self.w[:, 1]))
+            return np.exp(self.amp * (ey @ ex.T).real)
         g = np.zeros(np.broadcast(x, y).shape)
         for k in range(0, len(self.b), 64):
             w = self.w[k:k + 64]
