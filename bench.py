@@ -31,6 +31,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
+
+# HBM bytes per launch of a pass, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs
+# of this script, each scaled by the ratio of a plain copy kernel's known
+# bytes to what the same counter read for it.  Keyed by (workload, dtype,
+# pass) and tied to the SHA-256 of the kernel source they were taken on: a
+# changed kernel reports null until it is profiled again.
+TRAFFIC = {
+    ("two-level-256", "f32", "col_mac"): (48273125, "262747bad735ddfb"),
+    ("two-level-256", "f32", "row_inv"): (35142736, "262747bad735ddfb"),
+    ("two-level-256", "f32", "row_fwd"): (10494778, "262747bad735ddfb"),
+    ("two-level-256", "f32", "col_fwd"): (25515334, "262747bad735ddfb"),
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("td_kernels.hip", "td_fft.hpp", "td_jobs.h", "td_launch.h"):
+        with open(os.path.join(ROOT, "paper_1603_03142_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, dtype, pass_name):
+    rec = TRAFFIC.get((workload_name, dtype, pass_name))
+    if rec is None or rec[1] != kernel_source_hash():
+        return None
+    return rec[0]
+
+
+def copy_calibration(torch, mb):
+    """A plain device copy of known size (mb MiB read + mb MiB written), run
+    outside the timed region, for scaling HBM byte counters."""
+    n = (mb << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def workload(name):
@@ -74,7 +115,7 @@ def run_batch(args, td, torch, synth):
     el = time.perf_counter() - t0
     cells = sum(p.cells for p in plans)
     return {
-        "metric": "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle",
+        "metric": METRIC,
         "value": cells * args.steps / el, "unit": "cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
@@ -151,7 +192,7 @@ def run_serve(args, td, torch, synth):
     lats = np.array(lats)
     srv.close()
     return {
-        "metric": "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency",
+        "metric": METRIC,
         "value": cells / el, "unit": "cells/s", "n_gpus": 1, "steps": len(tickets),
         "warmup": ntypes, "ms_per_step": 1000 * el / len(tickets), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
@@ -185,6 +226,10 @@ def main():
     ap.add_argument("--inflight", type=int, default=4, help="serve: concurrent batches")
     ap.add_argument("--max-batch", type=int, default=16, help="serve: requests per batch")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget (GiB)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run a plain copy of this many MiB first (counter calibration)")
+    ap.add_argument("--no-fp64-leg", action="store_true",
+                    help="skip the per-solve FP64 eager comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -199,6 +244,8 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_mb:
+        copy_calibration(torch, args.copy_mb)
     if args.workload in ("batch-64", "serve"):
         out = (run_batch if args.workload == "batch-64" else run_serve)(args, td, torch, synth)
         print(json.dumps(out), flush=True)
@@ -257,10 +304,36 @@ def main():
         achieved = bytes_per_launch / per_launch_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_us": round(per_launch_s * 1e6, 2),
+                "traffic": measured_traffic(args.workload, args.dtype, dom),
+                "avg_launch_us": round(per_launch_s * 1e6, 2),
                 "alg_bytes_per_launch": int(bytes_per_launch),
                 "passes_us_per_solve": {p: round(1000.0 * passes[p][0] / args.steps, 2)
                                         for p in passes}}
+
+    # the plain per-solve FP64 GPU path (eager, one solve per call, FP64
+    # throughout) on the same workload, for the speed-up of this run over it
+    fp64 = None
+    if not args.no_fp64_leg and not (args.dtype == "f64" and args.mode == "eager"):
+        S64, DX64, DY64 = ([torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in arrs]
+                           for arrs in (sig, dx, dy))
+        ctx64 = td.Context(0)
+        plan64 = ctx64.plan(hier, "f64")
+        FX64, FY64 = plan64.outputs()
+        k64 = max(3, args.steps // 4)
+        for _ in range(3):
+            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream)
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t0
+        v64 = cells * k64 / el64
+        fp64 = {"value": v64, "unit": "cells/s", "steps": k64,
+                "ms_per_step": 1000.0 * el64 / k64, "speedup": value / v64}
+        plan64.close()
+        ctx64.close()
+        del S64, DX64, DY64, FX64, FY64
 
     # CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
@@ -290,7 +363,7 @@ def main():
                         ((ox ** 2).sum() + (oy ** 2).sum()))
 
     out = {
-        "metric": "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle",
+        "metric": METRIC,
         "value": value,
         "unit": "cells/s",
         "n_gpus": 1,
@@ -309,6 +382,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "rel_l2_vs_oracle_sampled": acc,
+        "fp64_per_solve_gpu": fp64,
     }
     print(json.dumps(out), flush=True)
 
