@@ -210,8 +210,8 @@ td_status td_server_destroy(td_server* s);
 td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m, int32_t kx,
                           int32_t ky, double* out_host);
 
-/* The five passes of a solve, in launch order. */
-#define TD_NPASS 5   /* row_fwd, col_fwd, col_mac, row_inv, row_inv_accumulate */
+/* The timed launch kinds of a solve, in launch order. */
+#define TD_NPASS 4   /* row_fwd, col, row_inv, row_inv_accumulate */
 
 /* Per-pass timing.  While enabled, every solve enqueued outside graph
  * capture records a HIP event pair around each pass on the solve's stream.
@@ -222,9 +222,11 @@ td_status td_timing_enable(td_context* ctx, int enable);
 td_status td_timing_read(td_context* ctx, double* ms, int64_t* launches);
 
 /* Algorithmic HBM bytes one solve of the plan moves in each pass (array of
- * TD_NPASS): every source value and workspace spectrum read once per use
- * its pass makes of it, every kernel-spectrum column read once per use,
- * every output written once. */
+ * TD_NPASS): row_fwd reads every source value in range and writes its row
+ * spectra; col reads every row-spectrum plane and every stored kernel plane
+ * once and writes every column output once; row_inv reads its column
+ * outputs once per target row that uses them and writes (or reads and
+ * writes, when accumulating) every force value. */
 td_status td_plan_traffic(const td_plan* plan, double* bytes);
 
 const char* td_status_string(td_status s);

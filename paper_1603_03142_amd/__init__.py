@@ -91,15 +91,15 @@ class Context:
         B.check(lib().td_autotune(self.handle, _DT[dtype], max_M,
                                   db_path.encode() if db_path else None), "td_autotune")
 
-    PASSES = ("row_fwd", "col_fwd", "col_mac", "row_inv", "row_inv_acc")
+    PASSES = ("row_fwd", "col", "row_inv", "row_inv_acc")
 
     def timing(self, enable: bool = True):
         B.check(lib().td_timing_enable(self.handle, 1 if enable else 0), "td_timing_enable")
 
     def timing_read(self):
         """{pass: (milliseconds, launches)} since the previous read."""
-        ms = (ctypes.c_double * 5)()
-        n = (ctypes.c_int64 * 5)()
+        ms = (ctypes.c_double * len(self.PASSES))()
+        n = (ctypes.c_int64 * len(self.PASSES))()
         B.check(lib().td_timing_read(self.handle, ms, n), "td_timing_read")
         return {p: (ms[i], n[i]) for i, p in enumerate(self.PASSES)}
 
@@ -157,7 +157,7 @@ class Plan:
 
     def traffic(self):
         """{pass: algorithmic HBM bytes per solve}."""
-        b = (ctypes.c_double * 5)()
+        b = (ctypes.c_double * len(Context.PASSES))()
         B.check(lib().td_plan_traffic(self.handle, b), "td_plan_traffic")
         return {p: b[i] for i, p in enumerate(Context.PASSES)}
 

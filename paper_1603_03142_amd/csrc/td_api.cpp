@@ -17,12 +17,14 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <thread>
 #include <tuple>
 #include <vector>
 
+#include "td_fft.hpp"
 #include "td_launch.h"
 #include "thindisk.h"
 
@@ -67,7 +69,9 @@ int fft_len(int n)
 
 size_t elem_size(td_dtype dt) { return dt == TD_F64 ? 16 : 8; }  // complex element
 
-enum Pass { P_ROWFWD = 0, P_COLFWD = 1, P_COLMAC = 2, P_ROWINV = 3 };
+// Launch-shape passes; timing adds a fourth slot for the accumulating
+// row-inverse launches.
+enum Pass { P_ROWFWD = 0, P_COL = 1, P_ROWINV = 2, NSHAPE = 3, NTIMED = 4 };
 
 // Kernel feeding output component c (0: Fx, 1: Fy) from field f (sigma,
 // dsdx, dsdy): I0, Ixx, Ixy for Fx and J0, Jyx, Jyy for Fy.
@@ -79,22 +83,23 @@ int shape_C(int v) { return v & 0xffff; }
 int shape_G(int v) { return std::max(1, v >> 16); }
 int pack_shape(int C, int G) { return C | (G << 16); }
 
-// Default launch shapes: 512 threads for the column passes and the row
-// inverse (col_mac: up to 8 outputs of a column at once; row_inv: up to 4
-// contributions of a row at once), 256 for the row FFTs; LDS <= 64 KiB.
+// Default launch shapes (from autotuning on gfx950): row FFTs 256 threads;
+// the column pass and the row inverse one column / row per workgroup with
+// up to 16 slots, 512 threads up to M = 256 and 256 threads beyond; LDS
+// <= 64 KiB.
 int default_shape(int pass, int M, td_dtype dt)
 {
     const size_t es = elem_size(dt);
     if (pass == P_ROWFWD) {
         int S = std::max(1, 2048 / M);
-        while (S > 1 && lds_bytes(pass, M, S, es) > 64 * 1024) S /= 2;
+        while (S > 1 && lds_bytes(M, S, es) > 64 * 1024) S /= 2;
         return pack_shape(S, 1);
     }
-    int S = std::max(1, 4096 / M);
-    int G = pass == P_COLFWD ? 1 : std::min(pass == P_ROWINV ? 4 : 8, S);
+    int S = std::max(1, (M <= 256 ? 4096 : 2048) / M);
+    int G = std::min(16, S);
     int C = std::max(1, S / G);
-    while (C > 1 && lds_bytes(pass, M, C, es, G) > 64 * 1024) C /= 2;
-    while (G > 1 && lds_bytes(pass, M, C, es, G) > 64 * 1024) G /= 2;
+    while (C > 1 && lds_bytes(M, C, es, G) > 64 * 1024) C /= 2;
+    while (G > 1 && lds_bytes(M, C, es, G) > 64 * 1024) G /= 2;
     return pack_shape(C, G);
 }
 
@@ -132,8 +137,8 @@ struct td_context {
     struct Timed { int pass; hipEvent_t a, b; };
     std::vector<Timed> timed;
     std::vector<hipEvent_t> ev_pool;
-    double t_ms[5] = {0, 0, 0, 0, 0};
-    int64_t t_n[5] = {0, 0, 0, 0, 0};
+    double t_ms[NTIMED] = {0, 0, 0, 0};
+    int64_t t_n[NTIMED] = {0, 0, 0, 0};
     hipEvent_t get_event()
     {
         hipEvent_t e = nullptr;
@@ -198,22 +203,27 @@ td_status twiddles(td_context* ctx, int M, td_dtype dt, const void** out)
         *out = it->second;
         return TD_OK;
     }
-    std::vector<double> h64(2 * (size_t)M);
-    std::vector<float> h32(2 * (size_t)M);
+    std::vector<double> h64(2 * (size_t)M, 0.0);
+    std::vector<float> h32(2 * (size_t)M, 0.0f);
     const long double two_pi = 6.283185307179586476925286766559005768L;
-    for (int k = 0; k < M; ++k) {
-        // exp(-2 pi i k / M) with the angle reduced to the first octant-free
-        // range by symmetry of the integer k.
-        long double a = two_pi * (long double)k / (long double)M;
-        long double c = cosl(a), s = -sinl(a);
-        if (4 * k == M) { c = 0; s = -1; }
-        if (2 * k == M) { c = -1; s = 0; }
-        if (4 * k == 3 * M) { c = 0; s = 1; }
-        h64[2 * k] = (double)c;
-        h64[2 * k + 1] = (double)s;
-        h32[2 * k] = (float)c;
-        h32[2 * k + 1] = (float)s;
-    }
+    // per-pass layout of fft_lds: entry tw_offset(M, NS) + (r-1) NS + k holds
+    // exp(-2 pi i r k / (8 NS)) = exp(-2 pi i e / M), e = r k M / (8 NS)
+    for (int NS = tw_first_span(M); NS < M; NS *= 8)
+        for (int r = 1; r < 8; ++r)
+            for (int k = 0; k < NS; ++k) {
+                const int idx = tw_offset(M, NS) + (r - 1) * NS + k;
+                const long long e = ((long long)r * k * (M / (8 * NS))) % M;
+                long double a = two_pi * (long double)e / (long double)M;
+                long double c = cosl(a), s = -sinl(a);
+                if (4 * e == M) { c = 0; s = -1; }
+                if (2 * e == M) { c = -1; s = 0; }
+                if (4 * e == 3LL * M) { c = 0; s = 1; }
+                if (e == 0) { c = 1; s = 0; }
+                h64[2 * idx] = (double)c;
+                h64[2 * idx + 1] = (double)s;
+                h32[2 * idx] = (float)c;
+                h32[2 * idx + 1] = (float)s;
+            }
     size_t bytes = (dt == TD_F64 ? sizeof(double) : sizeof(float)) * 2 * (size_t)M;
     void* d = nullptr;
     TD_TRY(ctx->alloc(bytes, &d));
@@ -412,22 +422,20 @@ namespace {
 // Jobs of one transform length M, on the host and on the device.
 struct Group {
     int M = 0;
-    int C[4] = {1, 1, 1, 1};   // sequences / columns per workgroup
-    int G[4] = {1, 1, 1, 1};   // slots per column (column passes)
+    int C[NSHAPE] = {1, 1, 1};   // sequences / columns / rows per workgroup
+    int G[NSHAPE] = {1, 1, 1};   // slots per column or row
     std::vector<RowFwdJob> rowfwd;
-    std::vector<ColFwdJob> colfwd;
-    std::vector<ColMacJob> colmac;
-    std::vector<MacOut> macouts;
-    std::vector<MacTerm> macterms;
+    std::vector<ColJob> col;
+    std::vector<ColIn> colins;
+    std::vector<ColOut> colouts;
     std::vector<RowInvJob> rinv[2];  // [0] write, [1] accumulate
     std::vector<RowInvContrib> contribs;
     // device copies
     RowFwdJob* d_rowfwd = nullptr;
-    ColFwdJob* d_colfwd = nullptr;
-    ColMacJob* d_colmac = nullptr;
-    MacOut* d_macouts = nullptr;
-    MacTerm* d_macterms = nullptr;
-    void* d_mactabs = nullptr;  // {d_macouts, d_macterms}
+    ColJob* d_col = nullptr;
+    ColIn* d_colins = nullptr;
+    ColOut* d_colouts = nullptr;
+    void* d_coltabs = nullptr;  // {d_colins, d_colouts}
     RowInvJob* d_rinv[2] = {nullptr, nullptr};
     RowInvContrib* d_contribs = nullptr;
 };
@@ -529,10 +537,8 @@ td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out
 //
 // Workspace per lattice t (level t's zero-padded M x M grid):
 //   own_in[t]      3 row-pass planes [M/2+1][n_t] of level t's fields
-//   own_sp[t]      3 spectra [M/2+1][M] of them (col_fwd)
 //   ph_in[s][t]    per finer level s: m^2 phases x 3 row-pass planes
 //                  [M/2+1][nr] of the polyphase sub-grids on lattice t
-//   ph_sp[s][t]    their spectra [M/2+1][M]
 //   own_out[t]     Fx, Fy column outputs [M/2+1][n_t]
 //   c3_out[t][s]   per finer level s: m^2 phases x (Fx, Fy) outputs
 //                  [M/2+1][ld] on lattice t for target level s
@@ -549,15 +555,13 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     };
     auto ptr = [&](size_t o) -> int64_t { return (int64_t)(o * es); };
     // ---- workspace layout
-    std::vector<size_t> own_in(L), own_sp(L), own_out(L);
-    std::vector<std::vector<size_t>> ph_in(L, std::vector<size_t>(L)), ph_sp(L, std::vector<size_t>(L)),
-        c3_out(L, std::vector<size_t>(L));
+    std::vector<size_t> own_in(L), own_out(L);
+    std::vector<std::vector<size_t>> ph_in(L, std::vector<size_t>(L)), c3_out(L, std::vector<size_t>(L));
     std::vector<std::vector<int>> ph_nr(L, std::vector<int>(L)), c3_ld(L, std::vector<int>(L));
     for (int l = 0; l < L; ++l) {
         const LevelG& g = P->lv[l];
         const size_t H = g.M / 2 + 1;
         own_in[l] = take(3 * H * g.n);
-        own_sp[l] = take(3 * H * g.M);
         own_out[l] = take(2 * H * g.n);
     }
     for (int t = 0; t < L; ++t)
@@ -568,7 +572,6 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             const int nr = (S.n + m - 1) / m + 1;
             ph_nr[s][t] = nr;
             ph_in[s][t] = take((size_t)m * m * 3 * H * nr);
-            ph_sp[s][t] = take((size_t)m * m * 3 * H * G.M);
             // coarser source t, finer target s: Case-3 outputs on lattice t
             const int ld = floor_div(S.oy + S.n - 1, m) - floor_div(S.oy, m) + 1;
             c3_ld[t][s] = ld;
@@ -580,28 +583,13 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     P->groups.clear();
     for (int l = 0; l < L; ++l) {
         Group& g = group_for(P->groups, P->lv[l].M);
-        for (int pass = 0; pass < 4; ++pass) {
+        for (int pass = 0; pass < NSHAPE; ++pass) {
             const int v = ctx->shape(pass, g.M, P->dt);
             g.C[pass] = shape_C(v);
             g.G[pass] = shape_G(v);
         }
     }
-    // column FFT jobs of one input plane set
-    auto add_colfwd = [&](Group& g, size_t in, size_t out, int ld, int lr_first) {
-        const int H = g.M / 2 + 1, C = g.C[P_COLFWD];
-        for (int kx0 = 0; kx0 < H; kx0 += C) {
-            ColFwdJob j;
-            memset(&j, 0, sizeof(j));
-            j.in = ptr(in);
-            j.out = ptr(out);
-            j.ld = ld;
-            j.lr_first = lr_first;
-            j.kx0 = kx0;
-            j.ncol = std::min(C, H - kx0);
-            g.colfwd.push_back(j);
-        }
-    };
-    // ---- passes 1 and 2: row FFTs and column FFTs of every input
+    // ---- pass 1: row FFTs of every input plane
     for (int l = 0; l < L; ++l) {
         const LevelG& G = P->lv[l];
         Group& g = group_for(P->groups, G.M);
@@ -622,7 +610,6 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 j.out = ptr(own_in[l] + f * plane);
                 g.rowfwd.push_back(j);
             }
-            add_colfwd(g, own_in[l] + f * plane, own_sp[l] + f * H * G.M, G.n, 0);
         }
         // polyphase sub-grids of every finer level s, placed on this lattice
         for (int s = l + 1; s < L; ++s) {
@@ -656,31 +643,28 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                             j.out = ptr(in);
                             g.rowfwd.push_back(j);
                         }
-                        add_colfwd(g, in, ph_sp[s][l] + ((size_t)phase * 3 + f) * H * G.M, nr, lr_lo);
                     }
                 }
         }
     }
-    // ---- pass 3: products and inverse column FFTs, per lattice
+    // ---- pass 2: column transforms, products and inverse column
+    // transforms, per lattice
     for (int t = 0; t < L; ++t) {
         const LevelG& G = P->lv[t];
         Group& g = group_for(P->groups, G.M);
         const size_t H = G.M / 2 + 1;
-        const int out0 = (int)g.macouts.size();
+        const int C = g.C[P_COL], Gs = g.G[P_COL];
         // (a) the level's own force: same-level kernels on its own fields,
         // Case-2 phase kernels on every finer level's sub-grids
+        const int in0 = (int)g.colins.size();
         {
             const SpecEntry* k1 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
-            std::vector<MacTerm> tm;  // terms of Fx; Fy uses the paired kernels
-            std::vector<MacTerm> tmy;
-            for (int f = 0; f < 3; ++f) {
-                tm.push_back({ptr(own_sp[t] + f * H * G.M), k1->ptr, kKernOfHost[0][f], 4});
-                tmy.push_back({ptr(own_sp[t] + f * H * G.M), k1->ptr, kKernOfHost[1][f], 4});
-            }
+            for (int f = 0; f < 3; ++f)
+                g.colins.push_back({ptr(own_in[t] + f * H * G.n), k1->ptr, G.n, 0, f, 4});
             for (int s = t + 1; s < L; ++s) {
                 const LevelG& S = P->lv[s];
-                const int m = ipow(r, s - t);
+                const int m = ipow(r, s - t), nr = ph_nr[s][t];
                 const SpecEntry* k2 = nullptr;
                 TD_TRY(plan_spectra(P, G.M, 2, m, &k2));
                 const size_t per_phase = 6 * H * G.M;
@@ -695,33 +679,28 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                     const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
                     const void* kern = (char*)k2->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
                     const int flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
-                    for (int f = 0; f < 3; ++f) {
-                        const int64_t in = ptr(ph_sp[s][t] + ((size_t)phase * 3 + f) * H * G.M);
-                        tm.push_back({in, kern, kKernOfHost[0][f], flip});
-                        tmy.push_back({in, kern, kKernOfHost[1][f], flip});
-                    }
+                    for (int f = 0; f < 3; ++f)
+                        g.colins.push_back({ptr(ph_in[s][t] + ((size_t)phase * 3 + f) * H * nr), kern,
+                                            nr, lr_lo, f, flip});
                 }
             }
-            for (int comp = 0; comp < 2; ++comp) {
-                MacOut o;
-                memset(&o, 0, sizeof(o));
-                o.out = ptr(own_out[t] + comp * H * G.n);
-                o.term0 = (int)g.macterms.size();
-                const auto& v = comp == 0 ? tm : tmy;
-                o.nterm = (int)v.size();
-                g.macterms.insert(g.macterms.end(), v.begin(), v.end());
-                o.out_ld = G.n;
-                o.out_lr_first = 0;
-                g.macouts.push_back(o);
-            }
+            const int out0 = (int)g.colouts.size();
+            for (int comp = 0; comp < 2; ++comp)
+                g.colouts.push_back({ptr(own_out[t] + comp * H * G.n), nullptr, G.n, 0, comp, 0});
+            const int nin = (int)g.colins.size() - in0;
+            for (int kx0 = 0; kx0 < (int)H; kx0 += C)
+                g.col.push_back({0, kx0, std::min(C, (int)H - kx0), in0, nin, out0, 2, 0});
         }
-        // (b) Case-3 phases of this (coarser) level onto every finer target
+        // (b) Case-3 phases of this (coarser) level onto every finer target:
+        // the level's three own planes (the first inputs above) are
+        // transformed again by every job; a job forms up to 4 G outputs
         for (int s = t + 1; s < L; ++s) {
             const LevelG& T = P->lv[s];
             const int m = ipow(r, s - t), ld = c3_ld[t][s];
             const SpecEntry* k3 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 3, m, &k3));
             const size_t per_phase = 6 * H * G.M;
+            const int out0 = (int)g.colouts.size();
             for (int pi = 0; pi < m * m; ++pi) {
                 int kx, ky;
                 mirror_order(m, pi, &kx, &ky);
@@ -729,45 +708,16 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
                 const void* kern = (char*)k3->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
                 const int flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
-                for (int comp = 0; comp < 2; ++comp) {
-                    MacOut o;
-                    memset(&o, 0, sizeof(o));
-                    o.out = ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld);
-                    o.term0 = (int)g.macterms.size();
-                    o.nterm = 3;
-                    for (int f = 0; f < 3; ++f)
-                        g.macterms.push_back({ptr(own_sp[t] + f * H * G.M), kern, kKernOfHost[comp][f], flip});
-                    o.out_ld = ld;
-                    o.out_lr_first = floor_div(T.oy, m) - G.oy;
-                    g.macouts.push_back(o);
-                }
+                for (int comp = 0; comp < 2; ++comp)
+                    g.colouts.push_back({ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld), kern, ld,
+                                         floor_div(T.oy, m) - G.oy, comp, flip});
             }
-        }
-        const int nout = (int)g.macouts.size() - out0;
-        const int C = g.C[P_COLMAC], Gs = g.G[P_COLMAC];
-        // the level's own Fx, Fy (outputs out0, out0 + 1) carry many terms:
-        // they get all slots of a column, split evenly; the Case-3 outputs
-        // (three terms each) take one slot apiece
-        const int own_split = std::max(1, Gs / 2);
-        for (int kx0 = 0; kx0 < (int)H; kx0 += C) {
-            ColMacJob j;
-            memset(&j, 0, sizeof(j));
-            j.kx0 = kx0;
-            j.ncol = std::min(C, (int)H - kx0);
-            j.out0 = out0;
-            j.nout = std::min(2, Gs);
-            j.split = Gs >= 2 ? own_split : 1;
-            g.colmac.push_back(j);
-            if (Gs < 2) {
-                j.out0 = out0 + 1;
-                g.colmac.push_back(j);
-            }
-            for (int o0 = out0 + 2; o0 < out0 + nout; o0 += Gs) {
-                j.out0 = o0;
-                j.nout = std::min(Gs, out0 + nout - o0);
-                j.split = 1;
-                g.colmac.push_back(j);
-            }
+            const int nout = (int)g.colouts.size() - out0;
+            const int chunk = 4 * Gs;
+            for (int kx0 = 0; kx0 < (int)H; kx0 += C)
+                for (int o0 = 0; o0 < nout; o0 += chunk)
+                    g.col.push_back({1, kx0, std::min(C, (int)H - kx0), in0, 3, out0 + o0,
+                                     std::min(chunk, nout - o0), 0});
         }
     }
     // ---- pass 4: row inverse, grouped by lattice length
@@ -855,10 +805,10 @@ td_status validate_jobs(td_plan* P)
         for (int f = 0; f < 5; ++f) nsrc[5 * l + f] = P->lv[l].n;
     for (auto& g : P->groups) {
         const int M = g.M, H = M / 2 + 1;
-        for (int pass = 0; pass < 4; ++pass) {
+        for (int pass = 0; pass < NSHAPE; ++pass) {
             const int C = g.C[pass], Gs = g.G[pass];
             if (C < 1 || Gs < 1 || Gs > 16 || C * Gs * (M / 8) > TD_MAX_THREADS ||
-                lds_bytes(pass, M, C, es, Gs) > TD_MAX_DYN_LDS)
+                lds_bytes(M, C, es, Gs) > TD_MAX_DYN_LDS)
                 return bad("launch shape");
         }
         // pass 1: rows written per row-pass plane
@@ -873,51 +823,49 @@ td_status validate_jobs(td_plan* P)
             if ((int)w.size() < j.ld) w.resize(j.ld, 0);
             for (int r = j.row0; r < j.row0 + j.nrow; ++r) w[r] = 1;
         }
-        // pass 2: columns written per spectrum plane
-        std::map<int64_t, std::vector<char>> cols_written;
-        for (auto& j : g.colfwd) {
-            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_COLFWD] || j.kx0 + j.ncol > H)
-                return bad("col_fwd columns");
-            if (j.lr_first < 0 || j.lr_first + j.ld > M) return bad("col_fwd rows");
-            if (!in_ws(j.in, (int64_t)H * j.ld) || !in_ws(j.out, (int64_t)H * M)) return bad("col_fwd planes");
-            auto it = rows_written.find(j.in);
-            if (it == rows_written.end() || (int)it->second.size() < j.ld) return bad("col_fwd reads unwritten rows");
-            for (int r = 0; r < j.ld; ++r)
-                if (!it->second[r]) return bad("col_fwd reads unwritten rows");
-            auto& w = cols_written[j.out];
-            if ((int)w.size() < H) w.resize(H, 0);
-            for (int c = j.kx0; c < j.kx0 + j.ncol; ++c) w[c] = 1;
+        // pass 2: inputs fully written by pass 1, outputs in range;
+        // columns written per output plane
+        std::vector<char> in_ok(g.colins.size(), 0);
+        for (size_t i = 0; i < g.colins.size(); ++i) {
+            const ColIn& I = g.colins[i];
+            if (I.ld < 1 || I.lr_first < 0 || I.lr_first + I.ld > M) return bad("col input rows");
+            if (I.f < 0 || I.f > 2 || I.flip < 0 || I.flip > 4) return bad("col input kernel");
+            if (!in_ws(I.in, (int64_t)H * I.ld)) return bad("col input plane");
+            auto it = rows_written.find(I.in);
+            if (it == rows_written.end() || (int)it->second.size() < I.ld) return bad("col reads unwritten rows");
+            for (int rr = 0; rr < I.ld; ++rr)
+                if (!it->second[rr]) return bad("col reads unwritten rows");
+            in_ok[i] = 1;
         }
-        // pass 3: outputs, terms, and columns written per output plane
+        for (auto& O : g.colouts) {
+            if (O.out_ld < 1 || O.out_lr_first < 0 || O.out_lr_first + O.out_ld > M) return bad("col output rows");
+            if (!in_ws(O.out, (int64_t)H * O.out_ld)) return bad("col output plane");
+            if (O.comp < 0 || O.comp > 1 || O.flip < 0 || O.flip > 3) return bad("col output kernel");
+        }
         std::map<int64_t, std::pair<int, std::vector<char>>> out_written;  // ld, columns
-        for (auto& o : g.macouts) {
-            if (o.out_lr_first < 0 || o.out_lr_first + o.out_ld > M) return bad("col_mac rows");
-            if (!in_ws(o.out, (int64_t)H * o.out_ld)) return bad("col_mac output");
-            if (o.term0 < 0 || o.nterm < 1 || o.term0 + o.nterm > (int)g.macterms.size())
-                return bad("col_mac terms");
-            for (int t = o.term0; t < o.term0 + o.nterm; ++t) {
-                const MacTerm& tm = g.macterms[t];
-                if (tm.X < 0 || tm.X > 5 || !tm.kern || tm.flip < 0 || tm.flip > 4) return bad("col_mac kernel");
-                auto it = cols_written.find(tm.in);
-                if (it == cols_written.end() || (int)it->second.size() < H) return bad("col_mac reads unwritten spectra");
-                for (int c = 0; c < H; ++c)
-                    if (!it->second[c]) return bad("col_mac reads unwritten spectra");
+        for (auto& j : g.col) {
+            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_COL] || j.kx0 + j.ncol > H) return bad("col columns");
+            if (j.in0 < 0 || j.nin < 1 || j.in0 + j.nin > (int)g.colins.size()) return bad("col inputs");
+            if (j.out0 < 0 || j.nout < 1 || j.out0 + j.nout > (int)g.colouts.size()) return bad("col outputs");
+            if (j.kind == 0) {
+                if (j.nout != 2) return bad("col own outputs");
+                for (int i = j.in0; i < j.in0 + j.nin; ++i)
+                    if (!g.colins[i].kern) return bad("col input kernel");
+            } else if (j.kind == 1) {
+                if (j.nin != 3) return bad("col Case-3 inputs");
+                for (int o = j.out0; o < j.out0 + j.nout; ++o)
+                    if (!g.colouts[o].kern) return bad("col output kernel");
+            } else {
+                return bad("col job kind");
             }
-        }
-        for (auto& j : g.colmac) {
-            if (j.kx0 < 0 || j.ncol < 1 || j.ncol > g.C[P_COLMAC] || j.kx0 + j.ncol > H)
-                return bad("col_mac columns");
-            if (j.out0 < 0 || j.nout < 1 || j.split < 1 || j.nout * j.split > g.G[P_COLMAC] ||
-                j.out0 + j.nout > (int)g.macouts.size())
-                return bad("col_mac outputs");
             for (int k = j.out0; k < j.out0 + j.nout; ++k) {
-                auto& w = out_written[g.macouts[k].out];
-                w.first = g.macouts[k].out_ld;
+                auto& w = out_written[g.colouts[k].out];
+                w.first = g.colouts[k].out_ld;
                 if ((int)w.second.size() < H) w.second.resize(H, 0);
-                for (int c = j.kx0; c < j.kx0 + j.ncol; ++c) w.second[c] = 1;
+                for (int cc = j.kx0; cc < j.kx0 + j.ncol; ++cc) w.second[cc] = 1;
             }
         }
-        // pass 4 (each contribution's input planes are proven once)
+        // pass 3 (each contribution's input planes are proven once)
         std::vector<char> contrib_ok(g.contribs.size(), 0);
         for (int a = 0; a < 2; ++a)
             for (auto& j : g.rinv[a]) {
@@ -997,15 +945,14 @@ td_status plan_upload(td_plan* P)
     td_context* ctx = P->ctx;
     for (auto& g : P->groups) {
         TD_TRY(upload(ctx, P, g.rowfwd, &g.d_rowfwd));
-        TD_TRY(upload(ctx, P, g.colfwd, &g.d_colfwd));
-        TD_TRY(upload(ctx, P, g.colmac, &g.d_colmac));
-        TD_TRY(upload(ctx, P, g.macouts, &g.d_macouts));
-        TD_TRY(upload(ctx, P, g.macterms, &g.d_macterms));
+        TD_TRY(upload(ctx, P, g.col, &g.d_col));
+        TD_TRY(upload(ctx, P, g.colins, &g.d_colins));
+        TD_TRY(upload(ctx, P, g.colouts, &g.d_colouts));
         {
-            const std::vector<const void*> tabs{g.d_macouts, g.d_macterms};
+            const std::vector<const void*> tabs{g.d_colins, g.d_colouts};
             const void** d = nullptr;
             TD_TRY(upload(ctx, P, tabs, &d));
-            g.d_mactabs = (void*)d;
+            g.d_coltabs = (void*)d;
         }
         TD_TRY(upload(ctx, P, g.rinv[0], &g.d_rinv[0]));
         TD_TRY(upload(ctx, P, g.rinv[1], &g.d_rinv[1]));
@@ -1130,13 +1077,13 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
     }
     // C per (pass, M) must agree across members; members built with other
     // tunings are launched in separate groups.
-    for (int pass = 0; pass < 5; ++pass) {
+    for (int pass = 0; pass < NTIMED; ++pass) {
         hipEvent_t ev_a = nullptr, ev_b = nullptr;
         bool any = false;
         for (auto& m : mem)
             for (auto& g : m.plan->groups) {
-                const size_t nj = pass == 0 ? g.rowfwd.size() : pass == 1 ? g.colfwd.size()
-                                : pass == 2 ? g.colmac.size() : g.rinv[pass == 3 ? 0 : 1].size();
+                const size_t nj = pass == P_ROWFWD ? g.rowfwd.size() : pass == P_COL ? g.col.size()
+                                : g.rinv[pass == P_ROWINV ? 0 : 1].size();
                 any |= nj > 0;
             }
         if (timed && any) {
@@ -1153,7 +1100,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
             for (auto& m : mem) {
                 Group* g = find_group(m.plan, M);
                 if (!g) continue;
-                const int pi = pass == 4 ? P_ROWINV : pass;
+                const int pi = pass == NSHAPE ? P_ROWINV : pass;
                 byC[pack_shape(g->C[pi], g->G[pi])].push_back({g, &m});
             }
             for (auto& kv : byC) {
@@ -1168,24 +1115,15 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
                         e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st)
                                 : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st);
-                } else if (pass == P_COLFWD) {
-                    std::vector<SegTable<ColFwdJob>> t;
+                } else if (pass == P_COL) {
+                    std::vector<SegTable<ColJob>> t;
                     std::vector<int> n;
                     for (auto& gs : kv.second)
-                        push_seg(t, n, gs.first->d_colfwd, (int)gs.first->colfwd.size(),
-                                 gs.second->slot_base, nullptr, gs.second->ws);
+                        push_seg(t, n, gs.first->d_col, (int)gs.first->col.size(), gs.second->slot_base,
+                                 (const void*)gs.first->d_coltabs, gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_col_fwd<double>(M, C, n[i], t[i], tw, st)
-                                : launch_col_fwd<float>(M, C, n[i], t[i], tw, st);
-                } else if (pass == P_COLMAC) {
-                    std::vector<SegTable<ColMacJob>> t;
-                    std::vector<int> n;
-                    for (auto& gs : kv.second)
-                        push_seg(t, n, gs.first->d_colmac, (int)gs.first->colmac.size(),
-                                 gs.second->slot_base, (const void*)gs.first->d_mactabs, gs.second->ws);
-                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_col_mac<double>(M, C, Gs, n[i], t[i], tw, st)
-                                : launch_col_mac<float>(M, C, Gs, n[i], t[i], tw, st);
+                        e = f64 ? launch_col<double>(M, C, Gs, n[i], t[i], tw, st)
+                                : launch_col<float>(M, C, Gs, n[i], t[i], tw, st);
                 } else {
                     const int a = pass == P_ROWINV ? 0 : 1;
                     std::vector<SegTable<RowInvJob>> t;
@@ -1318,8 +1256,10 @@ extern "C" td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_d
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         std::vector<const void*> seen;
         for (auto& g : P->groups) {
-            for (auto& t : g.macterms)
+            for (auto& t : g.colins)
                 if (std::find(seen.begin(), seen.end(), t.kern) == seen.end()) seen.push_back(t.kern);
+            for (auto& t : g.colouts)
+                if (t.kern && std::find(seen.begin(), seen.end(), t.kern) == seen.end()) seen.push_back(t.kern);
         }
         size_t b = 0;
         for (auto& kv : ctx->spectra) {
@@ -1867,7 +1807,7 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
         db_load(ctx, db_path, arch);
         bool all = true;
         for (int M = 64; M <= max_M; M *= 2)
-            for (int pass = 0; pass < 4; ++pass)
+            for (int pass = 0; pass < NSHAPE; ++pass)
                 all &= ctx->tune.count(std::make_tuple(pass, M, (int)dt)) > 0;
         if (all) return TD_OK;
     }
@@ -1888,14 +1828,14 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
             result = ctx->alloc((size_t)n * n * es, &bufs[k]);
             if (result == TD_OK) (void)hipMemset(bufs[k], 0, (size_t)n * n * es);
         }
-        for (int pass = 0; pass < 4 && result == TD_OK; ++pass) {
+        for (int pass = 0; pass < NSHAPE && result == TD_OK; ++pass) {
             int bestC = -1;
             double best = 1e30;
             std::vector<int> cands;
             for (int C = 1; C * (M / 8) <= TD_MAX_THREADS; C *= 2)
-                for (int Gs = 1; Gs <= ((pass == P_ROWFWD || pass == P_COLFWD) ? 1 : 16); Gs *= 2)
+                for (int Gs = 1; Gs <= (pass == P_ROWFWD ? 1 : 16); Gs *= 2)
                     if (C * Gs * (M / 8) <= TD_MAX_THREADS &&
-                        lds_bytes(pass, M, C, elem_size(dt), Gs) <= TD_MAX_DYN_LDS)
+                        lds_bytes(M, C, elem_size(dt), Gs) <= TD_MAX_DYN_LDS)
                         cands.push_back(pack_shape(C, Gs));
             for (int C : cands) {
                 {
@@ -2002,7 +1942,7 @@ extern "C" td_status td_timing_read(td_context* ctx, double* ms, int64_t* launch
         ctx->ev_pool.push_back(t.b);
     }
     ctx->timed.clear();
-    for (int p = 0; p < 5; ++p) {
+    for (int p = 0; p < NTIMED; ++p) {
         if (ms) ms[p] = ctx->t_ms[p];
         if (launches) launches[p] = ctx->t_n[p];
         ctx->t_ms[p] = 0;
@@ -2015,7 +1955,7 @@ extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
 {
     if (!P || !bytes) return fail(TD_EINVAL, "NULL argument");
     const double cs = (double)elem_size(P->dt), rs = cs / 2;
-    for (int p = 0; p < 5; ++p) bytes[p] = 0;
+    for (int p = 0; p < NTIMED; ++p) bytes[p] = 0;
     for (auto& g : P->groups) {
         const int M = g.M, H = M / 2 + 1;
         for (auto& j : g.rowfwd) {
@@ -2030,39 +1970,33 @@ extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
                 const int sr = j.m * (j.lr_first + r) + j.row_off;
                 rows += (sr >= 0 && sr < j.n_src) ? 1 : 0;
             }
-            bytes[0] += (double)rows * cols * rs + (double)H * j.nrow * cs;
+            bytes[P_ROWFWD] += (double)rows * cols * rs + (double)H * j.nrow * cs;
         }
-        for (auto& j : g.colfwd) bytes[1] += (double)j.ncol * (j.ld + M) * cs;
-        // col_mac: per column and output, every input spectrum column and the
-        // stored kernel column it multiplies (kernel columns shared by the
-        // outputs of one workgroup -- mirror images, Fx / Fy pairs -- once)
-        for (auto& j : g.colmac) {
-            std::vector<std::pair<const void*, int>> seen_k;
-            std::vector<int64_t> seen_in;
-            for (int k = j.out0; k < j.out0 + j.nout; ++k) {
-                const MacOut& o = g.macouts[k];
-                bytes[2] += (double)j.ncol * o.out_ld * cs;
-                for (int t = o.term0; t < o.term0 + o.nterm; ++t) {
-                    const MacTerm& tm = g.macterms[t];
-                    if (std::find(seen_in.begin(), seen_in.end(), tm.in) == seen_in.end()) {
-                        seen_in.push_back(tm.in);
-                        bytes[2] += (double)j.ncol * M * cs;
-                    }
-                    const auto key = std::make_pair(tm.kern, tm.X);
-                    if (std::find(seen_k.begin(), seen_k.end(), key) == seen_k.end()) {
-                        seen_k.push_back(key);
-                        bytes[2] += (double)j.ncol * ((tm.flip & 4) ? H * rs : M * cs);
-                    }
-                }
-            }
+        // col: every input plane, every stored kernel plane it multiplies
+        // (real quarter planes for same-level kernels) and every output
+        // plane, once per solve
+        std::set<int64_t> ins;
+        std::set<std::pair<const void*, int>> kerns;
+        for (auto& I : g.colins) {
+            if (ins.insert(I.in).second) bytes[P_COL] += (double)H * I.ld * cs;
+            for (int comp = 0; comp < 2; ++comp)
+                if (kerns.insert({I.kern, kKernOfHost[comp][I.f]}).second)
+                    bytes[P_COL] += (I.flip & 4) ? (double)H * H * rs : (double)H * M * cs;
+        }
+        for (auto& O : g.colouts) {
+            bytes[P_COL] += (double)H * O.out_ld * cs;
+            if (O.kern)
+                for (int f = 0; f < 3; ++f)
+                    if (kerns.insert({O.kern, kKernOfHost[O.comp][f]}).second)
+                        bytes[P_COL] += (double)H * M * cs;
         }
         for (int a = 0; a < 2; ++a)
             for (auto& j : g.rinv[a]) {
                 for (int k = 0; k < j.nc; ++k) {
                     const RowInvContrib& c = g.contribs[j.c0 + k];
-                    bytes[3 + a] += (double)c.m * j.ny * H * 2 * cs;
+                    bytes[P_ROWINV + a] += (double)c.m * j.ny * H * 2 * cs;
                 }
-                bytes[3 + a] += (double)j.ny * j.nx * 2 * rs * (a ? 2 : 1);
+                bytes[P_ROWINV + a] += (double)j.ny * j.nx * 2 * rs * (a ? 2 : 1);
             }
     }
     return TD_OK;

@@ -9,8 +9,18 @@
 // single LDS buffer per sequence suffices and the result is in natural order.
 //
 // Forward: X[k] = sum_n x[n] exp(-2 pi i k n / M); inverse uses +i and is
-// unnormalised.  Twiddles come from a table tw[k] = exp(-2 pi i k / M),
-// k < M, computed on the host in long double.
+// unnormalised.  Twiddles come from a table computed on the host in long
+// double and staged in LDS, laid out per pass so that the lanes of a
+// wavefront read consecutive entries (no bank conflicts): the radix-8 pass
+// of span NS finds exp(-2 pi i r k / (8 NS)) at tw_offset(M, NS) +
+// (r - 1) NS + k, r = 1..7, k < NS.  The table has fewer than M entries.
+//
+// Synchronisation: with M/8 <= 64 a sequence lives in one wavefront, whose
+// LDS operations complete in order, so the passes only need a wave-level
+// ordering point and the slots of a workgroup run independently; longer
+// sequences span several wavefronts and use workgroup barriers.  fft_lds
+// returns with the sequence ordered for its own wavefront(s) only: a caller
+// that then reads another wavefront's sequence must __syncthreads() first.
 //
 // LDS layout: element i of a sequence is stored at lds_pos(i) = i + i/8 and
 // sequences are lds_stride(M) = M + M/8 elements apart.  The extra element
@@ -106,6 +116,32 @@ __device__ __forceinline__ void dftR(cpx<T>* v)
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
+// Span of the first radix-8 pass with twiddles: after a radix-2 / radix-4
+// pass when log2(M) is not a multiple of 3, else after the first radix-8
+// pass (span 1, no twiddles).
+constexpr int tw_first_span(int M) { return ilog2(M) % 3 == 0 ? 8 : (1 << (ilog2(M) % 3)); }
+
+// Offset of the radix-8 pass of span NS in the twiddle table.
+constexpr int tw_offset(int M, int NS)
+{
+    int off = 0;
+    for (int s = tw_first_span(M); s < NS; s *= 8) off += 7 * s;
+    return off;
+}
+
+// Ordering point between the passes of one sequence (see above).
+template <int M>
+__device__ __forceinline__ void seq_sync()
+{
+    if constexpr (M / 8 <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One Stockham pass of radix R at span NS on sequence x (length M), for the
 // calling thread's `lane` in [0, M/8).
 template <typename T, int M, int R, int NS, bool INV>
@@ -113,7 +149,6 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 {
     constexpr int B = 8 / R;          // butterflies per thread
     constexpr int STRIDE = M / R;     // distance between butterfly inputs
-    constexpr int TWS = M / (NS * R); // twiddle table stride
     cpx<T> v[B][R];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -121,15 +156,17 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 #pragma unroll
         for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos(j + r * STRIDE)];
     }
-    __syncthreads();
+    seq_sync<M>();
 #pragma unroll
     for (int q = 0; q < B; ++q) {
         const int j = lane + q * (M / 8);
         const int k = (NS == 1) ? 0 : (j % NS);
         if constexpr (NS > 1) {
+            static_assert(R == 8, "only radix-8 passes carry twiddles");
+            const cpx<T>* tp = tw + tw_offset(M, NS) + k;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cpx<T> w = tw[r * k * TWS];
+                cpx<T> w = tp[(r - 1) * NS];
                 v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
             }
         }
@@ -138,7 +175,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 #pragma unroll
         for (int r = 0; r < R; ++r) x[lds_pos(base + r * NS)] = v[q][r];
     }
-    __syncthreads();
+    seq_sync<M>();
 }
 
 template <typename T, int M, int NS, bool INV>
@@ -151,14 +188,21 @@ __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restric
 }
 
 // Transform sequence `f = threadIdx.x / (M/8)` of the C sequences at buf
-// (padded layout).  Must be called by every thread of the workgroup (it
-// synchronises).
+// (padded layout).
+// Must be called by every thread of the workgroup (it synchronises).
+//
+// The thread index goes through an empty asm barrier: in a kernel that
+// calls fft_lds inside a loop, every LDS address and twiddle of every pass
+// is loop-invariant, and hoisting them all out of the loop would hold them
+// in registers for its whole length (tens of VGPRs, halving occupancy).
 template <typename T, int M, bool INV>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ tw)
 {
     static_assert(M >= 16 && (M & (M - 1)) == 0, "M must be a power of two >= 16");
-    const int f = threadIdx.x / (M / 8);
-    const int lane = threadIdx.x % (M / 8);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int f = tid / (M / 8);
+    const int lane = tid % (M / 8);
     cpx<T>* x = buf + (size_t)f * lds_stride(M);
     constexpr int REM = ilog2(M) % 3;
     if constexpr (REM == 1) {

@@ -1,17 +1,17 @@
 // Work descriptors shared by the host planner and the device passes.
 //
-// A solve is four passes over lists of jobs (one workgroup per job):
+// A solve is three passes over lists of jobs (one workgroup per job):
 //   1. row_fwd  zero-padded real-to-complex row FFTs of every source field
 //               (own level and polyphase sub-grids of finer levels), written
-//               transposed: spectrum column kx holds the rows.
-//   2. col_fwd  forward FFT of every spectrum column, zero-padded to the
-//               lattice length M: the full 2-D spectrum of every input.
-//   3. col_mac  per spectral column and output: the sum over inputs of input
-//               spectrum x kernel spectrum, then the inverse column FFT.
-//               Outputs are a level's own force (same-level and finer-source
-//               inputs, Case 2') and the polyphase outputs of a coarser
-//               source onto a finer target (Case 3').
-//   4. row_inv  complex-to-real row FFTs of the force spectra, window
+//               transposed: spectrum column kx holds the stored rows.
+//   2. col      per spectral column: the forward column FFT of every input
+//               plane, zero-padded to the lattice length M, multiplied by its
+//               kernel spectra and summed per output, then the inverse column
+//               FFT of every output.  Outputs are a level's own force
+//               (same-level and finer-source inputs, Case 2') and the
+//               polyphase outputs of a coarser source onto a finer target
+//               (Case 3').  No 2-D input spectrum is ever stored.
+//   3. row_inv  complex-to-real row FFTs of the force spectra, window
 //               extraction, phase interleave, sum over source levels,
 //               covered-cell masking.
 #pragma once
@@ -35,38 +35,42 @@ struct RowFwdJob {
     int64_t out;        // workspace byte offset: complex [M/2+1][ld]
 };
 
-// Forward column FFT of the C columns [kx0, kx0 + ncol) of one input plane.
-struct ColFwdJob {
-    int64_t in;          // workspace offset: complex [M/2+1][ld] (row pass output)
-    int64_t out;         // workspace offset: complex [M/2+1][M] (2-D spectrum)
-    int32_t ld;          // stored rows of the input plane
-    int32_t lr_first;    // lattice row of stored row 0
-    int32_t kx0, ncol;
-};
-
-// One product of an output: input spectrum x stored kernel spectrum X.
-struct MacTerm {
-    int64_t in;          // workspace offset: complex [M/2+1][M]
-    const void* kern;    // stored kernel spectra (see kern_at)
-    int32_t X;           // kernel index 0..5: I0, Ixx, Ixy, J0, Jyy, Jyx
+// One input plane of the column pass: a row-pass output [M/2+1][ld] whose
+// stored rows sit at lattice rows [lr_first, lr_first + ld) (zero
+// elsewhere), with the stored kernel spectra it is multiplied by.
+struct ColIn {
+    int64_t in;          // workspace offset: complex [M/2+1][ld]
+    const void* kern;    // stored kernel spectra of the level pair (see kern_at)
+    int32_t ld, lr_first;
+    int32_t f;           // field: 0 sigma, 1 dsdx, 2 dsdy
     int32_t flip;        // mirror / layout bits of the stored spectrum
 };
 
-// One output column family: sum of its terms, inverse column FFT, rows
-// [out_lr_first, out_lr_first + out_ld) written to [M/2+1][out_ld].
-struct MacOut {
+// One output plane of the column pass: the inverse column FFT of a sum of
+// products, lattice rows [out_lr_first, out_lr_first + out_ld) written to
+// [M/2+1][out_ld].
+struct ColOut {
     int64_t out;         // workspace offset
-    int32_t term0, nterm;
+    const void* kern;    // Case-3' outputs: the phase's stored kernel spectra
     int32_t out_ld, out_lr_first;
+    int32_t comp;        // 0: Fx, 1: Fy
+    int32_t flip;        // Case-3' outputs: mirror bits of the phase
 };
 
-// Columns [kx0, kx0 + ncol) x outputs [out0, out0 + nout); each output's
-// terms are split over `split` slots (nout * split <= slots per column),
-// whose partial sums are reduced before the inverse FFT.
-struct ColMacJob {
+// Columns [kx0, kx0 + ncol) of one job; a workgroup holds C columns x G
+// slots.
+//  kind 0 (a level's own force): inputs [in0, in0 + nin); slot g of a column
+//    takes inputs g, g + G, ..., transforms each and accumulates it times its
+//    kernels into Fx (output out0) and Fy (output out0 + 1); the slots'
+//    partial sums are reduced before the two inverse transforms.
+//  kind 1 (Case 3'): the three inputs [in0, in0 + 3) of the coarser level are
+//    transformed once; outputs [out0, out0 + nout), one per (phase,
+//    component), are formed from them G at a time and transformed back.
+struct ColJob {
+    int32_t kind;
     int32_t kx0, ncol;
+    int32_t in0, nin;
     int32_t out0, nout;
-    int32_t split;
     int32_t pad;
 };
 

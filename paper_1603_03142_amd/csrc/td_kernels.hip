@@ -119,11 +119,13 @@ __global__ void k_table(TableJob J)
 
 
 // Copy the twiddle table (M entries) into LDS; every pass of a workgroup's
-// FFTs then reads it from there.
+// FFTs then reads it from there.  Ends with a workgroup barrier: the FFTs
+// themselves may only order their own wavefront.
 template <typename T, int M>
 __device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src)
 {
     for (int i = threadIdx.x; i < M; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -172,6 +174,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     }
     __syncthreads();
     fft_lds<T, M, false>(buf, tw);
+    __syncthreads();  // the transposed write reads every sequence
     cpx<T>* out = reinterpret_cast<cpx<T>*>(ws + J.out);
     const int R = 2 * C;
     for (int idx = threadIdx.x; idx < (M / 2 + 1) * R; idx += blockDim.x) {
@@ -196,105 +199,131 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
 // ---------------------------------------------------------------------------
 
 // Kernels X = 0..5: I0, Ixx, Ixy, J0, Jyy, Jyx.  Parity under x- and
-// y-mirrors of the source cell about the target.
-__device__ __constant__ int kSignX[6] = {-1, 1, -1, 1, 1, -1};
-__device__ __constant__ int kSignY[6] = {1, 1, -1, -1, 1, -1};
+// y-mirrors of the source cell about the target:
+//   s_x = -1, 1, -1, 1, 1, -1 and s_y = 1, 1, -1, -1, 1, -1,
+// written as bit masks of the negative entries.
+__host__ __device__ constexpr int sign_x(int X) { return ((0x25 >> X) & 1) ? -1 : 1; }
+__host__ __device__ constexpr int sign_y(int X) { return ((0x2C >> X) & 1) ? -1 : 1; }
 // Kernel feeding output component c (0: Fx, 1: Fy) from field f (sigma,
-// dsdx, dsdy).
-__device__ __constant__ int kKernOf[2][3] = {{0, 1, 2}, {3, 5, 4}};
+// dsdx, dsdy): I0, Ixx, Ixy for Fx and J0, Jyx, Jyy for Fy.
+__host__ __device__ constexpr int kern_of(int c, int f) { return c == 0 ? f : 3 + (3 - f) % 3; }
 
-// Stored spectrum of kernel X at (kx, ky).
+// Kernel spectra and workspace planes live in global memory; their
+// addresses come from job descriptors, so the compiler cannot infer the
+// address space by itself (and would emit flat loads, which also hold up
+// every LDS wait).  Converted with C-style casts.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+// One complex value through a global pointer (a two-element vector load).
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cpx<T> ldg(gptr<cpx<T>> p, size_t i)
+{
+    const vec2<T> v = ((gptr<vec2<T>>)p)[i];
+    return cpx<T>{v.x, v.y};
+}
+
+// The eight values this thread needs (frequencies ky = lane + q M/8) of
+// stored kernel X at column kx.
 //  flip bit 2: a same-level kernel, symmetric under both mirrors, stored as
 //    one real R per frequency for ky in [0, M/2]: the spectrum is R when
 //    s_x s_y = +1 and i R otherwise, and S(kx, ky) = s_y S(kx, M - ky);
 //  otherwise a polyphase phase stored complex for all ky; bits 0 / 1 select
 //    its x- / y-mirror image: S'(kx, ky) = s_x conj S(kx, -ky),
 //    s_y S(kx, -ky), or s_x s_y conj S(kx, ky).
+// Branch-free apart from the layout test, which is uniform per slot.
 template <typename T, int M>
-__device__ __forceinline__ cpx<T> kern_at(const void* __restrict__ Kv, int X, int kx, int ky,
-                                          int flip)
+__device__ __forceinline__ void kern_column(cpx<T>* kv, const void* Kv, int X, int kx, int flip,
+                                            int lane)
 {
+    constexpr int TPS = M / 8, H = M / 2 + 1;
     if (flip & 4) {
-        constexpr int H = M / 2 + 1;
-        const T* R = reinterpret_cast<const T*>(Kv);
-        int k = ky;
-        T sg = 1;
-        if (ky > M / 2) {
-            k = M - ky;
-            sg = (T)kSignY[X];
+        gptr<T> R = (gptr<T>)Kv + ((size_t)X * H + kx) * H;
+        const T sy = (T)sign_y(X);
+        const bool imag = sign_x(X) * sign_y(X) < 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            T v;
+            if (q < 4) {
+                v = R[lane + q * TPS];                        // ky < M/2
+            } else {
+                const int ky = lane + q * TPS;                // ky >= M/2
+                v = R[M - ky];
+                if (q > 4 || lane > 0) v *= sy;               // ky = M/2 is stored directly
+            }
+            kv[q] = imag ? cpx<T>{0, v} : cpx<T>{v, 0};
         }
-        const T v = sg * R[((size_t)X * H + kx) * H + k];
-        return (kSignX[X] * kSignY[X] > 0) ? cpx<T>{v, 0} : cpx<T>{0, v};
+    } else {
+        gptr<cpx<T>> K = (gptr<cpx<T>>)Kv + ((size_t)X * H + kx) * M;
+        const bool rev = flip == 1 || flip == 2;
+        const T s = (T)(((flip & 1) ? sign_x(X) : 1) * ((flip & 2) ? sign_y(X) : 1));
+        const T si = (flip & 1) ? -s : s;  // x-mirrors conjugate
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ky = lane + q * TPS;
+            const cpx<T> z = ldg<T>(K, rev ? ((M - ky) & (M - 1)) : ky);
+            kv[q] = cpx<T>{s * z.re, si * z.im};
+        }
     }
-    const cpx<T>* K = reinterpret_cast<const cpx<T>*>(Kv);
-    const int kyy = (flip == 1 || flip == 2) ? ((M - ky) & (M - 1)) : ky;
-    cpx<T> s = K[((size_t)X * (M / 2 + 1) + kx) * M + kyy];
-    if (flip & 1) s.im = -s.im;
-    int sg = 1;
-    if (flip & 1) sg *= kSignX[X];
-    if (flip & 2) sg *= kSignY[X];
-    if (sg < 0) s = cpx<T>{-s.re, -s.im};
-    return s;
 }
 
-// ---------------------------------------------------------------------------
-// Pass 2: forward column FFTs of every input plane
-// ---------------------------------------------------------------------------
-// One slot per spectral column: the stored rows (zero elsewhere) are
-// transformed along the column and written as the column's M frequencies.
-
-template <typename T, int M>
-__global__ void __launch_bounds__(TD_MAX_THREADS) k_col_fwd(SegTable<ColFwdJob> segs,
-                                                            const cpx<T>* __restrict__ tw_g)
+// Index of a slot's current item, scalar when a slot is a whole wavefront
+// (M/8 >= 64): its descriptor then loads into scalar registers and every
+// branch on it is uniform.
+template <int M>
+__device__ __forceinline__ int slot_uniform(int i)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int TPS = M / 8;
-    constexpr int SP = lds_stride(M);
-    const int S = blockDim.x / TPS;
-    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* tw = A + S * SP;
-    stage_twiddles<T, M>(tw, tw_g);
-    int slot_unused;
-    const void* aux;
-    char* ws;
-    const ColFwdJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
-    const int slot = threadIdx.x / TPS, lane = threadIdx.x % TPS;
-    const bool col_ok = slot < J.ncol;
-    const int kx = J.kx0 + slot;
-    cpx<T>* a = A + slot * SP;
-    const cpx<T>* src = reinterpret_cast<const cpx<T>*>(ws + J.in) + (size_t)kx * J.ld;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int ky = lane + q * TPS, sr = ky - J.lr_first;
-        a[lds_pos(ky)] = (col_ok && sr >= 0 && sr < J.ld) ? src[sr] : cpx<T>{0, 0};
-    }
-    __syncthreads();
-    fft_lds<T, M, false>(A, tw);
-    if (col_ok) {
-        cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + J.out) + (size_t)kx * M;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) dst[lane + q * TPS] = a[lds_pos(lane + q * TPS)];
-    }
+    if constexpr (M / 8 >= 64) return __builtin_amdgcn_readfirstlane(i);
+    return i;
 }
 
 // ---------------------------------------------------------------------------
-// Pass 3: kernel-spectrum products summed over inputs, inverse column FFT
+// Pass 2: column FFTs fused with the kernel-spectrum products
 // ---------------------------------------------------------------------------
-// Slot (c, g) of a workgroup works on column kx0 + c for output
-// out0 + g / split, terms k, k + split, k + 2 split, ... (k = g % split):
-// every thread accumulates its eight frequencies over those terms (a
-// barrier-free stream of independent loads, the next term's descriptor
-// loaded ahead).  The split partial sums of an output are added in LDS into
-// its first slot, whose inverse column FFT then yields the output rows.
+// Slot (c, g) of a workgroup works on spectral column kx0 + c with its own
+// LDS sequence.  Every loop below runs the same number of iterations in all
+// slots of the workgroup (the FFTs synchronise the whole workgroup); slots
+// without work transform zeros.  Each thread owns frequencies
+// ky = lane + q M/8, q < 8, of its slot's sequence.
 
-struct MacTables {
-    const MacOut* outs;
-    const MacTerm* terms;
+struct ColTables {
+    const ColIn* ins;
+    const ColOut* outs;
 };
 
+// Stored rows of input plane I, column kx, into sequence a (zero elsewhere).
+// (Unconditional loads from a clamped row -- row 0 of the workspace for a
+// slot without an input -- then a select.)
 template <typename T, int M>
-__global__ void __launch_bounds__(TD_MAX_THREADS) k_col_mac(SegTable<ColMacJob> segs,
-                                                            const cpx<T>* __restrict__ tw_g, int G)
+__device__ __forceinline__ void load_column(cpx<T>* a, const char* ws, const ColIn& I, int kx,
+                                            bool ok, int lane)
+{
+    constexpr int TPS = M / 8;
+    gptr<cpx<T>> src = (gptr<cpx<T>>)(ws + (ok ? I.in + (int64_t)kx * I.ld * (int64_t)sizeof(cpx<T>) : 0));
+    const int last = ok ? I.ld - 1 : 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int sr = lane + q * TPS - I.lr_first;
+        const cpx<T> v = ldg<T>(src, min(max(sr, 0), last));
+        a[lds_pos(lane + q * TPS)] = (ok && sr >= 0 && sr <= last) ? v : cpx<T>{0, 0};
+    }
+}
+
+// Rows [out_lr_first, out_lr_first + out_ld) of the transformed sequence a.
+template <typename T, int M>
+__device__ __forceinline__ void store_column(const cpx<T>* a, char* ws, const ColOut& O, int kx,
+                                             int lane)
+{
+    constexpr int TPS = M / 8;
+    cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + O.out) + (size_t)kx * O.out_ld;
+    for (int sr = lane; sr < O.out_ld; sr += TPS) dst[sr] = a[lds_pos(O.out_lr_first + sr)];
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
+                                                        const cpx<T>* __restrict__ tw_g, int G)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TPS = M / 8;
@@ -306,67 +335,144 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col_mac(SegTable<ColMacJob> 
     int slot_unused;
     const void* aux;
     char* ws;
-    const ColMacJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
-    const MacTables tabs = *reinterpret_cast<const MacTables*>(aux);
-    const int slot = threadIdx.x / TPS, lane = threadIdx.x % TPS;
+    const ColJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
+    const ColTables tabs = *reinterpret_cast<const ColTables*>(aux);
+    const int slot = threadIdx.x / TPS, lane_c = threadIdx.x % TPS;
+    const int lane = lane_c;
     const int c = slot / G, g = slot % G;
-    const int o = g / J.split, k = g % J.split;
     const int kx = J.kx0 + c;
-    const bool act = c < J.ncol && o < J.nout;
+    const bool col_ok = c < J.ncol;
     cpx<T>* a = A + slot * SP;
-    cpx<T> acc[8];
+    cpx<T>* col0 = A + c * G * SP;  // the column's first slot
+    // Inside the loops the lane index is re-derived through an empty asm
+    // barrier, so that the per-frequency addresses are recomputed in each
+    // iteration instead of being hoisted and held in registers throughout.
+
+    if (J.kind == 0) {
+        cpx<T> ax[8], ay[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
-    MacOut O{0, 0, 0, 0, 0};
-    if (act) {
-        O = tabs.outs[J.out0 + o];
-        const MacTerm* __restrict__ tl = tabs.terms + O.term0;
-        int t = k;
-        MacTerm cur;
-        if (t < O.nterm) cur = tl[t];
-        while (t < O.nterm) {
-            const int tn = t + J.split;
-            MacTerm nxt = cur;
-            if (tn < O.nterm) nxt = tl[tn];
-            const cpx<T>* in = reinterpret_cast<const cpx<T>*>(ws + cur.in) + (size_t)kx * M;
-            cpx<T> vi[8], kv[8];
+        for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
+        for (int r0 = 0; r0 < J.nin; r0 += G) {
+            int lane = lane_c;
+            asm volatile("" : "+v"(lane));
+            const int i = slot_uniform<M>(r0 + g);
+            const bool ok = col_ok && i < J.nin;
+            ColIn I{0, nullptr, 0, 0, 0, 0};
+            if (ok) I = tabs.ins[J.in0 + i];
+            load_column<T, M>(a, ws, I, kx, ok, lane);
+            seq_sync<M>();
+            fft_lds<T, M, false>(A, tw);
+            if (ok) {
+                cpx<T> v[8], kv[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int ky = lane + q * TPS;
-                vi[q] = in[ky];
-                kv[q] = kern_at<T, M>(cur.kern, cur.X, kx, ky, cur.flip);
+                for (int q = 0; q < 8; ++q) v[q] = a[lds_pos(lane + q * TPS)];
+                kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) ax[q] = ax[q] + cmul(kv[q], v[q]);
+                kern_column<T, M>(kv, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) ay[q] = ay[q] + cmul(kv[q], v[q]);
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) acc[q] = acc[q] + cmul(kv[q], vi[q]);
-            cur = nxt;
-            t = tn;
+            // the next load writes only this thread's own positions
         }
-    }
+        // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
+        // (slot 0 as well when G == 1)
+        const int gy = G > 1 ? 1 : 0;
+        cpx<T> sx[8], sy[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = acc[q];
-    __syncthreads();
-    if (J.split > 1) {
-        // reduce the split partial sums into slot k = 0 of each output
-        if (act && k == 0) {
+        for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = ax[q];
+        __syncthreads();
+        if (g == 0) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int p = lds_pos(lane + q * TPS);
-                cpx<T> sum = acc[q];
-                for (int h = 1; h < J.split; ++h) sum = sum + A[(slot + h) * SP + p];
-                acc[q] = sum;
+                cpx<T> sum = col0[p];
+                for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
+                sx[q] = sum;
             }
         }
         __syncthreads();
-        if (act && k == 0) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = acc[q];
+        for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = ay[q];
+        __syncthreads();
+        if (g == gy) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = lds_pos(lane + q * TPS);
+                cpx<T> sum = col0[p];
+                for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
+                sy[q] = sum;
+            }
+        }
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = sx[q];
+        } else if (g == gy) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = sy[q];
+        }
+        __syncthreads();
+        fft_lds<T, M, true>(A, tw);
+        if (col_ok && g == 0) store_column<T, M>(a, ws, tabs.outs[J.out0], kx, lane);
+        if (col_ok && G > 1 && g == 1) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
+        if (G == 1) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = sy[q];
+            __syncthreads();
+            fft_lds<T, M, true>(A, tw);
+            if (col_ok) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
+        }
+        return;
+    }
+
+    // kind 1: transform the three inputs, keeping this thread's frequencies
+    // of all three in registers
+    cpx<T> vin[3][8];
+    for (int r0 = 0; r0 < 3; r0 += G) {
+        const int i = slot_uniform<M>(r0 + g);
+        const bool ok = col_ok && i < 3;
+        ColIn I{0, nullptr, 0, 0, 0, 0};
+        if (ok) I = tabs.ins[J.in0 + i];
+        load_column<T, M>(a, ws, I, kx, ok, lane);
+        seq_sync<M>();
+        fft_lds<T, M, false>(A, tw);
+        __syncthreads();  // every slot reads the three transformed inputs
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (f >= r0 && f < r0 + G) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos(lane + q * TPS)];
+            }
         }
         __syncthreads();
     }
-    fft_lds<T, M, true>(A, tw);
-    if (act && k == 0) {
-        cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + O.out) + (size_t)kx * O.out_ld;
-        for (int sr = lane; sr < O.out_ld; sr += TPS) dst[sr] = a[lds_pos(O.out_lr_first + sr)];
+    for (int o0 = 0; o0 < J.nout; o0 += G) {
+        int lane = lane_c;
+        asm volatile("" : "+v"(lane));
+        const int o = slot_uniform<M>(o0 + g);
+        const bool ok = col_ok && o < J.nout;
+        cpx<T> acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
+        ColOut O{0, nullptr, 0, 0, 0, 0};
+        if (ok) {
+            O = tabs.outs[J.out0 + o];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                cpx<T> kv[8];
+                kern_column<T, M>(kv, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] = acc[q] + cmul(kv[q], vin[f][q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = acc[q];
+        seq_sync<M>();
+        fft_lds<T, M, true>(A, tw);
+        if (ok) store_column<T, M>(a, ws, O, kx, lane);
+        seq_sync<M>();
     }
 }
 
@@ -454,6 +560,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
         }
         __syncthreads();
         fft_lds<T, M, true>(A, tw);
+        __syncthreads();  // outputs gather from every slot's sequence
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int idx = threadIdx.x + q * blockDim.x;
@@ -522,6 +629,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
     }
     __syncthreads();
     fft_lds<double, M, false>(buf, tw);
+    __syncthreads();  // the output loop reads every sequence
     const double sc = 1.0 / ((double)M * (double)M);
     for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
         const int c = i / M, ky = i % M;
@@ -531,7 +639,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
             out[((size_t)X * NCOL + kx0 + c) * M + ky] = cpx<TO>{(TO)(v.re * sc), (TO)(v.im * sc)};
         } else if (ky <= M / 2) {
             // same-level kernel: real (s_x s_y = +1) or imaginary spectrum
-            const double r = (kSignX[X] * kSignY[X] > 0) ? v.re : v.im;
+            const double r = (sign_x(X) * sign_y(X) > 0) ? v.re : v.im;
             outq[((size_t)X * NCOL + kx0 + c) * NCOL + ky] = (TO)(r * sc);
         }
     }
@@ -557,7 +665,7 @@ hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& s
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * (M / 8);
-    const size_t smem = lds_bytes(0, M, C, sizeof(cpx<T>));
+    const size_t smem = lds_bytes(M, C, sizeof(cpx<T>));
     SegTable<RowFwdJob> s = segs;
     const void* const* p = ptrs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
@@ -571,36 +679,18 @@ hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& s
 }
 
 template <typename T>
-hipError_t launch_col_fwd(int M, int C, int blocks, const SegTable<ColFwdJob>& segs, const void* tw,
-                          hipStream_t st)
-{
-    if (blocks <= 0) return hipSuccess;
-    const int threads = C * (M / 8);
-    const size_t smem = lds_bytes(1, M, C, sizeof(cpx<T>));
-    SegTable<ColFwdJob> s = segs;
-    const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
-    void* args[] = {&s, &t};
-    switch (M) {
-#define X(MM) case MM: return launch_common(k_col_fwd<T, MM>, blocks, threads, smem, st, args);
-        TD_FOR_EACH_M(X)
-#undef X
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename T>
-hipError_t launch_col_mac(int M, int C, int G, int blocks, const SegTable<ColMacJob>& segs,
-                          const void* tw, hipStream_t st)
+hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& segs,
+                      const void* tw, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * G * (M / 8);
-    const size_t smem = lds_bytes(2, M, C, sizeof(cpx<T>), G);
-    SegTable<ColMacJob> s = segs;
+    const size_t smem = lds_bytes(M, C, sizeof(cpx<T>), G);
+    SegTable<ColJob> s = segs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
     int g = G;
     void* args[] = {&s, &t, &g};
     switch (M) {
-#define X(MM) case MM: return launch_common(k_col_mac<T, MM>, blocks, threads, smem, st, args);
+#define X(MM) case MM: return launch_common(k_col<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -613,7 +703,7 @@ hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInv
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * G * (M / 8);
-    const size_t smem = lds_bytes(3, M, C, sizeof(cpx<T>), G);
+    const size_t smem = lds_bytes(M, C, sizeof(cpx<T>), G);
     SegTable<RowInvJob> s = segs;
     void* const* p = ptrs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
@@ -661,14 +751,10 @@ template hipError_t launch_row_fwd<float>(int, int, int, const SegTable<RowFwdJo
                                           const void* const*, const void*, hipStream_t);
 template hipError_t launch_row_fwd<double>(int, int, int, const SegTable<RowFwdJob>&,
                                            const void* const*, const void*, hipStream_t);
-template hipError_t launch_col_fwd<float>(int, int, int, const SegTable<ColFwdJob>&, const void*,
-                                          hipStream_t);
-template hipError_t launch_col_fwd<double>(int, int, int, const SegTable<ColFwdJob>&, const void*,
-                                           hipStream_t);
-template hipError_t launch_col_mac<float>(int, int, int, int, const SegTable<ColMacJob>&,
-                                          const void*, hipStream_t);
-template hipError_t launch_col_mac<double>(int, int, int, int, const SegTable<ColMacJob>&,
-                                           const void*, hipStream_t);
+template hipError_t launch_col<float>(int, int, int, int, const SegTable<ColJob>&, const void*,
+                                      hipStream_t);
+template hipError_t launch_col<double>(int, int, int, int, const SegTable<ColJob>&, const void*,
+                                       hipStream_t);
 template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
                                           void* const*, const void*, hipStream_t);
 template hipError_t launch_row_inv<double>(int, int, int, int, const SegTable<RowInvJob>&,
@@ -686,8 +772,7 @@ hipError_t prepare_kernels()
     hipError_t e = hipSuccess;
 #define SETA(k) if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 #define X(MM) SETA((k_row_fwd<float, MM>)) SETA((k_row_fwd<double, MM>)) \
-    SETA((k_col_fwd<float, MM>)) SETA((k_col_fwd<double, MM>)) \
-    SETA((k_col_mac<float, MM>)) SETA((k_col_mac<double, MM>)) \
+    SETA((k_col<float, MM>)) SETA((k_col<double, MM>)) \
     SETA((k_row_inv<float, MM>)) SETA((k_row_inv<double, MM>)) \
     SETA((k_spec_col<float, MM>)) SETA((k_spec_col<double, MM>))
     TD_FOR_EACH_M(X)

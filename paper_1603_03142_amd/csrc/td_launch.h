@@ -9,8 +9,8 @@ namespace td {
 
 // A launch processes the concatenated job lists of up to TD_MAX_SEGS plans
 // (one workgroup per job).  Each segment carries the pointer-table slot base
-// of its solve and an auxiliary per-plan array (terms, scatter outputs or
-// row contributions).  Passed by value as a kernel argument.
+// of its solve and an auxiliary per-plan table (column inputs and outputs,
+// or row contributions).  Passed by value as a kernel argument.
 #define TD_MAX_SEGS 40
 
 template <typename Job>
@@ -42,11 +42,8 @@ template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
                           const void* const* ptrs, const void* tw, hipStream_t st);
 template <typename T>
-hipError_t launch_col_fwd(int M, int C, int blocks, const SegTable<ColFwdJob>& segs, const void* tw,
-                          hipStream_t st);
-template <typename T>
-hipError_t launch_col_mac(int M, int C, int G, int blocks, const SegTable<ColMacJob>& segs,
-                          const void* tw, hipStream_t st);
+hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& segs,
+                      const void* tw, hipStream_t st);
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
                           void* const* ptrs, const void* tw, hipStream_t st);
@@ -67,10 +64,10 @@ hipError_t prepare_kernels();
 // the kernels' static LDS.
 #define TD_MAX_DYN_LDS (160u * 1024u - 512u)
 
-// Dynamic LDS of one workgroup of each pass: C sequences (row passes,
-// col_fwd) or C columns / rows x G slots, each padded to lds_stride(M), plus
-// the twiddle table (M entries).
-inline size_t lds_bytes(int pass, int M, int C, size_t elem, int G = 1)
+// Dynamic LDS of one workgroup of each pass: C sequences (row_fwd) or C
+// columns / rows x G slots, each padded to lds_stride(M), plus the twiddle
+// table (M entries).
+inline size_t lds_bytes(int M, int C, size_t elem, int G = 1)
 {
     const size_t SP = (size_t)M + M / 8;
     return ((size_t)C * G * SP + M) * elem;

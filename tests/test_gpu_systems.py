@@ -218,7 +218,7 @@ def test_autotuned_plans_keep_parity(tmp_path):
     c = td.Context(0)
     db = str(tmp_path / "tune.jsonl")
     c.autotune("f64", 128, db)
-    assert open(db).read().count('"pass"') >= 4
+    assert open(db).read().count('"pass"') >= 3
     hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / 40, 2, [(40, 0, 0), (32, 20, 12)])
     sig, dx, dy = rand_fields(hier, 9)
     ox, oy = oracle.forces(hier, sig, dx, dy)
@@ -245,9 +245,9 @@ def test_timing_and_traffic(ctx):
     torch.cuda.synchronize()
     t = ctx.timing_read()
     ctx.timing(False)
-    for p in ("row_fwd", "col_fwd", "col_mac", "row_inv"):
+    for p in ("row_fwd", "col", "row_inv"):
         assert t[p][1] == 3 and t[p][0] > 0
     tr = plan.traffic()
-    assert all(tr[p] > 0 for p in ("row_fwd", "col_fwd", "col_mac", "row_inv"))
+    assert all(tr[p] > 0 for p in ("row_fwd", "col", "row_inv"))
     ws, spec = plan.footprint()
     assert ws > 0 and spec > 0
