@@ -693,7 +693,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
         }
         // (b) Case-3 phases of this (coarser) level onto every finer target:
         // the level's three own planes (the first inputs above) are
-        // transformed again by every job; a job forms up to 4 G outputs
+        // transformed again by every job; a job forms up to 16 G outputs
         for (int s = t + 1; s < L; ++s) {
             const LevelG& T = P->lv[s];
             const int m = ipow(r, s - t), ld = c3_ld[t][s];
@@ -713,7 +713,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                                          floor_div(T.oy, m) - G.oy, comp, flip});
             }
             const int nout = (int)g.colouts.size() - out0;
-            const int chunk = 4 * Gs;
+            const int chunk = 16 * Gs;
             for (int kx0 = 0; kx0 < (int)H; kx0 += C)
                 for (int o0 = 0; o0 < nout; o0 += chunk)
                     g.col.push_back({1, kx0, std::min(C, (int)H - kx0), in0, 3, out0 + o0,
@@ -733,6 +733,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             c.phase_stride = 0;
             c.comp_stride = (int64_t)(T.M / 2 + 1) * T.n;
             c.m = 1;
+            c.mshift = 0;
             c.ld = T.n;
             c.lr_first = 0;
             c.ox_s = T.ox;
@@ -748,6 +749,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             c.phase_stride = (int64_t)2 * (S.M / 2 + 1) * ld;
             c.comp_stride = (int64_t)(S.M / 2 + 1) * ld;
             c.m = m;
+            c.mshift = ilog2(m);
             c.ld = ld;
             c.lr_first = floor_div(T.oy, m) - S.oy;
             c.ox_s = S.ox;
@@ -874,8 +876,10 @@ td_status validate_jobs(td_plan* P)
                 if (j.x0 < 0 || j.nx < 1 || j.x0 + j.nx > j.n_t || (long)j.nx > 2L * M)
                     return bad("rinv columns");
                 if (j.c0 < 0 || j.c0 + j.nc > (int)g.contribs.size()) return bad("rinv contribs");
+                if (j.oy_t < 0 || j.ox_t < 0) return bad("rinv offsets");
                 for (int k = 0; k < j.nc; ++k) {
                     const RowInvContrib& c = g.contribs[j.c0 + k];
+                    if (c.m < 1 || c.m > 16 || (1 << c.mshift) != c.m) return bad("rinv ratio");
                     // rows and columns reached by this job's targets
                     for (int rr : {j.y0, j.y0 + j.ny - 1}) {
                         const int gg = j.oy_t + rr, Jc = floor_div(gg, c.m);

@@ -82,7 +82,7 @@ struct RowInvContrib {
     int32_t ld;
     int32_t lr_first;      // lattice row of stored row 0
     int32_t ox_s, oy_s;    // lattice origin: offsets of the lattice's level
-    int32_t pad;
+    int32_t mshift;        // log2(m)
 };
 
 struct RowInvJob {

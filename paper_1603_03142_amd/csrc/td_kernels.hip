@@ -486,10 +486,25 @@ __device__ __forceinline__ int floor_div(int a, int b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+// Workgroups are dispatched to the eight XCDs round-robin, and each XCD has
+// its own L2.  Renumbering them so that runs of K consecutive jobs go to one
+// XCD keeps neighbouring target rows -- which read the same cache lines of
+// the transposed spectra (K rows of 8 bytes fill a 128-byte line) -- in one
+// L2, while the runs still rotate over the XCDs for load balance.
+__device__ __forceinline__ int xcd_block(int bid, int nblk)
+{
+    constexpr int NXCD = 8, K = 16;
+    const int full = nblk - nblk % (NXCD * K);
+    if (bid >= full) return bid;
+    const int x = bid % NXCD, l = bid / NXCD;
+    return (x + NXCD * (l / K)) * K + l % K;
+}
+
 // A workgroup owns C target rows; each row's items -- (contribution, x-phase)
 // pairs, one complex-to-real row transform each -- run G at a time in the
 // row's G slots.  Spectra are read transposed ([kx][row]), rows fastest.
-// Every thread accumulates the outputs it owns in registers.
+// The G M/8 threads of a row own its target columns x0 + t + k G M/8 and
+// accumulate them in registers over all items.
 template <typename T, int M>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> segs,
                                                   void* const* __restrict__ ptrs,
@@ -501,55 +516,58 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     constexpr int SP = lds_stride(M);
     const int S = blockDim.x / TPS;
     const int C = S / G;  // rows of this workgroup
+    const int GT = G * TPS;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* tw = A + S * SP;
-    __shared__ int it_m[16], it_kxp[16], it_oxs[16];
+    // per slot of the current round: contribution (-1: none), x-phase, and
+    // the contribution's ratio shift, origin column and plane base
+    __shared__ int it_c[16], it_kxp[16], it_sh[16], it_oxs[16];
     stage_twiddles<T, M>(tw, tw_g);
     int slot_base;
     const void* aux;
     char* ws;
-    const RowInvJob J = segs.find(blockIdx.x, &slot_base, &aux, &ws);
-    const RowInvContrib* __restrict__ contribs = reinterpret_cast<const RowInvContrib*>(aux);
+    const RowInvJob J = segs.find(xcd_block(blockIdx.x, gridDim.x), &slot_base, &aux, &ws);
+    const RowInvContrib* __restrict__ contribs = reinterpret_cast<const RowInvContrib*>(aux) + J.c0;
     int nitems = 0;
-    for (int k = 0; k < J.nc; ++k) nitems += contribs[J.c0 + k].m;
-    constexpr int NQ = 16;  // outputs per thread: C*nx <= C*2M = 16 * (C*M/8)
+    for (int k = 0; k < J.nc; ++k) nitems += 1 << contribs[k].mshift;
+    constexpr int NQ = 16;  // nx <= 2M = 16 M/8 <= 16 G M/8
+    const int crow = threadIdx.x / GT, t = threadIdx.x % GT;
     T accx[NQ], accy[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) { accx[q] = 0; accy[q] = 0; }
-    const int nout = J.ny * J.nx;
     for (int r0 = 0; r0 < nitems; r0 += G) {
-        // item descriptors of this round (identical for every row)
         if (threadIdx.x < G) {
             const int it = r0 + threadIdx.x;
-            int m = 1, kxp = -1, oxs = 0;
+            int c = -1, kxp = 0, sh = 0, oxs = 0;
             if (it < nitems) {
                 int k = 0, rem = it;
-                while (rem >= contribs[J.c0 + k].m) rem -= contribs[J.c0 + k].m, ++k;
-                m = contribs[J.c0 + k].m;
+                while (rem >= (1 << contribs[k].mshift)) rem -= 1 << contribs[k].mshift, ++k;
+                c = k;
                 kxp = rem;
-                oxs = contribs[J.c0 + k].ox_s;
+                sh = contribs[k].mshift;
+                oxs = contribs[k].ox_s;
             }
-            it_m[threadIdx.x] = m;
+            it_c[threadIdx.x] = c;
             it_kxp[threadIdx.x] = kxp;
+            it_sh[threadIdx.x] = sh;
             it_oxs[threadIdx.x] = oxs;
         }
+        __syncthreads();
         // load: element e -> (slot g, frequency kx, row c), rows fastest
         for (int e = threadIdx.x; e < G * H * C; e += blockDim.x) {
             const int cc = e % C, kx = (e / C) % H, gg = e / (C * H);
-            const int it = r0 + gg;
+            const int ci = it_c[gg];
             cpx<T> z{0, 0}, zr{0, 0};
-            if (it < nitems && cc < J.ny) {
-                int k = 0, rem = it;
-                while (rem >= contribs[J.c0 + k].m) rem -= contribs[J.c0 + k].m, ++k;
-                const RowInvContrib& Q = contribs[J.c0 + k];
-                const int gy = J.oy_t + J.y0 + cc;
-                const int Jc = floor_div(gy, Q.m);
-                const int kyp = gy - Jc * Q.m;
+            if (ci >= 0 && cc < J.ny) {
+                const RowInvContrib& Q = contribs[ci];
+                const int sh = Q.mshift;
+                const int gy = J.oy_t + J.y0 + cc;  // >= 0
+                const int Jc = gy >> sh, kyp = gy & ((1 << sh) - 1);
                 const int sr = Jc - Q.oy_s - Q.lr_first;
-                const cpx<T>* P = reinterpret_cast<const cpx<T>*>(ws + Q.base) +
-                                  (size_t)(kyp * Q.m + rem) * Q.phase_stride;
-                cpx<T> X = P[(size_t)kx * Q.ld + sr];
-                cpx<T> Y = P[Q.comp_stride + (size_t)kx * Q.ld + sr];
+                gptr<cpx<T>> P = (gptr<cpx<T>>)(ws + Q.base) +
+                                 (int64_t)((kyp << sh) + it_kxp[gg]) * Q.phase_stride;
+                cpx<T> X = ldg<T>(P, (size_t)kx * Q.ld + sr);
+                cpx<T> Y = ldg<T>(P, Q.comp_stride + (size_t)kx * Q.ld + sr);
                 if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
                 z = cpx<T>{X.re - Y.im, X.im + Y.re};
                 zr = cpx<T>{X.re + Y.im, Y.re - X.im};
@@ -560,33 +578,34 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
         }
         __syncthreads();
         fft_lds<T, M, true>(A, tw);
-        __syncthreads();  // outputs gather from every slot's sequence
+        __syncthreads();  // outputs gather from every slot of their row
+        for (int gg = 0; gg < G; ++gg) {
+            if (it_c[gg] < 0) break;
+            const int sh = it_sh[gg], kxp = it_kxp[gg], oxs = it_oxs[gg];
+            const cpx<T>* rowv = A + (crow * G + gg) * SP;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int idx = threadIdx.x + q * blockDim.x;
-            if (idx >= nout) continue;
-            const int r = idx / J.nx, ii = J.x0 + idx % J.nx;
-            const int gx = J.ox_t + ii;
-            for (int gg = 0; gg < G; ++gg) {
-                const int m = it_m[gg], kxp = it_kxp[gg];
-                if (kxp < 0) break;
-                const int Ic = floor_div(gx, m);
-                if (gx - Ic * m != kxp) continue;
-                const cpx<T> v = A[(r * G + gg) * SP + lds_pos(Ic - it_oxs[gg])];
+            for (int q = 0; q < NQ; ++q) {
+                const int ii = t + q * GT;
+                if (ii >= J.nx) break;
+                const int gx = J.ox_t + J.x0 + ii;  // >= 0
+                if ((gx & ((1 << sh) - 1)) != kxp) continue;
+                const cpx<T> v = rowv[lds_pos((gx >> sh) - oxs)];
                 accx[q] += v.re;
                 accy[q] += v.im;
             }
         }
         __syncthreads();
     }
-    T* fx = reinterpret_cast<T*>(ptrs[slot_base + J.out_slot]);
-    T* fy = reinterpret_cast<T*>(ptrs[slot_base + J.out_slot + 1]);
+    typedef __attribute__((address_space(1))) T* gout;
+    gout fx = (gout)ptrs[slot_base + J.out_slot];
+    gout fy = (gout)ptrs[slot_base + J.out_slot + 1];
+    const int row = J.y0 + crow;
+    if (crow >= J.ny) return;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
-        if (idx >= nout) continue;
-        const int r = idx / J.nx, ii = J.x0 + idx % J.nx;
-        const int row = J.y0 + r;
+        const int ii0 = t + q * GT;
+        if (ii0 >= J.nx) break;
+        const int ii = J.x0 + ii0;
         const bool cov = ii >= J.cov_i0 && ii < J.cov_i1 && row >= J.cov_j0 && row < J.cov_j1;
         const size_t o = (size_t)row * J.n_t + ii;
         if (!J.accumulate) {
