@@ -144,7 +144,10 @@ td_status td_plan_footprint(const td_plan* plan, size_t* workspace_bytes,
                             size_t* spectra_bytes);
 td_status td_plan_destroy(td_plan* plan);
 
-/* Enqueue one solve on `hip_stream` (a hipStream_t, or NULL). */
+/* Enqueue one solve on `hip_stream` (a hipStream_t, or NULL).  The field
+ * pointers travel in the kernel arguments: nothing is copied to the device
+ * per solve, and a solve captured into a graph replays on the captured
+ * pointers. */
 td_status td_solve(const td_request* req, void* hip_stream);
 
 /* ---------------------------------------------------------------- batches */
@@ -213,12 +216,15 @@ td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m, i
 /* The timed launch kinds of a solve, in launch order. */
 #define TD_NPASS 4   /* row_fwd, col, row_inv, row_inv_accumulate */
 
-/* Per-pass timing.  While enabled, every solve enqueued outside graph
- * capture records a HIP event pair around each pass on the solve's stream.
+/* Per-pass timing.  `pass_mask` selects the launch kinds to time (bit p =
+ * kind p in TD_NPASS order; TD_TIMING_ALL for every kind, 0 to stop).
+ * While enabled, every solve enqueued outside graph capture records a HIP
+ * event pair around each selected kind on the solve's stream.
  * td_timing_read waits for the recorded events, writes the summed
- * milliseconds and the number of timed pass launches per pass (arrays of
+ * milliseconds and the number of timed launches per kind (arrays of
  * TD_NPASS, either may be NULL) since the previous read, and clears them. */
-td_status td_timing_enable(td_context* ctx, int enable);
+#define TD_TIMING_ALL ((1 << TD_NPASS) - 1)
+td_status td_timing_enable(td_context* ctx, int pass_mask);
 td_status td_timing_read(td_context* ctx, double* ms, int64_t* launches);
 
 /* Algorithmic HBM bytes one solve of the plan moves in each pass (array of

@@ -93,8 +93,13 @@ class Context:
 
     PASSES = ("row_fwd", "col", "row_inv", "row_inv_acc")
 
-    def timing(self, enable: bool = True):
-        B.check(lib().td_timing_enable(self.handle, 1 if enable else 0), "td_timing_enable")
+    def timing(self, enable: bool = True, passes=None):
+        """Time every launch kind (or only those named in `passes`)."""
+        mask = 0
+        if enable:
+            mask = (1 << len(self.PASSES)) - 1 if passes is None else \
+                sum(1 << self.PASSES.index(p) for p in passes)
+        B.check(lib().td_timing_enable(self.handle, mask), "td_timing_enable")
 
     def timing_read(self):
         """{pass: (milliseconds, launches)} since the previous read."""

@@ -134,6 +134,7 @@ struct td_context {
     std::vector<void*> allocs;
     // per-pass timing (diagnostics)
     bool timing = false;
+    int timing_mask = 0;  // launch kinds timed (bit per kind)
     struct Timed { int pass; hipEvent_t a, b; };
     std::vector<Timed> timed;
     std::vector<hipEvent_t> ev_pool;
@@ -322,7 +323,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
         if (he == hipSuccess)
             he = launch_row_fwd<double>(M, C, (int)jobs.size(),
                                         single_seg<RowFwdJob>(djobs, (int)jobs.size(), 0, nullptr, (char*)rows),
-                                        (const void* const*)dptr, tw64, ctx->stream);
+                                        (const void* const*)dptr, FieldPtrs{}, tw64, ctx->stream);
         const int Cs = std::max(1, std::min(shape_C(default_shape(P_ROWINV, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
         void* dst = (char*)e.ptr + (size_t)p * per_phase * elem_size(dt);
         if (he == hipSuccess)
@@ -462,13 +463,6 @@ struct td_plan {
     size_t spectra_bytes = 0;  // resident spectra this plan reads
     size_t job_bytes = 0;
     std::vector<std::pair<void*, size_t>> dev_allocs;
-    // per-solve pointer table
-    void** d_ptrs = nullptr;
-    static const int RING = 8;
-    void** h_stage[RING] = {};
-    hipEvent_t stage_ev[RING] = {};
-    bool stage_used[RING] = {};
-    int stage_next = 0;
     uint64_t id = 0;
 };
 
@@ -973,14 +967,6 @@ void plan_free(td_plan* P)
     P->dev_allocs.clear();
     if (P->ws) ctx->release(P->ws, P->ws_bytes);
     P->ws = nullptr;
-    if (P->d_ptrs) ctx->release(P->d_ptrs, sizeof(void*) * 5 * P->nlevels);
-    P->d_ptrs = nullptr;
-    for (int k = 0; k < td_plan::RING; ++k) {
-        if (P->stage_ev[k]) (void)hipEventDestroy(P->stage_ev[k]);
-        if (P->h_stage[k]) (void)hipHostFree(P->h_stage[k]);
-        P->stage_ev[k] = nullptr;
-        P->h_stage[k] = nullptr;
-    }
 }
 
 // Copy a pointer table to the device through a ring of pinned staging
@@ -1061,7 +1047,7 @@ void push_seg(std::vector<SegTable<Job>>& tabs, std::vector<int>& totals, const 
 
 // One launch per (pass, M, <= TD_MAX_SEGS members), in pass order.
 td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>& mem,
-                         void* const* d_ptrs, hipStream_t st)
+                         void* const* d_ptrs, const FieldPtrs& fp, hipStream_t st)
 {
     std::vector<int> Ms;
     for (auto& m : mem)
@@ -1090,7 +1076,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                                 : g.rinv[pass == P_ROWINV ? 0 : 1].size();
                 any |= nj > 0;
             }
-        if (timed && any) {
+        if (timed && any && (ctx->timing_mask >> pass) & 1) {
             std::lock_guard<std::recursive_mutex> lk(ctx->mu);
             ev_a = ctx->get_event();
             ev_b = ctx->get_event();
@@ -1117,8 +1103,8 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                         push_seg(t, n, gs.first->d_rowfwd, (int)gs.first->rowfwd.size(), gs.second->slot_base,
                                  nullptr, gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st)
-                                : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, tw, st);
+                        e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, st)
+                                : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, st);
                 } else if (pass == P_COL) {
                     std::vector<SegTable<ColJob>> t;
                     std::vector<int> n;
@@ -1137,8 +1123,8 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                                  gs.second->slot_base, (const void*)gs.first->d_contribs,
                                  gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, tw, st)
-                                : launch_row_inv<float>(M, C, Gs, n[i], t[i], d_ptrs, tw, st);
+                        e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st)
+                                : launch_row_inv<float>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st);
                 }
                 if (e != hipSuccess)
                     return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
@@ -1245,12 +1231,6 @@ extern "C" td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_d
     P->ws_bytes = elems * elem_size(dt);
     if (st == TD_OK) st = validate_jobs(P.get());
     if (st == TD_OK) st = plan_upload(P.get());
-    if (st == TD_OK) st = ctx->alloc(sizeof(void*) * 5 * P->nlevels, (void**)&P->d_ptrs);
-    for (int k = 0; st == TD_OK && k < td_plan::RING; ++k) {
-        hipError_t e = hipHostMalloc((void**)&P->h_stage[k], sizeof(void*) * 5 * P->nlevels);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&P->stage_ev[k], hipEventDisableTiming);
-        if (e != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(e));
-    }
     if (st != TD_OK) {
         plan_free(P.get());
         return st;
@@ -1300,7 +1280,7 @@ extern "C" td_status td_plan_check(const td_hierarchy* h, td_dtype dt, size_t* w
 extern "C" td_status td_plan_footprint(const td_plan* p, size_t* ws, size_t* spec)
 {
     if (!p) return fail(TD_EINVAL, "NULL plan");
-    if (ws) *ws = p->ws_bytes + p->job_bytes + sizeof(void*) * 5 * p->nlevels;
+    if (ws) *ws = p->ws_bytes + p->job_bytes;
     if (spec) *spec = p->spectra_bytes;
     return TD_OK;
 }
@@ -1309,8 +1289,6 @@ extern "C" td_status td_plan_destroy(td_plan* p)
 {
     if (!p) return fail(TD_EINVAL, "NULL plan");
     DeviceGuard g(p->ctx->device);
-    for (int k = 0; k < td_plan::RING; ++k)
-        if (p->stage_used[k]) (void)hipEventSynchronize(p->stage_ev[k]);
     plan_free(p);
     delete p;
     return TD_OK;
@@ -1325,16 +1303,13 @@ extern "C" td_status td_solve(const td_request* req, void* stream)
     std::vector<void*> v(5 * P->nlevels, nullptr);
     TD_TRY(fill_ptrs(*req, P->nlevels, v, 0));
     if (!P->ws) TD_TRY(P->ctx->alloc(P->ws_bytes, &P->ws));
-    const int k = P->stage_next;
-    P->stage_next = (k + 1) % td_plan::RING;
-    if (P->stage_used[k]) TD_HIP(hipEventSynchronize(P->stage_ev[k]));
-    memcpy(P->h_stage[k], v.data(), sizeof(void*) * v.size());
-    TD_HIP(hipMemcpyAsync(P->d_ptrs, P->h_stage[k], sizeof(void*) * v.size(),
-                          hipMemcpyHostToDevice, st));
-    TD_HIP(hipEventRecord(P->stage_ev[k], st));
-    P->stage_used[k] = true;
+    // one solve: the field pointers travel in the kernel arguments
+    static_assert(5 * TD_MAX_LEVELS <= TD_KARG_PTRS, "kernel-argument pointer table too small");
+    FieldPtrs fp{};
+    fp.n = (int32_t)v.size();
+    for (size_t i = 0; i < v.size(); ++i) fp.p[i] = v[i];
     std::vector<Member> mem{{P, 0, (char*)P->ws}};
-    return launch_members(P->ctx, P->dt, mem, P->d_ptrs, st);
+    return launch_members(P->ctx, P->dt, mem, nullptr, fp, st);
 }
 
 // ===========================================================================
@@ -1411,7 +1386,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
                 TD_TRY(twiddles(B->ctx, g.M, B->dt, &tw));
             }
         TD_HIP(hipStreamBeginCapture(B->graph_stream, hipStreamCaptureModeThreadLocal));
-        td_status s = launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, B->graph_stream);
+        td_status s = launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, B->graph_stream);
         hipGraph_t gph = nullptr;
         hipError_t e = hipStreamEndCapture(B->graph_stream, &gph);
         if (s != TD_OK) {
@@ -1423,7 +1398,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
         TD_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     }
     TD_TRY(B->stager.push(B->d_ptrs, v, st));
-    if (!use_graph) return launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, st);
+    if (!use_graph) return launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, st);
     TD_HIP(hipGraphLaunch(B->exec, st));
     return TD_OK;
 }
@@ -1613,7 +1588,7 @@ void server_loop(td_server* S)
                 const td_dtype dt = mem[0].plan->dt;
                 lk.unlock();
                 if (st == TD_OK) st = slot->stager.push(slot->d_ptrs, v, slot->stream);
-                if (st == TD_OK) st = launch_members(S->ctx, dt, mem, slot->d_ptrs, slot->stream);
+                if (st == TD_OK) st = launch_members(S->ctx, dt, mem, slot->d_ptrs, FieldPtrs{}, slot->stream);
                 if (st == TD_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess)
                     st = fail(TD_EDEVICE, "event record");
                 lk.lock();
@@ -1927,7 +1902,8 @@ extern "C" td_status td_timing_enable(td_context* ctx, int enable)
 {
     if (!ctx) return fail(TD_EINVAL, "NULL context");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    ctx->timing = enable != 0;
+    ctx->timing = (enable & ((1 << NTIMED) - 1)) != 0;
+    ctx->timing_mask = enable & ((1 << NTIMED) - 1);
     return TD_OK;
 }
 

@@ -148,6 +148,7 @@ __device__ __forceinline__ T fetch_src(const T* __restrict__ src, const RowFwdJo
 template <typename T, int M>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> segs,
                                                   const void* const* __restrict__ ptrs,
+                                                  const FieldPtrs fp,
                                                   const cpx<T>* __restrict__ tw_g)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -160,7 +161,8 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     constexpr int SP = lds_stride(M);
     cpx<T>* tw = buf + C * SP;
     stage_twiddles<T, M>(tw, tw_g);
-    const T* src = reinterpret_cast<const T*>(ptrs[slot_base + J.src_slot]);
+    const int slot = slot_base + J.src_slot;
+    const T* src = reinterpret_cast<const T*>(fp.n ? fp.p[slot] : ptrs[slot]);
     const int rend = J.row0 + J.nrow;
     for (int idx = threadIdx.x; idx < C * M; idx += blockDim.x) {
         const int p = idx / M, lc = idx % M;
@@ -508,6 +510,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk)
 template <typename T, int M>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> segs,
                                                   void* const* __restrict__ ptrs,
+                                                  const FieldPtrs fp,
                                                   const cpx<T>* __restrict__ tw_g, int G)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -597,8 +600,9 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
         __syncthreads();
     }
     typedef __attribute__((address_space(1))) T* gout;
-    gout fx = (gout)ptrs[slot_base + J.out_slot];
-    gout fy = (gout)ptrs[slot_base + J.out_slot + 1];
+    const int slot = slot_base + J.out_slot;
+    gout fx = (gout)(fp.n ? fp.p[slot] : ptrs[slot]);
+    gout fy = (gout)(fp.n ? fp.p[slot + 1] : ptrs[slot + 1]);
     const int row = J.y0 + crow;
     if (crow >= J.ny) return;
 #pragma unroll
@@ -680,15 +684,17 @@ static hipError_t launch_common(KF kf, int blocks, int threads, size_t smem, hip
 
 template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
-                          const void* const* ptrs, const void* tw, hipStream_t st)
+                          const void* const* ptrs, const FieldPtrs& fp, const void* tw,
+                          hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * (M / 8);
     const size_t smem = lds_bytes(M, C, sizeof(cpx<T>));
     SegTable<RowFwdJob> s = segs;
     const void* const* p = ptrs;
+    FieldPtrs f = fp;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
-    void* args[] = {&s, &p, &t};
+    void* args[] = {&s, &p, &f, &t};
     switch (M) {
 #define X(MM) case MM: return launch_common(k_row_fwd<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
@@ -718,16 +724,17 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
 
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
-                          void* const* ptrs, const void* tw, hipStream_t st)
+                          void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * G * (M / 8);
     const size_t smem = lds_bytes(M, C, sizeof(cpx<T>), G);
     SegTable<RowInvJob> s = segs;
     void* const* p = ptrs;
+    FieldPtrs f = fp;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
     int g = G;
-    void* args[] = {&s, &p, &t, &g};
+    void* args[] = {&s, &p, &f, &t, &g};
     switch (M) {
 #define X(MM) case MM: return launch_common(k_row_inv<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
@@ -767,17 +774,19 @@ hipError_t launch_table(const TableJob& job, hipStream_t st)
 }
 
 template hipError_t launch_row_fwd<float>(int, int, int, const SegTable<RowFwdJob>&,
-                                          const void* const*, const void*, hipStream_t);
+                                          const void* const*, const FieldPtrs&, const void*,
+                                          hipStream_t);
 template hipError_t launch_row_fwd<double>(int, int, int, const SegTable<RowFwdJob>&,
-                                           const void* const*, const void*, hipStream_t);
+                                           const void* const*, const FieldPtrs&, const void*,
+                                           hipStream_t);
 template hipError_t launch_col<float>(int, int, int, int, const SegTable<ColJob>&, const void*,
                                       hipStream_t);
 template hipError_t launch_col<double>(int, int, int, int, const SegTable<ColJob>&, const void*,
                                        hipStream_t);
 template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
-                                          void* const*, const void*, hipStream_t);
+                                          void* const*, const FieldPtrs&, const void*, hipStream_t);
 template hipError_t launch_row_inv<double>(int, int, int, int, const SegTable<RowInvJob>&,
-                                           void* const*, const void*, hipStream_t);
+                                           void* const*, const FieldPtrs&, const void*, hipStream_t);
 template hipError_t launch_spec_col<float>(int, int, const void*, void*, const void*, int,
                                            hipStream_t);
 template hipError_t launch_spec_col<double>(int, int, const void*, void*, const void*, int,

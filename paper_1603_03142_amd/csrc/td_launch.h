@@ -38,15 +38,26 @@ struct SegTable {
     }
 };
 
+// Field pointers of a launch: by value in the kernel arguments (n > 0, one
+// solve of up to TD_MAX_LEVELS levels: 5 per level -- sigma, dsdx, dsdy, fx,
+// fy) or, for batches, in a device table (n == 0).
+#define TD_KARG_PTRS 40
+struct FieldPtrs {
+    int32_t n;
+    int32_t pad;
+    void* p[TD_KARG_PTRS];
+};
+
 template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
-                          const void* const* ptrs, const void* tw, hipStream_t st);
+                          const void* const* ptrs, const FieldPtrs& fp, const void* tw,
+                          hipStream_t st);
 template <typename T>
 hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& segs,
                       const void* tw, hipStream_t st);
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
-                          void* const* ptrs, const void* tw, hipStream_t st);
+                          void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st);
 template <typename TO>
 hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void* tw64,
                            int quarter, hipStream_t st);
