@@ -39,10 +39,9 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # pass) and tied to the SHA-256 of the kernel source they were taken on: a
 # changed kernel reports null until it is profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "col_mac"): (48273125, "262747bad735ddfb"),
-    ("two-level-256", "f32", "row_inv"): (35142736, "262747bad735ddfb"),
-    ("two-level-256", "f32", "row_fwd"): (10494778, "262747bad735ddfb"),
-    ("two-level-256", "f32", "col_fwd"): (25515334, "262747bad735ddfb"),
+    ("two-level-256", "f32", "col"): (29334564, "80bc9ef33b8e1f5d"),
+    ("two-level-256", "f32", "row_inv"): (7590181, "80bc9ef33b8e1f5d"),
+    ("two-level-256", "f32", "row_fwd"): (10503532, "80bc9ef33b8e1f5d"),
 }
 
 
