@@ -151,23 +151,37 @@ def run_serve(args, td, torch, synth):
         log(f"planned type {k}: levels {len(hier.patches)} n {hier.patches[0].n} "
             f"workspace {plan.footprint()[0] / 2**30:.2f} GiB ({time.perf_counter() - tp:.1f} s)")
     srv = td.Server(ctx, max_inflight=args.inflight, max_batch=args.max_batch)
+    srv.set_queue_limit(args.queue_limit)
     # warm-up: each type once
     for plan, f, outs in types:
         srv.submit(plan, *f, *outs[0])
         srv.drain()
     log(f"warm-up done ({time.perf_counter() - tp:.1f} s)")
     torch.cuda.synchronize()
+    st0 = srv.stats()
     arrivals = [t for t, _, _ in reqs]
     pick = rng.integers(0, ntypes, len(arrivals))
     tickets = []
+    refused = 0
     t0 = time.perf_counter()
+    next_log = 1.0
     for k, ta in enumerate(arrivals):
         while time.perf_counter() - t0 < ta:
             pass
         plan, f, outs = types[pick[k]]
-        tk, _, _ = srv.submit(plan, *f, *outs[k % 2])
-        tickets.append((tk, plan.cells))
-    log(f"{len(tickets)} requests submitted ({time.perf_counter() - t0:.2f} s)")
+        try:
+            tk, _, _ = srv.submit(plan, *f, *outs[k % 2], queue_if_full=False)
+            tickets.append((tk, plan.cells))
+        except td.TdError as e:
+            if e.status != 6:  # TD_EBUSY: the bounded queue is full
+                raise
+            refused += 1
+        if ta >= next_log:
+            log(f"t={ta:.1f} s: {len(tickets)} admitted, {refused} refused, "
+                f"{srv.stats()['completed'] - st0['completed']} completed")
+            next_log += 1.0
+    t_arr = time.perf_counter() - t0
+    log(f"{len(tickets)} requests admitted, {refused} refused ({t_arr:.2f} s)")
     last = time.perf_counter()
     while True:
         n_done = sum(srv.poll(tk)[0] for tk, _ in tickets[::max(1, len(tickets) // 200)])
@@ -188,6 +202,7 @@ def run_serve(args, td, torch, synth):
         lats.append(lat)
         cells += c
     st = srv.stats()
+    st = {k: st[k] - st0[k] if k != "peak_queue" else st[k] for k in st}
     lats = np.array(lats)
     srv.close()
     return {
@@ -197,8 +212,10 @@ def run_serve(args, td, torch, synth):
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "serve", "offered_rate": args.rate, "duration_s": args.duration,
                    "request_types": ntypes, "max_inflight": args.inflight,
-                   "max_batch": args.max_batch, "hbm_budget_gb": args.budget_gb},
-        "serving": {"requests": len(tickets), "wall_s": el,
+                   "max_batch": args.max_batch, "queue_limit": args.queue_limit,
+                   "hbm_budget_gb": args.budget_gb},
+        "serving": {"offered": len(arrivals), "admitted": len(tickets), "refused": refused,
+                    "arrival_window_s": t_arr, "wall_s": el,
                     "sustained_req_per_s": len(tickets) / el,
                     "p50_ms": float(np.percentile(lats, 50) * 1e3),
                     "p99_ms": float(np.percentile(lats, 99) * 1e3),
@@ -220,7 +237,9 @@ def main():
     ap.add_argument("--tune", metavar="DB", default=None,
                     help="autotune launch shapes first (JSON-lines database path)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean arrivals per s")
-    ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
+    ap.add_argument("--queue-limit", type=int, default=256,
+                    help="serve: requests waiting for admission at most (others refused)")
     ap.add_argument("--types", type=int, default=48, help="serve: distinct request hierarchies")
     ap.add_argument("--inflight", type=int, default=4, help="serve: concurrent batches")
     ap.add_argument("--max-batch", type=int, default=16, help="serve: requests per batch")

@@ -182,9 +182,13 @@ td_status td_autotune(td_context* ctx, td_dtype dtype, int32_t max_M, const char
  * max_inflight batches concurrently on its own streams. */
 td_status td_server_create(td_context* ctx, int32_t max_inflight, int32_t max_batch,
                            td_server** out);
+/* Requests waiting for admission at most (default 65536); submissions
+ * beyond it are refused (see td_server_submit). */
+td_status td_server_set_queue_limit(td_server* s, int32_t max_queued);
 /* Submit a solve.  The request's plan must stay alive until the ticket is
- * done.  If the server has no room (queue at capacity) and queue_if_full is
- * 0, returns TD_EBUSY.  Arrival time = time of the call. */
+ * done.  If the server has no room (queue at its limit) and queue_if_full
+ * is 0, returns TD_EBUSY (counted as refused).  Arrival time = time of the
+ * call. */
 td_status td_server_submit(td_server* s, const td_request* req, int32_t queue_if_full,
                            uint64_t* ticket);
 /* done = 1 once the outputs of `ticket` are complete on the device.

@@ -260,6 +260,10 @@ class Server:
         self.handle = h
         self._live = {}
 
+    def set_queue_limit(self, max_queued: int):
+        B.check(lib().td_server_set_queue_limit(self.handle, max_queued),
+                "td_server_set_queue_limit")
+
     def submit(self, plan: Plan, sigma, dsdx=None, dsdy=None, fx=None, fy=None,
                queue_if_full: bool = True):
         req, fx, fy = plan.request(sigma, dsdx, dsdy, fx, fy)

@@ -1629,6 +1629,14 @@ extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int
     return TD_OK;
 }
 
+extern "C" td_status td_server_set_queue_limit(td_server* S, int32_t max_queued)
+{
+    if (!S || max_queued < 1) return fail(TD_EINVAL, "bad server or queue limit");
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->queue_cap = (size_t)max_queued;
+    return TD_OK;
+}
+
 extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32_t queue_if_full,
                                       uint64_t* ticket)
 {

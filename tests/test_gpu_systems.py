@@ -251,3 +251,27 @@ def test_timing_and_traffic(ctx):
     assert all(tr[p] > 0 for p in ("row_fwd", "col", "row_inv"))
     ws, spec = plan.footprint()
     assert ws > 0 and spec > 0
+
+
+def test_server_queue_limit_refuses(ctx):
+    """With the admission queue bounded, submissions beyond it are refused
+    (TD_EBUSY) and counted; every admitted one completes."""
+    import paper_1603_03142_amd as td
+    hier, _ = synth.config3()  # about a millisecond per solve
+    plan = ctx.plan(hier, "f32")
+    f = _dev_fields(hier, 6, "f32")[0]
+    srv = td.Server(ctx, max_inflight=1, max_batch=1)
+    srv.set_queue_limit(2)
+    ok = busy = 0
+    for _ in range(40):
+        try:
+            srv.submit(plan, *f, queue_if_full=False)
+            ok += 1
+        except td.TdError as e:
+            assert e.status == 6  # TD_EBUSY
+            busy += 1
+    srv.drain()
+    st = srv.stats()
+    assert busy > 0 and ok >= 2
+    assert st["completed"] == ok and st["refused"] == busy
+    srv.close()
