@@ -66,38 +66,47 @@ typedef enum {
 
 typedef enum { TD_F32 = 0, TD_F64 = 1 } td_dtype;
 
+/* One square patch of the hierarchy (a grid Omega^l_k of Section 2.1). */
 typedef struct {
-    int32_t n;   /* cells per side                                         */
-    int32_t ox;  /* lower-left offset in this level's cells, from level 0  */
-    int32_t oy;
-} td_level;
+    int32_t level; /* refinement level, 0 = base                          */
+    int32_t n;     /* cells per side                                      */
+    int32_t ox;    /* lower-left offset in this level's cells, from the   */
+    int32_t oy;    /* level-0 origin                                      */
+} td_patch;
 
+/* A nested-grid hierarchy: exactly one level-0 patch (at offset 0, 0), and
+ * on every level l >= 1 one or more non-overlapping patches, each inside a
+ * patch of level l-1 with its edges on level-(l-1) nodes (Section 2.1:
+ * integer refinement ratio).  Patches are listed grouped by level, level 0
+ * first; every per-patch array of a request follows this order. */
 typedef struct {
-    double x0, y0;          /* lower-left corner of level 0               */
-    double h0;              /* level-0 cell side                          */
-    int32_t ratio;          /* refinement ratio between levels: 2 or 4    */
-    int32_t nlevels;        /* 1 .. TD_MAX_LEVELS                         */
-    const td_level* levels; /* [nlevels], level 0 first                   */
+    double x0, y0;           /* lower-left corner of level 0              */
+    double h0;               /* level-0 cell side                         */
+    int32_t ratio;           /* refinement ratio between levels: 2 or 4   */
+    int32_t npatches;        /* 1 .. TD_MAX_PATCHES                       */
+    const td_patch* patches; /* [npatches], grouped by level              */
 } td_hierarchy;
 
 #define TD_MAX_LEVELS 8
-#define TD_MAX_N 2048   /* cells per side of one level                    */
+#define TD_MAX_PATCHES 8   /* over all levels                             */
+#define TD_MAX_N 2048      /* cells per side of a level's bounding square */
 
 typedef struct td_context td_context;
 typedef struct td_plan td_plan;
 typedef struct td_batch td_batch;
 typedef struct td_server td_server;
 
-/* One force solve.  Arrays are indexed by level; all pointers are device
- * pointers of the plan's dtype.  dsdx / dsdy may be NULL (all slopes zero);
- * an individual entry may also be NULL. */
+/* One force solve.  Arrays are indexed by patch (hierarchy order); patch k
+ * holds n_k x n_k values.  All pointers are device pointers of the plan's
+ * dtype.  dsdx / dsdy may be NULL (all slopes zero); an individual entry
+ * may also be NULL. */
 typedef struct {
     td_plan* plan;
-    const void* const* sigma;   /* [nlevels] sigma at cell centres          */
-    const void* const* dsdx;    /* [nlevels] or NULL: x-slope in each cell  */
-    const void* const* dsdy;    /* [nlevels] or NULL                        */
-    void* const* fx;            /* [nlevels] outputs                        */
-    void* const* fy;            /* [nlevels] outputs                        */
+    const void* const* sigma;   /* [npatches] sigma at cell centres         */
+    const void* const* dsdx;    /* [npatches] or NULL: x-slope in each cell */
+    const void* const* dsdy;    /* [npatches] or NULL                       */
+    void* const* fx;            /* [npatches] outputs                       */
+    void* const* fy;            /* [npatches] outputs                       */
 } td_request;
 
 /* ---------------------------------------------------------------- context */
@@ -112,15 +121,19 @@ td_status td_context_usage(const td_context* ctx, size_t* bytes_in_use, size_t* 
 
 /* ---------------------------------------------------------------- geometry */
 
-/* Validate a hierarchy (ratio, sizes, alignment, nesting).  TD_OK if it can
- * be planned. */
+/* Validate a hierarchy (ratio, sizes, alignment, nesting, overlap).  TD_OK
+ * if it can be planned.  Levels may differ in resolution by at most 16x
+ * (ratio^(levels-1) <= 16), and each level's patches must span at most
+ * TD_MAX_N cells (TD_EUNSUPPORTED otherwise). */
 td_status td_hierarchy_check(const td_hierarchy* h);
 
-/* Fill levels[1..nlevels-1].ox/oy so that each child patch (of the n given
- * in levels[l].n) is centred as near as its parent lattice allows to
- * (cx[l-1], cy[l-1]) -- lower-left rounded to the nearest parent node and
- * clamped inside the parent.  levels[0] gets offset (0, 0). */
-td_status td_hierarchy_snap(td_hierarchy* inout, td_level* levels, const double* cx,
+/* For a hierarchy of one patch per level (patches[l] on level l, sizes
+ * given): fill patches[1..].ox/oy so that each child patch is centred as
+ * near as its parent lattice allows to (cx[l-1], cy[l-1]) -- lower-left
+ * rounded to the nearest parent node and clamped inside the parent
+ * (requested centres need not lie on any lattice).  patches[0] gets offset
+ * (0, 0); inout->patches is set to `patches`. */
+td_status td_hierarchy_snap(td_hierarchy* inout, td_patch* patches, const double* cx,
                             const double* cy);
 
 /* ---------------------------------------------------------------- plans */

@@ -44,8 +44,8 @@ def _check_fields(plan: "Plan", arrays, name, required=True):
         if required:
             raise ValueError(f"{name} is required")
         return None
-    if len(arrays) != plan.nlevels:
-        raise ValueError(f"{name}: expected {plan.nlevels} arrays, got {len(arrays)}")
+    if len(arrays) != plan.npatches:
+        raise ValueError(f"{name}: expected {plan.npatches} arrays (one per patch), got {len(arrays)}")
     for l, (t, n) in enumerate(zip(arrays, plan.sizes)):
         if t is None:
             if required:
@@ -132,7 +132,8 @@ def check_plan(hier, dtype: str = "f32") -> int:
 
 
 class Plan:
-    """td_plan for one hierarchy (one patch per level) and dtype."""
+    """td_plan for one hierarchy and dtype; field lists are per patch, in the
+    hierarchy's patch order."""
 
     def __init__(self, ctx: Context, hier, dtype: str = "f32"):
         if dtype not in _DT:
@@ -141,8 +142,9 @@ class Plan:
         self.dtype = dtype
         self.hier = hier
         h = B.make_hierarchy(hier)
-        self.nlevels = h.nlevels
-        self.sizes = [h.levels[l].n for l in range(h.nlevels)]
+        self.npatches = h.npatches
+        self.sizes = [h.patches[k].n for k in range(h.npatches)]
+        self.nlevels = 1 + max(h.patches[k].level for k in range(h.npatches))
         handle = ctypes.c_void_p()
         B.check(lib().td_plan_create(ctx.handle, ctypes.byref(h), _DT[dtype],
                                      ctypes.byref(handle)), "td_plan_create")

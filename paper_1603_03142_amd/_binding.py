@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libthindisk.so")
 TD_OK, TD_EINVAL, TD_EALIGN, TD_ENEST, TD_ENOMEM, TD_EDEVICE, TD_EBUSY, TD_EUNSUPPORTED = range(8)
 TD_F32, TD_F64 = 0, 1
 TD_MAX_LEVELS = 8
+TD_MAX_PATCHES = 8
 
 # Every entry point the header declares.
 EXPORTS = [
@@ -39,14 +40,15 @@ _STATUS = {0: "TD_OK", 1: "TD_EINVAL", 2: "TD_EALIGN", 3: "TD_ENEST", 4: "TD_ENO
            5: "TD_EDEVICE", 6: "TD_EBUSY", 7: "TD_EUNSUPPORTED"}
 
 
-class td_level(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("ox", ctypes.c_int32), ("oy", ctypes.c_int32)]
+class td_patch(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("n", ctypes.c_int32), ("ox", ctypes.c_int32),
+                ("oy", ctypes.c_int32)]
 
 
 class td_hierarchy(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("h0", ctypes.c_double),
-                ("ratio", ctypes.c_int32), ("nlevels", ctypes.c_int32),
-                ("levels", ctypes.POINTER(td_level))]
+                ("ratio", ctypes.c_int32), ("npatches", ctypes.c_int32),
+                ("patches", ctypes.POINTER(td_patch))]
 
 
 VP = ctypes.c_void_p
@@ -80,7 +82,7 @@ def lib():
             "td_context_destroy": ([VP], S),
             "td_context_usage": ([VP, sz, sz], S),
             "td_hierarchy_check": ([ctypes.POINTER(td_hierarchy)], S),
-            "td_hierarchy_snap": ([ctypes.POINTER(td_hierarchy), ctypes.POINTER(td_level),
+            "td_hierarchy_snap": ([ctypes.POINTER(td_hierarchy), ctypes.POINTER(td_patch),
                                    ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double)], S),
             "td_plan_create": ([VP, ctypes.POINTER(td_hierarchy), ctypes.c_int,
@@ -128,18 +130,19 @@ def check(status: int, where: str):
 
 
 def make_hierarchy(hier):
-    """td_hierarchy from an object with x0, y0, h0, ratio and one patch per
-    level (``patches`` with level/n/ox/oy, or ``levels`` as (n, ox, oy))."""
+    """td_hierarchy from an object with x0, y0, h0, ratio and either
+    ``patches`` (level/n/ox/oy, grouped by level, level 0 first -- the order
+    of every per-patch array) or ``levels`` ((n, ox, oy), one patch per
+    level)."""
     if hasattr(hier, "patches"):
-        pats = sorted(hier.patches, key=lambda p: p.level)
-        if [p.level for p in pats] != list(range(len(pats))):
-            raise ValueError("the HIP path takes exactly one patch per level")
-        lv = [(p.n, p.ox, p.oy) for p in pats]
+        pats = [(p.level, p.n, p.ox, p.oy) for p in hier.patches]
+        if [p[0] for p in pats] != sorted(p[0] for p in pats):
+            raise ValueError("patches must be grouped by level, level 0 first")
     else:
-        lv = list(hier.levels)
-    arr = (td_level * len(lv))(*[td_level(n, ox, oy) for n, ox, oy in lv])
-    h = td_hierarchy(float(hier.x0), float(hier.y0), float(hier.h0), int(hier.ratio), len(lv),
-                     ctypes.cast(arr, ctypes.POINTER(td_level)))
+        pats = [(l, n, ox, oy) for l, (n, ox, oy) in enumerate(hier.levels)]
+    arr = (td_patch * len(pats))(*[td_patch(*p) for p in pats])
+    h = td_hierarchy(float(hier.x0), float(hier.y0), float(hier.h0), int(hier.ratio), len(pats),
+                     ctypes.cast(arr, ctypes.POINTER(td_patch)))
     h._keep = arr
     return h
 

@@ -60,6 +60,13 @@ int floor_div(int a, int b)
 }
 int ceil_div(int a, int b) { return -floor_div(-a, b); }
 
+int ipow(int b, int e)
+{
+    int r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+
 int fft_len(int n)
 {
     int M = 16;
@@ -279,6 +286,16 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
     td_status st = ctx->alloc(tbytes, &table);
     if (st == TD_OK) st = ctx->alloc(rbytes, &rows);
     if (st == TD_OK) st = ctx->alloc(6 * sizeof(void*), &dptr);
+    void* dlp = nullptr;  // the tables as one M x M patch, field X at slot X
+    if (st == TD_OK) st = ctx->alloc(sizeof(LevelPatches), &dlp);
+    if (st == TD_OK) {
+        LevelPatches lp;
+        memset(&lp, 0, sizeof(lp));
+        lp.np = 1;
+        lp.pn[0] = M;
+        hipError_t he = hipMemcpy(dlp, &lp, sizeof(lp), hipMemcpyHostToDevice);
+        if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
+    }
     const void* tw64 = nullptr;
     if (st == TD_OK) st = twiddles(ctx, M, TD_F64, &tw64);
     RowFwdJob* djobs = nullptr;
@@ -293,8 +310,8 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
             for (int r0 = 0; r0 < M; r0 += 2 * C) {
                 RowFwdJob j;
                 memset(&j, 0, sizeof(j));
-                j.src_slot = X;
-                j.n_src = M;
+                j.lvl = 0;
+                j.f = X;
                 j.m = 1;
                 j.ld = M;
                 j.row0 = r0;
@@ -322,7 +339,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
         hipError_t he = launch_table(tj, ctx->stream);
         if (he == hipSuccess)
             he = launch_row_fwd<double>(M, C, (int)jobs.size(),
-                                        single_seg<RowFwdJob>(djobs, (int)jobs.size(), 0, nullptr, (char*)rows),
+                                        single_seg<RowFwdJob>(djobs, (int)jobs.size(), 0, dlp, (char*)rows),
                                         (const void* const*)dptr, FieldPtrs{}, tw64, ctx->stream);
         const int Cs = std::max(1, std::min(shape_C(default_shape(P_ROWINV, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
         void* dst = (char*)e.ptr + (size_t)p * per_phase * elem_size(dt);
@@ -335,6 +352,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
     ctx->release(table, tbytes);
     ctx->release(rows, rbytes);
     ctx->release(dptr, 6 * sizeof(void*));
+    ctx->release(dlp, sizeof(LevelPatches));
     if (djobs) ctx->release(djobs, jobs.size() * sizeof(RowFwdJob));
     if (st != TD_OK) {
         ctx->release(e.ptr, e.bytes);
@@ -352,65 +370,133 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
 // hierarchy validation
 // ===========================================================================
 
+namespace {
+
+// Level of every patch and the index of each level's first patch; checks
+// that patches are grouped by level, level 0 first, with one level-0 patch.
+td_status patch_levels(const td_hierarchy* h, int* nlevels)
+{
+    if (!h || !h->patches) return fail(TD_EINVAL, "hierarchy or patches is NULL");
+    if (h->npatches < 1 || h->npatches > TD_MAX_PATCHES)
+        return fail(TD_EINVAL, "npatches must be in 1.." + std::to_string(TD_MAX_PATCHES));
+    const td_patch* P = h->patches;
+    if (P[0].level != 0) return fail(TD_EINVAL, "the first patch must be the level-0 patch");
+    std::vector<int> count(1, 1);
+    for (int k = 1; k < h->npatches; ++k) {
+        const int l = P[k].level, prev = P[k - 1].level;
+        if (l != prev && l != prev + 1)
+            return fail(TD_EINVAL, "patches must be grouped by level in increasing order");
+        if (l == 0) return fail(TD_EINVAL, "exactly one level-0 patch");
+        if (l == (int)count.size()) count.push_back(0);
+        count[l] += 1;
+    }
+    if ((int)count.size() > TD_MAX_LEVELS)
+        return fail(TD_EINVAL, "at most " + std::to_string(TD_MAX_LEVELS) + " levels");
+    for (int c : count)
+        if (c > TD_PATCHES_PER_LEVEL)
+            return fail(TD_EINVAL, "at most " + std::to_string(TD_PATCHES_PER_LEVEL) + " patches per level");
+    *nlevels = (int)count.size();
+    return TD_OK;
+}
+
+// Bounding rectangle of a level's patches (level cells): origin and size.
+void level_window(const td_hierarchy* h, int level, int* ox, int* oy, int* nx, int* ny)
+{
+    int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+    for (int k = 0; k < h->npatches; ++k) {
+        const td_patch& p = h->patches[k];
+        if (p.level != level) continue;
+        x0 = std::min(x0, p.ox);
+        y0 = std::min(y0, p.oy);
+        x1 = std::max(x1, p.ox + p.n);
+        y1 = std::max(y1, p.oy + p.n);
+    }
+    *ox = x0;
+    *oy = y0;
+    *nx = x1 - x0;
+    *ny = y1 - y0;
+}
+
+}  // namespace
+
 extern "C" td_status td_hierarchy_check(const td_hierarchy* h)
 {
-    if (!h || !h->levels) return fail(TD_EINVAL, "hierarchy or levels is NULL");
-    if (h->nlevels < 1 || h->nlevels > TD_MAX_LEVELS)
-        return fail(TD_EINVAL, "nlevels must be in 1.." + std::to_string(TD_MAX_LEVELS));
+    int L = 0;
+    TD_TRY(patch_levels(h, &L));
     if (h->ratio != 2 && h->ratio != 4)
         return fail(TD_EUNSUPPORTED, "refinement ratio must be 2 or 4");
     if (!(h->h0 > 0) || !std::isfinite(h->h0) || !std::isfinite(h->x0) || !std::isfinite(h->y0))
         return fail(TD_EINVAL, "h0 must be positive and x0, y0, h0 finite");
-    const td_level* L = h->levels;
-    if (L[0].ox != 0 || L[0].oy != 0) return fail(TD_EINVAL, "level 0 offsets must be 0");
-    long span = 1;
-    for (int l = 0; l < h->nlevels; ++l) {
-        if (L[l].n < 1 || L[l].n > TD_MAX_N)
-            return fail(TD_EINVAL, "level " + std::to_string(l) + ": n must be in 1.." +
-                                       std::to_string(TD_MAX_N));
-        if (L[l].ox < 0 || L[l].oy < 0)
-            return fail(TD_ENEST, "level " + std::to_string(l) + ": negative offset");
-        if (l == 0) continue;
-        span *= h->ratio;
-        if (span * (long)L[0].n > (1L << 30)) return fail(TD_EINVAL, "hierarchy too deep");
-        const int r = h->ratio;
-        if (L[l].n % r || L[l].ox % r || L[l].oy % r)
-            return fail(TD_EALIGN, "level " + std::to_string(l) +
-                                       ": size and offsets must be multiples of the ratio");
-        const int px0 = L[l].ox / r, py0 = L[l].oy / r, w = L[l].n / r;
-        if (px0 < L[l - 1].ox || py0 < L[l - 1].oy || px0 + w > L[l - 1].ox + L[l - 1].n ||
-            py0 + w > L[l - 1].oy + L[l - 1].n)
-            return fail(TD_ENEST, "level " + std::to_string(l) + " is not inside level " +
-                                      std::to_string(l - 1));
+    const td_patch* P = h->patches;
+    if (P[0].ox != 0 || P[0].oy != 0) return fail(TD_EINVAL, "level-0 offsets must be 0");
+    const int r = h->ratio;
+    if (ipow(r, L - 1) > 16)
+        return fail(TD_EUNSUPPORTED, "levels may differ in resolution by at most 16x (ratio^(levels-1) <= 16)");
+    for (int k = 0; k < h->npatches; ++k) {
+        const td_patch& p = P[k];
+        const std::string who = "patch " + std::to_string(k) + " (level " + std::to_string(p.level) + ")";
+        if (p.n < 1 || p.n > TD_MAX_N)
+            return fail(TD_EINVAL, who + ": n must be in 1.." + std::to_string(TD_MAX_N));
+        if (p.ox < 0 || p.oy < 0) return fail(TD_ENEST, who + ": negative offset");
+        if (p.level == 0) continue;
+        long span = 1;
+        for (int l = 0; l < p.level; ++l) span *= r;
+        if (span * (long)P[0].n > (1L << 30)) return fail(TD_EINVAL, "hierarchy too deep");
+        if (p.n % r || p.ox % r || p.oy % r)
+            return fail(TD_EALIGN, who + ": size and offsets must be multiples of the ratio");
+        // inside one patch of the level above
+        const int px0 = p.ox / r, py0 = p.oy / r, w = p.n / r;
+        bool inside = false;
+        for (int q = 0; q < h->npatches; ++q) {
+            const td_patch& u = P[q];
+            inside |= u.level == p.level - 1 && px0 >= u.ox && py0 >= u.oy &&
+                      px0 + w <= u.ox + u.n && py0 + w <= u.oy + u.n;
+        }
+        if (!inside) return fail(TD_ENEST, who + " is not inside a patch of level " + std::to_string(p.level - 1));
+        // no overlap with another patch of the same level
+        for (int q = 0; q < k; ++q) {
+            const td_patch& u = P[q];
+            if (u.level == p.level && p.ox < u.ox + u.n && u.ox < p.ox + p.n && p.oy < u.oy + u.n &&
+                u.oy < p.oy + p.n)
+                return fail(TD_EINVAL, who + " overlaps patch " + std::to_string(q));
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        int ox, oy, nx, ny;
+        level_window(h, l, &ox, &oy, &nx, &ny);
+        if (nx > TD_MAX_N || ny > TD_MAX_N)
+            return fail(TD_EUNSUPPORTED, "level " + std::to_string(l) + ": patches span more than " +
+                                             std::to_string(TD_MAX_N) + " cells");
     }
     return TD_OK;
 }
 
-extern "C" td_status td_hierarchy_snap(td_hierarchy* h, td_level* levels, const double* cx,
+extern "C" td_status td_hierarchy_snap(td_hierarchy* h, td_patch* patches, const double* cx,
                                        const double* cy)
 {
-    if (!h || !levels || (h->nlevels > 1 && (!cx || !cy)))
-        return fail(TD_EINVAL, "NULL argument");
-    if (h->nlevels < 1 || h->nlevels > TD_MAX_LEVELS) return fail(TD_EINVAL, "bad nlevels");
+    if (!h || !patches || (h->npatches > 1 && (!cx || !cy))) return fail(TD_EINVAL, "NULL argument");
+    if (h->npatches < 1 || h->npatches > TD_MAX_LEVELS) return fail(TD_EINVAL, "bad npatches");
     if (h->ratio != 2 && h->ratio != 4) return fail(TD_EUNSUPPORTED, "ratio must be 2 or 4");
-    levels[0].ox = levels[0].oy = 0;
+    for (int l = 0; l < h->npatches; ++l)
+        if (patches[l].level != l) return fail(TD_EINVAL, "snap takes one patch per level, patch l on level l");
+    patches[0].ox = patches[0].oy = 0;
     double hh = h->h0;
-    for (int l = 1; l < h->nlevels; ++l) {
-        const int r = h->ratio, n = levels[l].n, pn = levels[l - 1].n;
+    for (int l = 1; l < h->npatches; ++l) {
+        const int r = h->ratio, n = patches[l].n, pn = patches[l - 1].n;
         if (n % r) return fail(TD_EALIGN, "child size must be a multiple of the ratio");
         const int span = n / r;
         if (span > pn) return fail(TD_ENEST, "child wider than its parent");
-        const double px0 = h->x0 + levels[l - 1].ox * hh, py0 = h->y0 + levels[l - 1].oy * hh;
+        const double px0 = h->x0 + patches[l - 1].ox * hh, py0 = h->y0 + patches[l - 1].oy * hh;
         const double ext = n * hh / r;
         long kx = (long)std::floor((cx[l - 1] - ext / 2 - px0) / hh + 0.5);
         long ky = (long)std::floor((cy[l - 1] - ext / 2 - py0) / hh + 0.5);
         kx = std::min<long>(std::max<long>(kx, 0), pn - span);
         ky = std::min<long>(std::max<long>(ky, 0), pn - span);
-        levels[l].ox = r * (levels[l - 1].ox + (int)kx);
-        levels[l].oy = r * (levels[l - 1].oy + (int)ky);
+        patches[l].ox = r * (patches[l - 1].ox + (int)kx);
+        patches[l].oy = r * (patches[l - 1].oy + (int)ky);
         hh /= r;
     }
-    h->levels = levels;
+    h->patches = patches;
     return TD_OK;
 }
 
@@ -439,12 +525,14 @@ struct Group {
     void* d_coltabs = nullptr;  // {d_colins, d_colouts}
     RowInvJob* d_rinv[2] = {nullptr, nullptr};
     RowInvContrib* d_contribs = nullptr;
+    RowInvTables* d_rinv_tabs = nullptr;  // {d_contribs, the plan's level tables}
 };
 
+// A level's window (bounding rectangle of its patches, level cells) and
+// transform length.
 struct LevelG {
-    int n, ox, oy, M;
+    int ox, oy, nx, ny, M;
     double h;
-    int cov_i0, cov_i1, cov_j0, cov_j1;
 };
 
 }  // namespace
@@ -455,7 +543,11 @@ struct td_plan {
     td_dtype dt = TD_F32;
     int ratio = 2;
     int nlevels = 0;
+    int npatches = 0;
     std::vector<LevelG> lv;
+    std::vector<LevelPatches> lp;          // per level, for the row kernels
+    std::vector<int> patch_n;              // side of every patch
+    LevelPatches* d_lp = nullptr;
     double x0 = 0, y0 = 0, h0 = 0;
     std::vector<Group> groups;
     void* ws = nullptr;        // workspace for td_solve, allocated on first use
@@ -505,12 +597,6 @@ void mirror_order(int m, int i, int* kx, int* ky)
     *ky = (mir & 2) ? m - 1 - sy : sy;
 }
 
-int ipow(int b, int e)
-{
-    int r = 1;
-    while (e-- > 0) r *= b;
-    return r;
-}
 
 // Kernel spectra of a plan; a dry (host-only) plan gets a stand-in entry
 // whose address is never dereferenced.
@@ -530,10 +616,10 @@ td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out
 // workspace size in complex elements.
 //
 // Workspace per lattice t (level t's zero-padded M x M grid):
-//   own_in[t]      3 row-pass planes [M/2+1][n_t] of level t's fields
+//   own_in[t]      3 row-pass planes [M/2+1][ny_t] of level t's fields
 //   ph_in[s][t]    per finer level s: m^2 phases x 3 row-pass planes
 //                  [M/2+1][nr] of the polyphase sub-grids on lattice t
-//   own_out[t]     Fx, Fy column outputs [M/2+1][n_t]
+//   own_out[t]     Fx, Fy column outputs [M/2+1][ny_t]
 //   c3_out[t][s]   per finer level s: m^2 phases x (Fx, Fy) outputs
 //                  [M/2+1][ld] on lattice t for target level s
 td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
@@ -555,19 +641,19 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     for (int l = 0; l < L; ++l) {
         const LevelG& g = P->lv[l];
         const size_t H = g.M / 2 + 1;
-        own_in[l] = take(3 * H * g.n);
-        own_out[l] = take(2 * H * g.n);
+        own_in[l] = take(3 * H * g.ny);
+        own_out[l] = take(2 * H * g.ny);
     }
     for (int t = 0; t < L; ++t)
         for (int s = t + 1; s < L; ++s) {
             const int m = ipow(r, s - t);
             const LevelG &G = P->lv[t], &S = P->lv[s];
             const size_t H = G.M / 2 + 1;
-            const int nr = (S.n + m - 1) / m + 1;
+            const int nr = (S.ny + m - 1) / m + 1;
             ph_nr[s][t] = nr;
             ph_in[s][t] = take((size_t)m * m * 3 * H * nr);
             // coarser source t, finer target s: Case-3 outputs on lattice t
-            const int ld = floor_div(S.oy + S.n - 1, m) - floor_div(S.oy, m) + 1;
+            const int ld = floor_div(S.oy + S.ny - 1, m) - floor_div(S.oy, m) + 1;
             c3_ld[t][s] = ld;
             c3_out[t][s] = take((size_t)m * m * 2 * H * ld);
         }
@@ -588,18 +674,17 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
         const LevelG& G = P->lv[l];
         Group& g = group_for(P->groups, G.M);
         const int R = 2 * g.C[P_ROWFWD];
-        const size_t H = G.M / 2 + 1, plane = H * G.n;
+        const size_t H = G.M / 2 + 1, plane = H * G.ny;
         for (int f = 0; f < 3; ++f) {
-            for (int r0 = 0; r0 < G.n; r0 += R) {
+            for (int r0 = 0; r0 < G.ny; r0 += R) {
                 RowFwdJob j;
                 memset(&j, 0, sizeof(j));
-                j.src_slot = 5 * l + f;
-                j.n_src = G.n;
+                j.lvl = l;
+                j.f = f;
                 j.m = 1;
-                j.ld = G.n;
+                j.ld = G.ny;
                 j.row0 = r0;
-                j.nrow = std::min(R, G.n - r0);
-                j.cov_i0 = G.cov_i0; j.cov_i1 = G.cov_i1; j.cov_j0 = G.cov_j0; j.cov_j1 = G.cov_j1;
+                j.nrow = std::min(R, G.ny - r0);
                 j.scale = f == 0 ? 1.0 : G.h;
                 j.out = ptr(own_in[l] + f * plane);
                 g.rowfwd.push_back(j);
@@ -612,7 +697,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             for (int ky = 0; ky < m; ++ky)
                 for (int kx = 0; kx < m; ++kx) {
                     const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
-                    const int lr_hi = floor_div(S.oy + S.n - 1 - ky, m) - G.oy;
+                    const int lr_hi = floor_div(S.oy + S.ny - 1 - ky, m) - G.oy;
                     if (lr_hi < lr_lo) continue;
                     const int phase = ky * m + kx;
                     // every stored row is written (rows past the source are
@@ -622,8 +707,8 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                         for (int r0 = 0; r0 < nr; r0 += R) {
                             RowFwdJob j;
                             memset(&j, 0, sizeof(j));
-                            j.src_slot = 5 * s + f;
-                            j.n_src = S.n;
+                            j.lvl = s;
+                            j.f = f;
                             j.m = m;
                             j.row_off = m * G.oy + ky - S.oy;
                             j.col_off = m * G.ox + kx - S.ox;
@@ -631,8 +716,6 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                             j.ld = nr;
                             j.row0 = r0;
                             j.nrow = std::min(R, nr - r0);
-                            j.cov_i0 = S.cov_i0; j.cov_i1 = S.cov_i1;
-                            j.cov_j0 = S.cov_j0; j.cov_j1 = S.cov_j1;
                             j.scale = f == 0 ? 1.0 : S.h;
                             j.out = ptr(in);
                             g.rowfwd.push_back(j);
@@ -655,7 +738,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             const SpecEntry* k1 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
             for (int f = 0; f < 3; ++f)
-                g.colins.push_back({ptr(own_in[t] + f * H * G.n), k1->ptr, G.n, 0, f, 4});
+                g.colins.push_back({ptr(own_in[t] + f * H * G.ny), k1->ptr, G.ny, 0, f, 4});
             for (int s = t + 1; s < L; ++s) {
                 const LevelG& S = P->lv[s];
                 const int m = ipow(r, s - t), nr = ph_nr[s][t];
@@ -667,7 +750,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                     int kx, ky;
                     mirror_order(m, pi, &kx, &ky);
                     const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
-                    const int lr_hi = floor_div(S.oy + S.n - 1 - ky, m) - G.oy;
+                    const int lr_hi = floor_div(S.oy + S.ny - 1 - ky, m) - G.oy;
                     if (lr_hi < lr_lo) continue;
                     const int phase = ky * m + kx;
                     const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
@@ -680,7 +763,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             }
             const int out0 = (int)g.colouts.size();
             for (int comp = 0; comp < 2; ++comp)
-                g.colouts.push_back({ptr(own_out[t] + comp * H * G.n), nullptr, G.n, 0, comp, 0});
+                g.colouts.push_back({ptr(own_out[t] + comp * H * G.ny), nullptr, G.ny, 0, comp, 0});
             const int nin = (int)g.colins.size() - in0;
             for (int kx0 = 0; kx0 < (int)H; kx0 += C)
                 g.col.push_back({0, kx0, std::min(C, (int)H - kx0), in0, nin, out0, 2, 0});
@@ -725,10 +808,10 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             memset(&c, 0, sizeof(c));
             c.base = ptr(own_out[t]);
             c.phase_stride = 0;
-            c.comp_stride = (int64_t)(T.M / 2 + 1) * T.n;
+            c.comp_stride = (int64_t)(T.M / 2 + 1) * T.ny;
             c.m = 1;
             c.mshift = 0;
-            c.ld = T.n;
+            c.ld = T.ny;
             c.lr_first = 0;
             c.ox_s = T.ox;
             c.oy_s = T.oy;
@@ -763,23 +846,23 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             const int C = g.C[P_ROWINV];
             const int acc = (gi == 0) ? 0 : 1;  // Ms[0] is the own lattice's M
             // at most 2M target columns per job: 16 outputs per thread
-            const int xchunk = std::min(T.n, 2 * M);
-            for (int y0 = 0; y0 < T.n; y0 += C)
-            for (int x0 = 0; x0 < T.n; x0 += xchunk) {
+            const int xchunk = std::min(T.nx, 2 * M);
+            for (int y0 = 0; y0 < T.ny; y0 += C)
+            for (int x0 = 0; x0 < T.nx; x0 += xchunk) {
                 RowInvJob j;
                 memset(&j, 0, sizeof(j));
-                j.n_t = T.n;
+                j.lvl = t;
+                j.nx_t = T.nx;
+                j.ny_t = T.ny;
                 j.ox_t = T.ox;
                 j.oy_t = T.oy;
                 j.y0 = y0;
-                j.ny = std::min(C, T.n - y0);
-                j.out_slot = 5 * t + 3;
-                j.cov_i0 = T.cov_i0; j.cov_i1 = T.cov_i1; j.cov_j0 = T.cov_j0; j.cov_j1 = T.cov_j1;
+                j.ny = std::min(C, T.ny - y0);
                 j.c0 = c0;
                 j.nc = nc;
                 j.accumulate = acc;
                 j.x0 = x0;
-                j.nx = std::min(xchunk, T.n - x0);
+                j.nx = std::min(xchunk, T.nx - x0);
                 g.rinv[acc].push_back(j);
             }
         }
@@ -796,9 +879,23 @@ td_status validate_jobs(td_plan* P)
     const int64_t ws = (int64_t)P->ws_bytes;
     auto in_ws = [&](int64_t off, int64_t elems) { return off >= 0 && off + elems * (int64_t)es <= ws; };
     auto bad = [&](const char* what) { return fail(TD_EINVAL, std::string("plan validation: ") + what); };
-    std::vector<int> nsrc(5 * P->nlevels);
-    for (int l = 0; l < P->nlevels; ++l)
-        for (int f = 0; f < 5; ++f) nsrc[5 * l + f] = P->lv[l].n;
+    // patch tables: patches inside their level's window, covered squares
+    // inside the window, pointer slots within the request's table
+    if ((int)P->lp.size() != P->nlevels) return bad("level tables");
+    for (int l = 0; l < P->nlevels; ++l) {
+        const LevelPatches& lp = P->lp[l];
+        const LevelG& G = P->lv[l];
+        if (lp.np < 1 || lp.np > TD_PATCHES_PER_LEVEL || lp.nc < 0 || lp.nc > TD_PATCHES_PER_LEVEL)
+            return bad("level patch counts");
+        for (int k = 0; k < lp.np; ++k)
+            if (lp.pi0[k] < 0 || lp.pj0[k] < 0 || lp.pn[k] < 1 || lp.pi0[k] + lp.pn[k] > G.nx ||
+                lp.pj0[k] + lp.pn[k] > G.ny || lp.pslot[k] < 0 || lp.pslot[k] + 4 >= 5 * P->npatches ||
+                lp.pslot[k] % 5 || P->patch_n[lp.pslot[k] / 5] != lp.pn[k])
+                return bad("level patch");
+        for (int k = 0; k < lp.nc; ++k)
+            if (lp.ci0[k] < 0 || lp.cj0[k] < 0 || lp.ci0[k] + lp.cn[k] > G.nx || lp.cj0[k] + lp.cn[k] > G.ny)
+                return bad("covered square");
+    }
     for (auto& g : P->groups) {
         const int M = g.M, H = M / 2 + 1;
         for (int pass = 0; pass < NSHAPE; ++pass) {
@@ -810,8 +907,7 @@ td_status validate_jobs(td_plan* P)
         // pass 1: rows written per row-pass plane
         std::map<int64_t, std::vector<char>> rows_written;
         for (auto& j : g.rowfwd) {
-            if (j.src_slot < 0 || j.src_slot >= (int)nsrc.size() || nsrc[j.src_slot] != j.n_src)
-                return bad("row source");
+            if (j.lvl < 0 || j.lvl >= P->nlevels || j.f < 0 || j.f > 2) return bad("row source");
             if (j.row0 < 0 || j.nrow < 1 || j.nrow > 2 * g.C[P_ROWFWD] || j.row0 + j.nrow > j.ld)
                 return bad("row range");
             if (!in_ws(j.out, (int64_t)H * j.ld)) return bad("row output");
@@ -865,9 +961,11 @@ td_status validate_jobs(td_plan* P)
         std::vector<char> contrib_ok(g.contribs.size(), 0);
         for (int a = 0; a < 2; ++a)
             for (auto& j : g.rinv[a]) {
-                if (j.y0 < 0 || j.ny < 1 || j.ny > g.C[P_ROWINV] || j.y0 + j.ny > j.n_t) return bad("rinv rows");
-                if (j.out_slot < 0 || j.out_slot + 1 >= (int)nsrc.size()) return bad("rinv slot");
-                if (j.x0 < 0 || j.nx < 1 || j.x0 + j.nx > j.n_t || (long)j.nx > 2L * M)
+                if (j.lvl < 0 || j.lvl >= P->nlevels || j.nx_t != P->lv[j.lvl].nx ||
+                    j.ny_t != P->lv[j.lvl].ny || j.ox_t != P->lv[j.lvl].ox || j.oy_t != P->lv[j.lvl].oy)
+                    return bad("rinv level");
+                if (j.y0 < 0 || j.ny < 1 || j.ny > g.C[P_ROWINV] || j.y0 + j.ny > j.ny_t) return bad("rinv rows");
+                if (j.x0 < 0 || j.nx < 1 || j.x0 + j.nx > j.nx_t || (long)j.nx > 2L * M)
                     return bad("rinv columns");
                 if (j.c0 < 0 || j.c0 + j.nc > (int)g.contribs.size()) return bad("rinv contribs");
                 if (j.oy_t < 0 || j.ox_t < 0) return bad("rinv offsets");
@@ -907,40 +1005,53 @@ td_status validate_jobs(td_plan* P)
 // Level geometry (sizes, offsets, FFT lengths, covered rectangles).
 td_status plan_geometry(td_plan* P, const td_hierarchy* h, td_dtype dt)
 {
+    int L = 0;
+    TD_TRY(patch_levels(h, &L));
     P->dt = dt;
     P->ratio = h->ratio;
-    P->nlevels = h->nlevels;
+    P->nlevels = L;
+    P->npatches = h->npatches;
     P->x0 = h->x0;
     P->y0 = h->y0;
     P->h0 = h->h0;
     P->id = g_plan_ids++;
     double hh = h->h0;
-    for (int l = 0; l < h->nlevels; ++l) {
+    for (int l = 0; l < L; ++l) {
         LevelG g;
-        g.n = h->levels[l].n;
-        g.ox = h->levels[l].ox;
-        g.oy = h->levels[l].oy;
-        g.M = fft_len(g.n);
+        level_window(h, l, &g.ox, &g.oy, &g.nx, &g.ny);
+        g.M = fft_len(std::max(g.nx, g.ny));
         g.h = hh;
-        g.cov_i0 = g.cov_i1 = g.cov_j0 = g.cov_j1 = 0;
-        if (l + 1 < h->nlevels) {
-            const td_level& c = h->levels[l + 1];
-            g.cov_i0 = c.ox / h->ratio - g.ox;
-            g.cov_i1 = g.cov_i0 + c.n / h->ratio;
-            g.cov_j0 = c.oy / h->ratio - g.oy;
-            g.cov_j1 = g.cov_j0 + c.n / h->ratio;
-        }
         if (dt == TD_F64 && g.M > 2048)
-            return fail(TD_EUNSUPPORTED, "FP64 plans support at most 1024 cells per side");
+            return fail(TD_EUNSUPPORTED, "FP64 plans support at most 1024 cells per level window side");
+        LevelPatches lp;
+        memset(&lp, 0, sizeof(lp));
+        for (int k = 0; k < h->npatches; ++k) {
+            const td_patch& q = h->patches[k];
+            if (q.level == l) {
+                lp.pi0[lp.np] = q.ox - g.ox;
+                lp.pj0[lp.np] = q.oy - g.oy;
+                lp.pn[lp.np] = q.n;
+                lp.pslot[lp.np] = 5 * k;
+                lp.np += 1;
+            } else if (q.level == l + 1) {
+                lp.ci0[lp.nc] = q.ox / h->ratio - g.ox;
+                lp.cj0[lp.nc] = q.oy / h->ratio - g.oy;
+                lp.cn[lp.nc] = q.n / h->ratio;
+                lp.nc += 1;
+            }
+        }
         P->lv.push_back(g);
+        P->lp.push_back(lp);
         hh /= h->ratio;
     }
+    for (int k = 0; k < h->npatches; ++k) P->patch_n.push_back(h->patches[k].n);
     return TD_OK;
 }
 
 td_status plan_upload(td_plan* P)
 {
     td_context* ctx = P->ctx;
+    TD_TRY(upload(ctx, P, P->lp, &P->d_lp));
     for (auto& g : P->groups) {
         TD_TRY(upload(ctx, P, g.rowfwd, &g.d_rowfwd));
         TD_TRY(upload(ctx, P, g.col, &g.d_col));
@@ -955,6 +1066,10 @@ td_status plan_upload(td_plan* P)
         TD_TRY(upload(ctx, P, g.rinv[0], &g.d_rinv[0]));
         TD_TRY(upload(ctx, P, g.rinv[1], &g.d_rinv[1]));
         TD_TRY(upload(ctx, P, g.contribs, &g.d_contribs));
+        {
+            const std::vector<RowInvTables> tabs{{g.d_contribs, P->d_lp}};
+            TD_TRY(upload(ctx, P, tabs, &g.d_rinv_tabs));
+        }
     }
     return TD_OK;
 }
@@ -1101,7 +1216,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                     std::vector<int> n;
                     for (auto& gs : kv.second)
                         push_seg(t, n, gs.first->d_rowfwd, (int)gs.first->rowfwd.size(), gs.second->slot_base,
-                                 nullptr, gs.second->ws);
+                                 (const void*)gs.second->plan->d_lp, gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
                         e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, st)
                                 : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, st);
@@ -1120,7 +1235,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                     std::vector<int> n;
                     for (auto& gs : kv.second)
                         push_seg(t, n, gs.first->d_rinv[a], (int)gs.first->rinv[a].size(),
-                                 gs.second->slot_base, (const void*)gs.first->d_contribs,
+                                 gs.second->slot_base, (const void*)gs.first->d_rinv_tabs,
                                  gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
                         e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st)
@@ -1139,12 +1254,12 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
     return TD_OK;
 }
 
-td_status fill_ptrs(const td_request& q, int nlevels, std::vector<void*>& v, size_t base)
+td_status fill_ptrs(const td_request& q, int npatches, std::vector<void*>& v, size_t base)
 {
     if (!q.sigma || !q.fx || !q.fy) return fail(TD_EINVAL, "sigma, fx and fy are required");
-    for (int l = 0; l < nlevels; ++l) {
+    for (int l = 0; l < npatches; ++l) {
         if (!q.sigma[l] || !q.fx[l] || !q.fy[l])
-            return fail(TD_EINVAL, "NULL sigma/fx/fy pointer at level " + std::to_string(l));
+            return fail(TD_EINVAL, "NULL sigma/fx/fy pointer of patch " + std::to_string(l));
         v[base + 5 * l + 0] = (void*)q.sigma[l];
         v[base + 5 * l + 1] = q.dsdx ? (void*)q.dsdx[l] : nullptr;
         v[base + 5 * l + 2] = q.dsdy ? (void*)q.dsdy[l] : nullptr;
@@ -1300,8 +1415,8 @@ extern "C" td_status td_solve(const td_request* req, void* stream)
     td_plan* P = req->plan;
     DeviceGuard g(P->ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    std::vector<void*> v(5 * P->nlevels, nullptr);
-    TD_TRY(fill_ptrs(*req, P->nlevels, v, 0));
+    std::vector<void*> v(5 * P->npatches, nullptr);
+    TD_TRY(fill_ptrs(*req, P->npatches, v, 0));
     if (!P->ws) TD_TRY(P->ctx->alloc(P->ws_bytes, &P->ws));
     // one solve: the field pointers travel in the kernel arguments
     static_assert(5 * TD_MAX_LEVELS <= TD_KARG_PTRS, "kernel-argument pointer table too small");
@@ -1348,7 +1463,7 @@ extern "C" td_status td_batch_create(td_context* ctx, int32_t count, td_plan* co
         B->plans.push_back(p);
         ws_off.push_back(B->ws_bytes);
         B->mem.push_back({p, (int)B->nslots, nullptr});
-        B->nslots += 5 * p->nlevels;
+        B->nslots += 5 * p->npatches;
         B->ws_bytes += (p->ws_bytes + 255) & ~size_t(255);
     }
     td_status st = ctx->alloc(B->ws_bytes, &B->ws);
@@ -1374,7 +1489,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
     std::vector<void*> v(B->nslots, nullptr);
     for (size_t k = 0; k < B->plans.size(); ++k) {
         if (reqs[k].plan != B->plans[k]) return fail(TD_EINVAL, "request plan does not match the batch");
-        TD_TRY(fill_ptrs(reqs[k], B->plans[k]->nlevels, v, B->mem[k].slot_base));
+        TD_TRY(fill_ptrs(reqs[k], B->plans[k]->npatches, v, B->mem[k].slot_base));
     }
     if (use_graph && !B->exec) {
         // Capture once on a private stream; the pointer-table copy stays
@@ -1561,7 +1676,7 @@ void server_loop(td_server* S)
                 }
                 slot->ws.push_back({ws, got});
                 mem.push_back({T.plan, (int)nslots, (char*)ws});
-                nslots += 5 * T.plan->nlevels;
+                nslots += 5 * T.plan->npatches;
                 pick.push_back(*it);
                 it = S->queue.erase(it);
             }
@@ -1645,8 +1760,8 @@ extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32
     const td_plan* P = req->plan;
     Ticket T;
     T.plan = req->plan;
-    T.ptrs.assign(5 * P->nlevels, nullptr);
-    TD_TRY(fill_ptrs(*req, P->nlevels, T.ptrs, 0));
+    T.ptrs.assign(5 * P->npatches, nullptr);
+    TD_TRY(fill_ptrs(*req, P->npatches, T.ptrs, 0));
     T.need = (P->ws_bytes + 255) & ~size_t(255);
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->ctx->budget && T.need > S->ctx->budget) {
@@ -1807,7 +1922,7 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
     for (int M = 64; M <= max_M && result == TD_OK; M *= 2) {
         // a two-level hierarchy whose lattices have length M exercises all passes
         const int n = M / 2;
-        td_level lv[2] = {{n, 0, 0}, {n, n / 2, n / 2}};
+        td_patch lv[2] = {{0, n, 0, 0}, {1, n, n / 2, n / 2}};
         td_hierarchy h{-1.0, -1.0, 2.0 / n, 2, 2, lv};
         const size_t es = dt == TD_F64 ? 8 : 4;
         void* bufs[10] = {};
@@ -1948,15 +2063,16 @@ extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
         const int M = g.M, H = M / 2 + 1;
         for (auto& j : g.rowfwd) {
             // source values in range (rows x columns), spectrum rows written
+            const LevelG& S = P->lv[j.lvl];
             int cols = 0;
             for (int lc = 0; lc < M; ++lc) {
                 const int c = j.m * lc + j.col_off;
-                cols += (c >= 0 && c < j.n_src) ? 1 : 0;
+                cols += (c >= 0 && c < S.nx) ? 1 : 0;
             }
             int rows = 0;
             for (int r = j.row0; r < j.row0 + j.nrow; ++r) {
                 const int sr = j.m * (j.lr_first + r) + j.row_off;
-                rows += (sr >= 0 && sr < j.n_src) ? 1 : 0;
+                rows += (sr >= 0 && sr < S.ny) ? 1 : 0;
             }
             bytes[P_ROWFWD] += (double)rows * cols * rs + (double)H * j.nrow * cs;
         }

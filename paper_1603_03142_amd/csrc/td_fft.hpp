@@ -149,12 +149,28 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 {
     constexpr int B = 8 / R;          // butterflies per thread
     constexpr int STRIDE = M / R;     // distance between butterfly inputs
+    // For M >= 64 every read of a thread sits at a compile-time offset from
+    // lds_pos(lane) (the offsets are multiples of 8), and every write of a
+    // butterfly at offset r NS + (r NS)/8 from lds_pos(base): one address
+    // per thread and butterfly, the rest immediate offsets.
+    constexpr bool LIN = M >= 64;
     cpx<T> v[B][R];
+    if constexpr (LIN) {
+        const cpx<T>* rp = x + lds_pos(lane);
 #pragma unroll
-    for (int q = 0; q < B; ++q) {
-        const int j = lane + q * (M / 8);
+        for (int q = 0; q < B; ++q)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos(j + r * STRIDE)];
+            for (int r = 0; r < R; ++r) {
+                const int c = q * (M / 8) + r * STRIDE;
+                v[q][r] = rp[c + c / 8];
+            }
+    } else {
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int j = lane + q * (M / 8);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos(j + r * STRIDE)];
+        }
     }
     seq_sync<M>();
 #pragma unroll
@@ -172,8 +188,14 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
         }
         dftR<T, R, INV>(v[q]);
         const int base = (j / NS) * NS * R + k;
+        if constexpr (LIN) {
+            cpx<T>* wp = x + lds_pos(base);
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[lds_pos(base + r * NS)] = v[q][r];
+            for (int r = 0; r < R; ++r) wp[r * NS + (r * NS) / 8] = v[q][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[lds_pos(base + r * NS)] = v[q][r];
+        }
     }
     seq_sync<M>();
 }

@@ -19,17 +19,31 @@
 
 namespace td {
 
+#define TD_PATCHES_PER_LEVEL 8
+
+// The patches of one level in its window coordinates (the window is the
+// bounding rectangle of the level's patches; cells of the window outside
+// every patch are not part of the level), and the squares covered by the
+// next finer level's patches.  One per level and plan, in device memory.
+struct LevelPatches {
+    int32_t np, nc;
+    int32_t pi0[TD_PATCHES_PER_LEVEL], pj0[TD_PATCHES_PER_LEVEL];  // patch origins
+    int32_t pn[TD_PATCHES_PER_LEVEL];                             // patch sides
+    int32_t pslot[TD_PATCHES_PER_LEVEL];   // pointer-table slot of the patch's field 0
+    int32_t ci0[TD_PATCHES_PER_LEVEL], cj0[TD_PATCHES_PER_LEVEL];  // covered squares
+    int32_t cn[TD_PATCHES_PER_LEVEL];
+};
+
 struct RowFwdJob {
-    int32_t src_slot;   // pointer-table slot of the source field
-    int32_t n_src;      // source array is n_src x n_src
+    int32_t lvl;        // source level (index into the plan's LevelPatches)
+    int32_t f;          // source field: pointer slot = pslot[patch] + f
     int32_t m;          // lattice -> source decimation
-    int32_t row_off;    // source row = m * lattice_row + row_off
+    int32_t row_off;    // source row = m * lattice_row + row_off (window coords)
     int32_t col_off;    // source col = m * lattice_col + col_off
     int32_t lr_first;   // lattice row of stored row 0
     int32_t ld;         // stored rows per spectral column
     int32_t row0;       // first stored row of this job
     int32_t nrow;       // rows of this job
-    int32_t cov_i0, cov_i1, cov_j0, cov_j1;  // covered source cells, half-open
     int32_t pad;
     double scale;       // multiplies every value (slope scaling)
     int64_t out;        // workspace byte offset: complex [M/2+1][ld]
@@ -86,14 +100,19 @@ struct RowInvContrib {
 };
 
 struct RowInvJob {
-    int32_t n_t, ox_t, oy_t;    // target level size and offsets
+    int32_t lvl;                // target level (index into the LevelPatches)
+    int32_t nx_t, ny_t;         // target window size
+    int32_t ox_t, oy_t;         // target window origin (level cells)
     int32_t y0, ny;             // target rows of this job
-    int32_t out_slot;           // fx slot; fy = out_slot + 1
-    int32_t cov_i0, cov_i1, cov_j0, cov_j1;  // covered target cells
     int32_t c0, nc;             // contributions
     int32_t accumulate;         // 0: write (masking covered cells), 1: add
     int32_t x0, nx;             // target columns of this job (nx <= 2M)
-    int32_t pad;
+};
+
+// Auxiliary table of a row-inverse launch segment.
+struct RowInvTables {
+    const RowInvContrib* contribs;
+    const LevelPatches* levels;
 };
 
 // Kernel-table request: one phase of one (M, case, m) key, written as six

@@ -132,15 +132,17 @@ __device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __rest
 // Pass 1: zero-padded real row FFTs, transposed write
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__device__ __forceinline__ T fetch_src(const T* __restrict__ src, const RowFwdJob& J, int lr,
-                                       int lc)
+// Patch tables are read through global-address-space pointers (uniform per
+// job, so the loads are scalar).
+typedef const __attribute__((address_space(1))) LevelPatches* gpatches;
+
+// Is window cell (i, j) of a level covered by a patch of the next finer level?
+__device__ __forceinline__ bool covered(gpatches L, int i, int j)
 {
-    const int srow = J.m * lr + J.row_off;
-    const int scol = J.m * lc + J.col_off;
-    if (srow < 0 || srow >= J.n_src || scol < 0 || scol >= J.n_src) return (T)0;
-    if (scol >= J.cov_i0 && scol < J.cov_i1 && srow >= J.cov_j0 && srow < J.cov_j1) return (T)0;
-    return (T)(J.scale * (double)src[(size_t)srow * J.n_src + scol]);
+    bool c = false;
+    for (int k = 0; k < L->nc; ++k)
+        c |= i >= L->ci0[k] && i < L->ci0[k] + L->cn[k] && j >= L->cj0[k] && j < L->cj0[k] + L->cn[k];
+    return c;
 }
 
 // C = blockDim/(M/8) complex sequences; sequence p carries stored rows
@@ -161,16 +163,28 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     constexpr int SP = lds_stride(M);
     cpx<T>* tw = buf + C * SP;
     stage_twiddles<T, M>(tw, tw_g);
-    const int slot = slot_base + J.src_slot;
-    const T* src = reinterpret_cast<const T*>(fp.n ? fp.p[slot] : ptrs[slot]);
+    // source cells: window cell (m lc + col_off, m lr + row_off) of level
+    // J.lvl, taken from the patch that holds it, zero where no patch does
+    // or a finer patch covers it
+    gpatches L = (gpatches)aux + J.lvl;
+    const int np = L->np;
     const int rend = J.row0 + J.nrow;
     for (int idx = threadIdx.x; idx < C * M; idx += blockDim.x) {
         const int p = idx / M, lc = idx % M;
         const int s0 = J.row0 + 2 * p;
+        const int scol = J.m * lc + J.col_off;
+        const int sr0 = J.m * (J.lr_first + s0) + J.row_off, sr1 = sr0 + J.m;
         T a = 0, b = 0;
-        if (src) {
-            if (s0 < rend) a = fetch_src(src, J, J.lr_first + s0, lc);
-            if (s0 + 1 < rend) b = fetch_src(src, J, J.lr_first + s0 + 1, lc);
+        for (int k = 0; k < np; ++k) {
+            const int slot = slot_base + L->pslot[k] + J.f;
+            const T* src = reinterpret_cast<const T*>(fp.n ? fp.p[slot] : ptrs[slot]);
+            const int n = L->pn[k], i = scol - L->pi0[k];
+            if (!src || i < 0 || i >= n) continue;
+            const int j0 = sr0 - L->pj0[k], j1 = sr1 - L->pj0[k];
+            if (s0 < rend && j0 >= 0 && j0 < n && !covered(L, scol, sr0))
+                a = (T)(J.scale * (double)src[(size_t)j0 * n + i]);
+            if (s0 + 1 < rend && j1 >= 0 && j1 < n && !covered(L, scol, sr1))
+                b = (T)(J.scale * (double)src[(size_t)j1 * n + i]);
         }
         buf[p * SP + lds_pos(lc)] = cpx<T>{a, b};
     }
@@ -530,7 +544,9 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     const void* aux;
     char* ws;
     const RowInvJob J = segs.find(xcd_block(blockIdx.x, gridDim.x), &slot_base, &aux, &ws);
-    const RowInvContrib* __restrict__ contribs = reinterpret_cast<const RowInvContrib*>(aux) + J.c0;
+    const RowInvTables tabs = *reinterpret_cast<const RowInvTables*>(aux);
+    const RowInvContrib* __restrict__ contribs = tabs.contribs + J.c0;
+    gpatches L = (gpatches)tabs.levels + J.lvl;
     int nitems = 0;
     for (int k = 0; k < J.nc; ++k) nitems += 1 << contribs[k].mshift;
     constexpr int NQ = 16;  // nx <= 2M = 16 M/8 <= 16 G M/8
@@ -599,25 +615,32 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
         }
         __syncthreads();
     }
+    // outputs: window cell (ii, row) goes to the patch that holds it (none:
+    // not part of the level); cells covered by a finer patch are written 0
     typedef __attribute__((address_space(1))) T* gout;
-    const int slot = slot_base + J.out_slot;
-    gout fx = (gout)(fp.n ? fp.p[slot] : ptrs[slot]);
-    gout fy = (gout)(fp.n ? fp.p[slot + 1] : ptrs[slot + 1]);
     const int row = J.y0 + crow;
     if (crow >= J.ny) return;
+    for (int k = 0; k < L->np; ++k) {
+        const int slot = slot_base + L->pslot[k] + 3;
+        gout fx = (gout)(fp.n ? fp.p[slot] : ptrs[slot]);
+        gout fy = (gout)(fp.n ? fp.p[slot + 1] : ptrs[slot + 1]);
+        const int n = L->pn[k], j = row - L->pj0[k];
+        if (j < 0 || j >= n) continue;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int ii0 = t + q * GT;
-        if (ii0 >= J.nx) break;
-        const int ii = J.x0 + ii0;
-        const bool cov = ii >= J.cov_i0 && ii < J.cov_i1 && row >= J.cov_j0 && row < J.cov_j1;
-        const size_t o = (size_t)row * J.n_t + ii;
-        if (!J.accumulate) {
-            if (fx) fx[o] = cov ? (T)0 : accx[q];
-            if (fy) fy[o] = cov ? (T)0 : accy[q];
-        } else if (!cov) {
-            if (fx) fx[o] += accx[q];
-            if (fy) fy[o] += accy[q];
+        for (int q = 0; q < NQ; ++q) {
+            const int ii0 = t + q * GT;
+            if (ii0 >= J.nx) break;
+            const int ii = J.x0 + ii0, i = ii - L->pi0[k];
+            if (i < 0 || i >= n) continue;
+            const bool cov = covered(L, ii, row);
+            const size_t o = (size_t)j * n + i;
+            if (!J.accumulate) {
+                if (fx) fx[o] = cov ? (T)0 : accx[q];
+                if (fy) fy[o] = cov ? (T)0 : accy[q];
+            } else if (!cov) {
+                if (fx) fx[o] += accx[q];
+                if (fy) fy[o] += accy[q];
+            }
         }
     }
 }

@@ -31,6 +31,7 @@ __all__ = [
     "Patch", "Hierarchy", "disk_dn", "clump", "LognormalField", "sample_fields",
     "cell_centres", "covered_mask", "sample_targets", "config1", "config2", "config3",
     "config4", "config5_requests", "nested_hierarchy", "snap_offsets", "example_hierarchy",
+    "two_disks", "two_disks_gradient", "random_patches",
 ]
 
 
@@ -373,12 +374,88 @@ def request_sigma(order: int, alpha: float, fseed: int, h0: float, modes: int = 
     return product(disk_dn(order, alpha), LognormalField(fseed, 0.2, 4 * h0, modes))
 
 
+def _snap(v: float, h: float) -> int:
+    return int(math.floor(v / h + 0.5))
+
+
 def example_hierarchy(example: int, n: int) -> Hierarchy:
-    """Grids of the paper's Examples 1 and 2 (Section 3): N cells per side on
-    every level, level 0 on [-1,1]^2, level l on [-2^-l, 2^-l]^2."""
+    """Grids of the paper's Examples 1-4 (Section 3), ratio 2, level 0 on
+    [-1,1]^2 with N cells per side (h_l = 2^(1-l) / N).
+      1: level 1 = [-1/2,1/2]^2 (N cells).
+      2: level 1 as in 1, level 2 = [-1/4,1/4]^2 (N cells).
+      3: level 1 = [-0.75,-0.25] x [-0.25,0.25] and [0.25,0.75] x [-0.25,0.25]
+         (N/2 cells each; N a multiple of 8).
+      4: level 2 = the two squares of 3 (N cells each); level 1 = squares of
+         side 0.8 around them, [-0.9,-0.1] x [-0.4,0.4] and mirror, whose
+         edges lie on no 2^k lattice: each is snapped to the nearest level-0
+         nodes (side rounded to a whole number of level-0 cells)."""
+    h0 = 2.0 / n
     if example == 1:
-        return nested_hierarchy(-1.0, -1.0, 2.0 / n, 2, [(n, 0, 0), (n, n // 2, n // 2)])
+        return nested_hierarchy(-1.0, -1.0, h0, 2, [(n, 0, 0), (n, n // 2, n // 2)])
     if example == 2:
-        return nested_hierarchy(-1.0, -1.0, 2.0 / n, 2,
+        return nested_hierarchy(-1.0, -1.0, h0, 2,
                                 [(n, 0, 0), (n, n // 2, n // 2), (n, 3 * n // 2, 3 * n // 2)])
+    if example in (3, 4):
+        if n % 8:
+            raise ValueError("N must be a multiple of 8")
+        pats = [Patch(0, n, 0, 0)]
+        h1, h2 = h0 / 2, h0 / 4
+        if example == 3:
+            for x0 in (-0.75, 0.25):
+                pats.append(Patch(1, n // 2, _snap(x0 + 1.0, h1), _snap(-0.25 + 1.0, h1)))
+            return Hierarchy(-1.0, -1.0, h0, 2, pats)
+        side = _snap(0.8, h0)  # level-0 cells
+        for x0 in (-0.9, 0.1):
+            pats.append(Patch(1, 2 * side, 2 * _snap(x0 + 1.0, h0), 2 * _snap(-0.4 + 1.0, h0)))
+        for x0 in (-0.75, 0.25):
+            pats.append(Patch(2, n, _snap(x0 + 1.0, h2), _snap(-0.25 + 1.0, h2)))
+        return Hierarchy(-1.0, -1.0, h0, 2, pats)
     raise ValueError(example)
+
+
+TWO_DISKS = ((-0.5, 0.0), (0.5, 0.0))
+TWO_DISK_ALPHA = math.sqrt(2.0) / 4
+
+
+def two_disks(n: int = 5, alpha: float = TWO_DISK_ALPHA):
+    """Examples 3-4: two sigma_{D_n} disks centred at (-1/2, 0), (1/2, 0)."""
+    return total(*[disk_dn(n, alpha, cx=cx, cy=cy) for cx, cy in TWO_DISKS])
+
+
+def two_disks_gradient(n: int = 5, alpha: float = TWO_DISK_ALPHA):
+    gs = [disk_dn_gradient(n, alpha, cx=cx, cy=cy) for cx, cy in TWO_DISKS]
+
+    def g(x, y):
+        ax, ay = gs[0](x, y)
+        bx, by = gs[1](x, y)
+        return ax + bx, ay + by
+    return g
+
+
+def random_patches(seed: int, n0: int = 32, levels: int = 3, per_level: int = 2,
+                   ratio: int = 2, max_patches: int = 8) -> Hierarchy:
+    """Several non-overlapping aligned square patches per level, each inside
+    one patch of the level above (seeded; at most max_patches in all)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    while ratio ** (levels - 1) > 16:
+        levels -= 1
+    pats = [Patch(0, n0, 0, 0)]
+    parents = [pats[0]]
+    for lev in range(1, levels):
+        placed = []
+        for _ in range(per_level * 8):
+            if len(placed) == per_level or len(pats) + len(placed) == max_patches:
+                break
+            par = parents[int(rng.integers(0, len(parents)))]
+            w = int(rng.integers(2, max(3, par.n // 2) + 1))      # parent cells
+            kx = int(rng.integers(0, par.n - w + 1))
+            ky = int(rng.integers(0, par.n - w + 1))
+            cand = Patch(lev, ratio * w, ratio * (par.ox + kx), ratio * (par.oy + ky))
+            if all(cand.ox + cand.n <= q.ox or q.ox + q.n <= cand.ox or
+                   cand.oy + cand.n <= q.oy or q.oy + q.n <= cand.oy for q in placed):
+                placed.append(cand)
+        if not placed:
+            break
+        pats.extend(placed)
+        parents = placed
+    return Hierarchy(-1.0, -1.0, 2.0 / n0, ratio, pats)

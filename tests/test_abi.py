@@ -31,10 +31,12 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in L.td_version()
 
 
-def _check(levels, ratio=2, h0=2 / 16):
+def _check(levels, ratio=2, h0=2 / 16, patches=None):
+    """levels: one (n, ox, oy) patch per level; patches: (level, n, ox, oy)."""
     from paper_1603_03142_amd import _binding as B
-    arr = (B.td_level * len(levels))(*[B.td_level(*lv) for lv in levels])
-    h = B.td_hierarchy(-1.0, -1.0, h0, ratio, len(levels), ctypes.cast(arr, ctypes.POINTER(B.td_level)))
+    pats = patches if patches is not None else [(l, *lv) for l, lv in enumerate(levels)]
+    arr = (B.td_patch * len(pats))(*[B.td_patch(*p) for p in pats])
+    h = B.td_hierarchy(-1.0, -1.0, h0, ratio, len(pats), ctypes.cast(arr, ctypes.POINTER(B.td_patch)))
     return B.lib().td_hierarchy_check(ctypes.byref(h))
 
 
@@ -54,9 +56,20 @@ def test_hierarchy_validation_codes():
     assert _check([(2049, 0, 0)]) == B.TD_EINVAL                    # beyond TD_MAX_N
     assert _check([(16, 0, 0), (16, 56, 8)], ratio=4) == B.TD_ENEST
     assert _check([(16, 0, 0), (16, 16, 24)], ratio=4) == B.TD_OK
-    assert _check([(8, 0, 0)] * 9) == B.TD_EINVAL                   # too many levels
-    msg = B.lib().td_last_error().decode()
-    assert "nlevels" in msg
+    assert _check([(8, 0, 0)] * 9) == B.TD_EINVAL                   # too many patches
+    assert "npatches" in B.lib().td_last_error().decode()
+    # several patches per level
+    two = [(0, 16, 0, 0), (1, 8, 4, 12), (1, 8, 20, 12)]
+    assert _check(None, patches=two) == B.TD_OK
+    assert _check(None, patches=[(0, 16, 0, 0), (1, 8, 4, 12), (1, 8, 10, 12)]) == B.TD_EINVAL  # overlap
+    assert "overlaps" in B.lib().td_last_error().decode()
+    assert _check(None, patches=[(0, 16, 0, 0), (1, 8, 4, 12), (1, 8, 28, 12)]) == B.TD_ENEST   # outside
+    assert _check(None, patches=[(0, 16, 0, 0), (1, 8, 4, 12), (0, 8, 0, 0)]) == B.TD_EINVAL    # order
+    assert _check(None, patches=[(0, 16, 0, 0), (2, 8, 4, 12)]) == B.TD_EINVAL                  # level gap
+    # a level-2 patch inside the second level-1 patch only
+    three = two + [(2, 8, 44, 28)]
+    assert _check(None, patches=three) == B.TD_OK
+    assert _check(None, patches=two + [(2, 8, 30, 28)]) == B.TD_ENEST  # straddles both
 
 
 def test_snap_matches_python_generator():
@@ -65,8 +78,8 @@ def test_snap_matches_python_generator():
     from paper_1603_03142_amd import _binding as B
     h0 = 2.0 / 512
     want = synth.snap_offsets(-1.0, -1.0, h0, 2, [512] * 4, [(0.3, 0.0)] * 3)
-    lv = (B.td_level * 4)(*[B.td_level(512, 0, 0) for _ in range(4)])
-    h = B.td_hierarchy(-1.0, -1.0, h0, 2, 4, ctypes.cast(lv, ctypes.POINTER(B.td_level)))
+    lv = (B.td_patch * 4)(*[B.td_patch(l, 512, 0, 0) for l in range(4)])
+    h = B.td_hierarchy(-1.0, -1.0, h0, 2, 4, ctypes.cast(lv, ctypes.POINTER(B.td_patch)))
     cx = (ctypes.c_double * 3)(0.3, 0.3, 0.3)
     cy = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
     assert B.lib().td_hierarchy_snap(ctypes.byref(h), lv, cx, cy) == B.TD_OK
@@ -129,3 +142,20 @@ def test_plan_check_workloads():
         assert td.check_plan(h, "f32") > 0
     for h, _ in synth.config4(count=16):
         assert td.check_plan(h, "f32") > 0
+
+
+def test_plan_check_random_patches():
+    """The same host-side proof on hierarchies with several patches per
+    level (ratios 2 and 4, up to 4 levels, at most 8 patches)."""
+    import paper_1603_03142_amd as td
+    import synth
+    multi = 0
+    for seed in range(120):
+        h = synth.random_patches(seed, n0=[16, 24, 32, 40][seed % 4], levels=2 + seed % 3,
+                                 per_level=1 + seed % 3, ratio=[2, 4][seed % 2])
+        multi += any(sum(p.level == l for p in h.patches) > 1 for l in range(4))
+        for dt in ("f32", "f64"):
+            assert td.check_plan(h, dt) > 0
+    assert multi > 50
+    for ex, n in ((3, 32), (3, 1024), (4, 64), (4, 512)):
+        assert td.check_plan(synth.example_hierarchy(ex, n), "f32") > 0
