@@ -429,3 +429,33 @@ def test_polyphase_identities(m):
             lhs3 = sum(a3[n] * z ** n for n in range(na3) if n % m == k)
             bz = sum(b[i] * z ** i for i in range(len(b)) if i % m == k)
             assert abs(lhs3 - cz1 * bz) < 1e-12 * (1 + abs(lhs3))
+
+
+def test_example3_table3_two_patches():
+    """Several patches on one level: the paper's Example 3 (two sigma_{D5}
+    disks, two level-1 patches) at N = 32 against Table 3's E1 columns."""
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "table3_example3_e1.txt")):
+        if not line.startswith("#") and line.strip():
+            n, a, b = line.split()
+            rows[int(n)] = (float(a), float(b))
+    hier = synth.example_hierarchy(3, 32)
+    assert sum(p.level == 1 for p in hier.patches) == 2
+    alpha = synth.TWO_DISK_ALPHA
+    sig, dx, dy = synth.sample_fields(hier, synth.two_disks(), "analytic", synth.two_disks_gradient())
+    fx, fy = oracle.forces(hier, sig, dx, dy)
+    ex, ey = [], []
+    for k, p in enumerate(hier.patches):
+        X, Y = synth.cell_centres(hier, p)
+        act = ~synth.covered_mask(hier, p)
+        ax = np.zeros(act.sum())
+        ay = np.zeros(act.sum())
+        for cx, cy in synth.TWO_DISKS:
+            bx, by = analytic.force_xy(5, X[act], Y[act], alpha, cx=cx, cy=cy)
+            ax += bx
+            ay += by
+        ex.append(np.abs(fx[k][act] - ax))
+        ey.append(np.abs(fy[k][act] - ay))
+    ex, ey = np.concatenate(ex).mean(), np.concatenate(ey).mean()
+    assert ex == pytest.approx(rows[32][0], rel=0.07)
+    assert ey == pytest.approx(rows[32][1], rel=0.07)
