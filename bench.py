@@ -11,7 +11,8 @@ Inputs are resident in HBM before the timed region; kernel spectra are
 resident (plan built beforehand).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
-                  [--workload two-level-256|single-64|four-level-512|batch-64|serve]
+                  [--workload two-level-256|single-64|four-level-512|example3-512|
+                              example1-1024|batch-64|serve]
                   [--mode eager|graph] [--no-cpu] [--tune DB]
 
 Other workloads: batch-64 = 64 independent disks (base N in {64..512}, 1-3
@@ -81,6 +82,12 @@ def workload(name):
         hier, fn = synth.config1()
     elif name == "four-level-512":
         hier, fn = synth.config3()
+    elif name == "example3-512":
+        # the paper's Example 3: two sigma_D5 disks, two level-1 patches
+        hier, fn = synth.example_hierarchy(3, 512), synth.two_disks()
+    elif name == "example1-1024":
+        # the paper's Example 1 at its largest size (convergence study)
+        hier, fn = synth.example_hierarchy(1, 1024), synth.disk_dn(5, 0.85)
     else:
         raise SystemExit(f"unknown workload {name}")
     return hier, fn
@@ -402,8 +409,8 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": args.workload, "levels": len(hier.patches),
-                   "cells_per_level": [p.n for p in hier.patches], "ratio": hier.ratio,
+        "config": {"workload": args.workload, "levels": hier.nlevels,
+                   "patches": [[p.level, p.n] for p in hier.patches], "ratio": hier.ratio,
                    "cells_per_solve": cells, "mode": args.mode,
                    "plan_build_s": round(plan_s, 3), "autotune_s": tune_s},
         "roofline": roof,

@@ -19,15 +19,17 @@
  * exchanging x and y.
  *
  * Conventions
- *   - Level l has one square patch of n_l x n_l cells of side h0 / ratio^l.
- *     Its lower-left corner is (x0 + ox_l h_l, y0 + oy_l h_l): ox_l, oy_l are
- *     integer offsets in level-l cells from the level-0 origin (ox_0 = oy_0
- *     = 0).  Level l+1 must lie inside level l with its edges on level-l
+ *   - Level l holds one or more square patches of cells of side
+ *     h0 / ratio^l (ratio 2, 3 or 4); level 0 is a single patch.  A patch's
+ *     lower-left corner is (x0 + ox h_l, y0 + oy h_l): ox, oy are integer
+ *     offsets in level-l cells from the level-0 origin.  Every patch of
+ *     level l+1 lies inside one patch of level l with its edges on level-l
  *     nodes (Section 2.1: integer ratio between nested levels).
- *   - A cell covered by level l+1 is not part of level l's domain: its
- *     sigma / slopes are ignored, and its force outputs are written as 0.
- *   - Every field is row-major [j][i] (x fastest), n_l * n_l elements of the
- *     plan's dtype (float for TD_F32, double for TD_F64).
+ *   - A cell covered by a patch of level l+1 is not part of level l's
+ *     domain: its sigma / slopes are ignored, and its force outputs are
+ *     written as 0.
+ *   - Every field is row-major [j][i] (x fastest), n * n elements per patch
+ *     of the plan's dtype (float for TD_F32, double for TD_F64).
  *   - Forces have the units of sigma (G = 1): F = -grad Phi, attractive.
  *
  * Ownership and errors
@@ -82,7 +84,7 @@ typedef struct {
 typedef struct {
     double x0, y0;           /* lower-left corner of level 0              */
     double h0;               /* level-0 cell side                         */
-    int32_t ratio;           /* refinement ratio between levels: 2 or 4   */
+    int32_t ratio;           /* refinement ratio between levels: 2, 3, 4  */
     int32_t npatches;        /* 1 .. TD_MAX_PATCHES                       */
     const td_patch* patches; /* [npatches], grouped by level              */
 } td_hierarchy;

@@ -259,8 +259,9 @@ SegTable<Job> single_seg(const Job* jobs, int n, int slot_base, const void* aux,
 }
 
 // Build (once per context) the kernel spectra of one (M, kind, m, dtype).
-// Stored phases: kind 1 -> (0,0); kinds 2/3 -> (kx, ky) in [0, m/2)^2, the
-// others being mirror images.  Layout [phase][X][M/2+1][M] complex.
+// Stored phases: kind 1 -> (0,0); kinds 2/3 -> (kx, ky) in [0, hp)^2 with
+// hp = ceil(m/2), the others being mirror images (for odd m the middle
+// phase of each axis is its own mirror).  Layout [phase][X][M/2+1][M].
 td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const SpecEntry** out)
 {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -270,7 +271,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
         *out = &it->second;
         return TD_OK;
     }
-    const int hp = (kind == 1) ? 1 : m / 2;
+    const int hp = (kind == 1) ? 1 : (m + 1) / 2;
     const int nphase = hp * hp;
     const size_t NCOL = M / 2 + 1;
     const size_t per_phase = 6 * NCOL * (size_t)M;
@@ -423,8 +424,8 @@ extern "C" td_status td_hierarchy_check(const td_hierarchy* h)
 {
     int L = 0;
     TD_TRY(patch_levels(h, &L));
-    if (h->ratio != 2 && h->ratio != 4)
-        return fail(TD_EUNSUPPORTED, "refinement ratio must be 2 or 4");
+    if (h->ratio < 2 || h->ratio > 4)
+        return fail(TD_EUNSUPPORTED, "refinement ratio must be 2, 3 or 4");
     if (!(h->h0 > 0) || !std::isfinite(h->h0) || !std::isfinite(h->x0) || !std::isfinite(h->y0))
         return fail(TD_EINVAL, "h0 must be positive and x0, y0, h0 finite");
     const td_patch* P = h->patches;
@@ -476,7 +477,7 @@ extern "C" td_status td_hierarchy_snap(td_hierarchy* h, td_patch* patches, const
 {
     if (!h || !patches || (h->npatches > 1 && (!cx || !cy))) return fail(TD_EINVAL, "NULL argument");
     if (h->npatches < 1 || h->npatches > TD_MAX_LEVELS) return fail(TD_EINVAL, "bad npatches");
-    if (h->ratio != 2 && h->ratio != 4) return fail(TD_EUNSUPPORTED, "ratio must be 2 or 4");
+    if (h->ratio < 2 || h->ratio > 4) return fail(TD_EUNSUPPORTED, "ratio must be 2, 3 or 4");
     for (int l = 0; l < h->npatches; ++l)
         if (patches[l].level != l) return fail(TD_EINVAL, "snap takes one patch per level, patch l on level l");
     patches[0].ox = patches[0].oy = 0;
@@ -586,15 +587,32 @@ Group& group_for(std::vector<Group>& groups, int M)
     return groups.back();
 }
 
-// Enumerate the m*m polyphase phases so that the four mirror images of
-// each stored phase (sx, sy) in [0, m/2)^2 come one after another.
-void mirror_order(int m, int i, int* kx, int* ky)
+// Every polyphase phase (kx, ky) of ratio m, ordered so that the mirror
+// images of each stored phase (sx, sy) in [0, ceil(m/2))^2 come one after
+// another (two or one of them on an axis whose middle phase, odd m, is its
+// own mirror).
+std::vector<std::pair<int, int>> phase_order(int m)
 {
-    const int h = m / 2;
-    const int base = i / 4, mir = i % 4;
-    const int sx = base % h, sy = base / h;
-    *kx = (mir & 1) ? m - 1 - sx : sx;
-    *ky = (mir & 2) ? m - 1 - sy : sy;
+    std::vector<std::pair<int, int>> out;
+    const int hp = (m + 1) / 2;
+    for (int sy = 0; sy < hp; ++sy)
+        for (int sx = 0; sx < hp; ++sx)
+            for (int mir = 0; mir < 4; ++mir) {
+                const int kx = (mir & 1) ? m - 1 - sx : sx, ky = (mir & 2) ? m - 1 - sy : sy;
+                if (((mir & 1) && kx == sx) || ((mir & 2) && ky == sy)) continue;  // self-mirror
+                out.push_back({kx, ky});
+            }
+    return out;
+}
+
+// Stored spectra of phase (kx, ky) within an entry, and the mirror bits
+// that map them onto it.
+const void* phase_kernels(const SpecEntry* e, int m, int kx, int ky, size_t per_phase_bytes, int* flip)
+{
+    const int hp = (m + 1) / 2;
+    const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
+    *flip = (kx >= hp ? 1 : 0) | (ky >= hp ? 2 : 0);
+    return (const char*)e->ptr + (size_t)(sy * hp + sx) * per_phase_bytes;
 }
 
 
@@ -604,7 +622,7 @@ td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out
 {
     if (!P->dry) return spectra(P->ctx, M, kind, m, P->dt, out);
     static SpecEntry fake;
-    const int hp = kind == 1 ? 1 : m / 2;
+    const int hp = kind == 1 ? 1 : (m + 1) / 2;
     fake.ptr = (void*)(uintptr_t)4096;
     fake.nphase = hp * hp;
     fake.bytes = (size_t)hp * hp * 6 * (M / 2 + 1) * (size_t)M * elem_size(P->dt);
@@ -746,16 +764,14 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 TD_TRY(plan_spectra(P, G.M, 2, m, &k2));
                 const size_t per_phase = 6 * H * G.M;
                 // mirror images of one stored phase are adjacent
-                for (int pi = 0; pi < m * m; ++pi) {
-                    int kx, ky;
-                    mirror_order(m, pi, &kx, &ky);
+                for (const auto& ph : phase_order(m)) {
+                    const int kx = ph.first, ky = ph.second;
                     const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
                     const int lr_hi = floor_div(S.oy + S.ny - 1 - ky, m) - G.oy;
                     if (lr_hi < lr_lo) continue;
                     const int phase = ky * m + kx;
-                    const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
-                    const void* kern = (char*)k2->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
-                    const int flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
+                    int flip = 0;
+                    const void* kern = phase_kernels(k2, m, kx, ky, per_phase * es, &flip);
                     for (int f = 0; f < 3; ++f)
                         g.colins.push_back({ptr(ph_in[s][t] + ((size_t)phase * 3 + f) * H * nr), kern,
                                             nr, lr_lo, f, flip});
@@ -778,13 +794,11 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             TD_TRY(plan_spectra(P, G.M, 3, m, &k3));
             const size_t per_phase = 6 * H * G.M;
             const int out0 = (int)g.colouts.size();
-            for (int pi = 0; pi < m * m; ++pi) {
-                int kx, ky;
-                mirror_order(m, pi, &kx, &ky);
+            for (const auto& ph : phase_order(m)) {
+                const int kx = ph.first, ky = ph.second;
                 const int phase = ky * m + kx;
-                const int sx = std::min(kx, m - 1 - kx), sy = std::min(ky, m - 1 - ky);
-                const void* kern = (char*)k3->ptr + (size_t)(sy * (m / 2) + sx) * per_phase * es;
-                const int flip = (kx >= m / 2 ? 1 : 0) | (ky >= m / 2 ? 2 : 0);
+                int flip = 0;
+                const void* kern = phase_kernels(k3, m, kx, ky, per_phase * es, &flip);
                 for (int comp = 0; comp < 2; ++comp)
                     g.colouts.push_back({ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld), kern, ld,
                                          floor_div(T.oy, m) - G.oy, comp, flip});
@@ -826,7 +840,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             c.phase_stride = (int64_t)2 * (S.M / 2 + 1) * ld;
             c.comp_stride = (int64_t)(S.M / 2 + 1) * ld;
             c.m = m;
-            c.mshift = ilog2(m);
+            c.mshift = (m & (m - 1)) ? -1 : ilog2(m);  // -1: not a power of two
             c.ld = ld;
             c.lr_first = floor_div(T.oy, m) - S.oy;
             c.ox_s = S.ox;
@@ -971,7 +985,8 @@ td_status validate_jobs(td_plan* P)
                 if (j.oy_t < 0 || j.ox_t < 0) return bad("rinv offsets");
                 for (int k = 0; k < j.nc; ++k) {
                     const RowInvContrib& c = g.contribs[j.c0 + k];
-                    if (c.m < 1 || c.m > 16 || (1 << c.mshift) != c.m) return bad("rinv ratio");
+                    if (c.m < 1 || c.m > 16 || (c.mshift >= 0 ? (1 << c.mshift) != c.m : !(c.m & (c.m - 1))))
+                        return bad("rinv ratio");
                     // rows and columns reached by this job's targets
                     for (int rr : {j.y0, j.y0 + j.ny - 1}) {
                         const int gg = j.oy_t + rr, Jc = floor_div(gg, c.m);
@@ -2000,7 +2015,7 @@ extern "C" td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, i
     if (kind < 1 || kind > 3) return fail(TD_EINVAL, "kind must be 1, 2 or 3");
     if (kind == 1) m = 1;
     if (m < 1 || kx < 0 || ky < 0 || kx >= m || ky >= m) return fail(TD_EINVAL, "bad m or phase");
-    if (kind != 1 && (m % 2)) return fail(TD_EUNSUPPORTED, "m must be even");
+    if (kind != 1 && m > 16) return fail(TD_EUNSUPPORTED, "m must be at most 16");
     DeviceGuard dg(ctx->device);
     const size_t bytes = 6 * (size_t)M * M * sizeof(double);
     void* d = nullptr;

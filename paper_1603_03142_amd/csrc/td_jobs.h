@@ -96,7 +96,7 @@ struct RowInvContrib {
     int32_t ld;
     int32_t lr_first;      // lattice row of stored row 0
     int32_t ox_s, oy_s;    // lattice origin: offsets of the lattice's level
-    int32_t mshift;        // log2(m)
+    int32_t mshift;        // log2(m), or -1 when m is not a power of two
 };
 
 struct RowInvJob {

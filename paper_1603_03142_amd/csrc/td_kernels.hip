@@ -516,6 +516,12 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk)
     return (x + NXCD * (l / K)) * K + l % K;
 }
 
+// a / m for a >= 0: a shift when m = 2^sh (sh >= 0), else a division.
+__device__ __forceinline__ int ratio_div(int a, int m, int sh)
+{
+    return sh >= 0 ? a >> sh : a / m;
+}
+
 // A workgroup owns C target rows; each row's items -- (contribution, x-phase)
 // pairs, one complex-to-real row transform each -- run G at a time in the
 // row's G slots.  Spectra are read transposed ([kx][row]), rows fastest.
@@ -548,7 +554,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     const RowInvContrib* __restrict__ contribs = tabs.contribs + J.c0;
     gpatches L = (gpatches)tabs.levels + J.lvl;
     int nitems = 0;
-    for (int k = 0; k < J.nc; ++k) nitems += 1 << contribs[k].mshift;
+    for (int k = 0; k < J.nc; ++k) nitems += contribs[k].m;
     constexpr int NQ = 16;  // nx <= 2M = 16 M/8 <= 16 G M/8
     const int crow = threadIdx.x / GT, t = threadIdx.x % GT;
     T accx[NQ], accy[NQ];
@@ -560,10 +566,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
             int c = -1, kxp = 0, sh = 0, oxs = 0;
             if (it < nitems) {
                 int k = 0, rem = it;
-                while (rem >= (1 << contribs[k].mshift)) rem -= 1 << contribs[k].mshift, ++k;
+                while (rem >= contribs[k].m) rem -= contribs[k].m, ++k;
                 c = k;
                 kxp = rem;
-                sh = contribs[k].mshift;
+                sh = contribs[k].mshift >= 0 ? contribs[k].mshift : -contribs[k].m;
                 oxs = contribs[k].ox_s;
             }
             it_c[threadIdx.x] = c;
@@ -579,12 +585,11 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
             cpx<T> z{0, 0}, zr{0, 0};
             if (ci >= 0 && cc < J.ny) {
                 const RowInvContrib& Q = contribs[ci];
-                const int sh = Q.mshift;
                 const int gy = J.oy_t + J.y0 + cc;  // >= 0
-                const int Jc = gy >> sh, kyp = gy & ((1 << sh) - 1);
+                const int Jc = ratio_div(gy, Q.m, Q.mshift), kyp = gy - Jc * Q.m;
                 const int sr = Jc - Q.oy_s - Q.lr_first;
                 gptr<cpx<T>> P = (gptr<cpx<T>>)(ws + Q.base) +
-                                 (int64_t)((kyp << sh) + it_kxp[gg]) * Q.phase_stride;
+                                 (int64_t)(kyp * Q.m + it_kxp[gg]) * Q.phase_stride;
                 cpx<T> X = ldg<T>(P, (size_t)kx * Q.ld + sr);
                 cpx<T> Y = ldg<T>(P, Q.comp_stride + (size_t)kx * Q.ld + sr);
                 if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
@@ -600,15 +605,18 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
         __syncthreads();  // outputs gather from every slot of their row
         for (int gg = 0; gg < G; ++gg) {
             if (it_c[gg] < 0) break;
+            // it_sh: log2(m), or -m when m is not a power of two
             const int sh = it_sh[gg], kxp = it_kxp[gg], oxs = it_oxs[gg];
+            const int mm = sh >= 0 ? 1 << sh : -sh;
             const cpx<T>* rowv = A + (crow * G + gg) * SP;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int ii = t + q * GT;
                 if (ii >= J.nx) break;
                 const int gx = J.ox_t + J.x0 + ii;  // >= 0
-                if ((gx & ((1 << sh) - 1)) != kxp) continue;
-                const cpx<T> v = rowv[lds_pos((gx >> sh) - oxs)];
+                const int Ic = ratio_div(gx, mm, sh >= 0 ? sh : -1);
+                if (gx - Ic * mm != kxp) continue;
+                const cpx<T> v = rowv[lds_pos(Ic - oxs)];
                 accx[q] += v.re;
                 accy[q] += v.im;
             }

@@ -50,7 +50,10 @@ def test_hierarchy_validation_codes():
     assert _check([(16, 0, 0), (16, 18, 8)]) == B.TD_ENEST          # sticks out
     assert _check([(16, 0, 0), (34, 0, 0)]) == B.TD_ENEST           # wider than parent
     assert _check([(16, 2, 0)]) == B.TD_EINVAL                      # level-0 offset
-    assert _check([(16, 0, 0)], ratio=3) == B.TD_EUNSUPPORTED
+    assert _check([(16, 0, 0)], ratio=5) == B.TD_EUNSUPPORTED
+    assert _check([(18, 0, 0), (15, 12, 21)], ratio=3) == B.TD_OK
+    assert _check([(18, 0, 0), (15, 12, 20)], ratio=3) == B.TD_EALIGN       # off the lattice
+    assert _check([(9, 0, 0), (9, 3, 3), (9, 9, 9), (9, 27, 27)], ratio=3) == B.TD_EUNSUPPORTED  # 27x
     assert _check([(0, 0, 0)]) == B.TD_EINVAL
     assert _check([(2048, 0, 0)]) == B.TD_OK
     assert _check([(2049, 0, 0)]) == B.TD_EINVAL                    # beyond TD_MAX_N
@@ -151,8 +154,8 @@ def test_plan_check_random_patches():
     import synth
     multi = 0
     for seed in range(120):
-        h = synth.random_patches(seed, n0=[16, 24, 32, 40][seed % 4], levels=2 + seed % 3,
-                                 per_level=1 + seed % 3, ratio=[2, 4][seed % 2])
+        h = synth.random_patches(seed, n0=[16, 24, 36, 40][seed % 4], levels=2 + seed % 3,
+                                 per_level=1 + seed % 3, ratio=[2, 4, 3][seed % 3])
         multi += any(sum(p.level == l for p in h.patches) > 1 for l in range(4))
         for dt in ("f32", "f64"):
             assert td.check_plan(h, dt) > 0

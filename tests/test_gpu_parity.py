@@ -32,7 +32,9 @@ def ctx():
 # ---------------------------------------------------------------------------
 
 TABLE_CASES = [(16, 1, 1, 0, 0), (32, 1, 1, 0, 0), (16, 2, 2, 0, 0), (16, 2, 2, 1, 1),
-               (32, 2, 4, 1, 3), (16, 3, 2, 0, 1), (32, 3, 4, 3, 2), (16, 3, 2, 1, 1)]
+               (32, 2, 4, 1, 3), (16, 3, 2, 0, 1), (32, 3, 4, 3, 2), (16, 3, 2, 1, 1),
+               # odd ratio: half-integer Case-2 offsets, self-mirror middle phase
+               (16, 2, 3, 1, 1), (32, 2, 9, 7, 2), (16, 3, 3, 2, 0), (32, 3, 9, 4, 8)]
 
 
 @pytest.mark.parametrize("M,kind,m,kx,ky", TABLE_CASES)
@@ -57,8 +59,11 @@ def test_kernel_table_vs_oracle(ctx, M, kind, m, kx, ky):
             want[:, ny, nx] = c
     assert np.all(np.isfinite(got))
     scale = np.abs(want).max()
-    # a few ulp of the largest entry; the oracle itself is long double
-    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-14 * scale)
+    # a few ulp of the largest entry, times m: the antiderivatives (Section
+    # 2.1) grow with the corner coordinates, which reach m M / 2 cells, so the
+    # rounding of their four-corner difference grows with m (the oracle itself
+    # is long double)
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-14 * m * scale)
 
 
 # ---------------------------------------------------------------------------
@@ -85,6 +90,9 @@ HIERS = {
     "4lev": H([(16, 0, 0), (16, 8, 8), (16, 24, 20), (8, 60, 52)]),
     # m = 16 pair whose target spans more columns than 2M of the coarse lattice
     "ratio4_deep": H([(6, 0, 0), (20, 4, 4), (44, 44, 44)], ratio=4),
+    # odd ratio (m = 3, 9)
+    "ratio3_2lev": H([(18, 0, 0), (15, 12, 21)], ratio=3),
+    "ratio3_3lev": H([(12, 0, 0), (18, 9, 6), (27, 36, 30)], ratio=3),
 }
 
 

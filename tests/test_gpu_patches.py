@@ -44,12 +44,13 @@ def radial():
     return lambda r: np.where(r <= ALPHA, si(np.minimum(r, ALPHA)), so(np.maximum(r, ALPHA)))
 
 
-SEEDS = [(s, [16, 24, 32, 40][s % 4], 2 + s % 3, 1 + s % 3, [2, 4][s % 2]) for s in range(3, 11)]
+SEEDS = [(s, [16, 24, 36, 40][s % 4], 2 + s % 3, 1 + s % 3, [2, 4, 3][s % 3]) for s in range(3, 12)]
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_random_patches_parity(ctx, dtype, tol):
-    """Random fields on random multi-patch hierarchies, full field."""
+    """Random fields on random multi-patch hierarchies (ratios 2, 3, 4), full
+    field."""
     multi = 0
     for seed, n0, levels, per, ratio in SEEDS:
         hier = synth.random_patches(seed, n0=n0, levels=levels, per_level=per, ratio=ratio)

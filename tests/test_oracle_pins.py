@@ -159,6 +159,8 @@ HIERS = {
     "one": synth.nested_hierarchy(-1.0, -1.0, 2 / 12, 2, [(12, 0, 0)]),
     "two": synth.nested_hierarchy(-1.0, -1.0, 2 / 10, 2, [(10, 0, 0), (8, 6, 4)]),
     "three": synth.nested_hierarchy(-1.0, -1.0, 2 / 8, 2, [(8, 0, 0), (8, 4, 2), (6, 10, 8)]),
+    "ratio3": synth.nested_hierarchy(-1.0, -1.0, 2 / 9, 3, [(9, 0, 0), (9, 6, 9), (9, 24, 33)]),
+    "two_patches": synth.random_patches(4, n0=12, levels=3, per_level=2, ratio=2),
 }
 
 
