@@ -98,10 +98,25 @@ typedef struct td_plan td_plan;
 typedef struct td_batch td_batch;
 typedef struct td_server td_server;
 
+/* Where the in-cell slopes of the linear reconstruction (Section 2.1, eq.
+ * eqnSigma) come from.  The paper fixes the slopes only as constants of each
+ * cell.  TD_SLOPES_ESTIMATE derives them from sigma on the device, inside
+ * the solve: the centred difference (s[i+1] - s[i-1]) / 2h of the cell
+ * values, the one-sided difference towards the interior in a patch's first
+ * and last column (row), and 0 along an axis where the patch is one cell
+ * wide.  Each patch uses only its own values, covered cells included (their
+ * stored value enters their neighbours' slopes; as sources they are still
+ * excluded).  With these slopes the solver reproduces the error tables of
+ * Section 3 (Tables 1-5). */
+#define TD_SLOPES_GIVEN 0     /* dsdx / dsdy as passed (NULL = zero)      */
+#define TD_SLOPES_ESTIMATE 1  /* from sigma, as above; dsdx, dsdy NULL    */
+
 /* One force solve.  Arrays are indexed by patch (hierarchy order); patch k
- * holds n_k x n_k values.  All pointers are device pointers of the plan's
- * dtype.  dsdx / dsdy may be NULL (all slopes zero); an individual entry
- * may also be NULL. */
+ * holds n_k x n_k values, row-major [y][x].  All pointers are device
+ * pointers of the plan's dtype, aligned to its element size (TD_EINVAL
+ * otherwise).  With TD_SLOPES_GIVEN, dsdx / dsdy may be NULL (all slopes
+ * zero) and an individual entry may also be NULL.  A zero-initialised
+ * slopes field means TD_SLOPES_GIVEN. */
 typedef struct {
     td_plan* plan;
     const void* const* sigma;   /* [npatches] sigma at cell centres         */
@@ -109,6 +124,7 @@ typedef struct {
     const void* const* dsdy;    /* [npatches] or NULL                       */
     void* const* fx;            /* [npatches] outputs                       */
     void* const* fy;            /* [npatches] outputs                       */
+    int32_t slopes;             /* TD_SLOPES_GIVEN or TD_SLOPES_ESTIMATE    */
 } td_request;
 
 /* ---------------------------------------------------------------- context */

@@ -10,7 +10,10 @@ Contents:
     second-order cell-integral formulae (Section 2.1), plus the 1-D
     generalized convolutions of Section 2.2 written out as sums;
   * ``analytic`` -- potential-density pairs of the generalized Maclaurin
-    disks (appendix) for the convergence pins.
+    disks (appendix) for the convergence pins;
+  * ``slope_estimate.slopes`` (also ``oracle.slopes``) -- in-cell slopes
+    estimated from the cell values (centred differences, one-sided at patch
+    edges).
 """
 from __future__ import annotations
 
@@ -141,3 +144,6 @@ def genconv1d(mode: int, m: int, b, c, na: int) -> np.ndarray:
     a = np.zeros(na)
     lib().oracle_genconv1d(mode, m, _dp(b), len(b), _dp(c), len(c), _dp(a), na)
     return a
+
+
+from .slope_estimate import slopes  # noqa: E402

@@ -20,6 +20,7 @@ from ._binding import TdError, lib
 __all__ = ["Context", "Plan", "Batch", "Server", "TdError", "lib", "version"]
 
 _DT = {"f32": B.TD_F32, "f64": B.TD_F64}
+_SLOPES = {"given": B.TD_SLOPES_GIVEN, "estimate": B.TD_SLOPES_ESTIMATE}
 
 
 def version() -> str:
@@ -186,7 +187,12 @@ class Plan:
         fy = [torch.empty((n, n), dtype=self.torch_dtype, device=dev) for n in self.sizes]
         return fx, fy
 
-    def request(self, sigma, dsdx=None, dsdy=None, fx=None, fy=None):
+    def request(self, sigma, dsdx=None, dsdy=None, fx=None, fy=None, slopes="given"):
+        """slopes: "given" (dsdx / dsdy as passed, None = zero) or "estimate"
+        (TD_SLOPES_ESTIMATE: from sigma on the device; pass no slopes)."""
+        mode = _SLOPES.get(slopes)
+        if mode is None:
+            raise ValueError(f"slopes must be one of {sorted(_SLOPES)}")
         _check_fields(self, sigma, "sigma")
         _check_fields(self, dsdx, "dsdx", required=False)
         _check_fields(self, dsdy, "dsdy", required=False)
@@ -194,14 +200,15 @@ class Plan:
             fx, fy = self.outputs()
         _check_fields(self, fx, "fx")
         _check_fields(self, fy, "fy")
-        req = B.make_request(self.handle, sigma, dsdx, dsdy, fx, fy)
+        req = B.make_request(self.handle, sigma, dsdx, dsdy, fx, fy, mode)
         req._tensors = (sigma, dsdx, dsdy, fx, fy)
         return req, fx, fy
 
-    def solve(self, sigma, dsdx=None, dsdy=None, fx=None, fy=None, stream=None):
+    def solve(self, sigma, dsdx=None, dsdy=None, fx=None, fy=None, stream=None,
+              slopes="given"):
         """Enqueue td_solve on the current (or given) torch stream; returns
         (fx, fy) lists.  Asynchronous: synchronise before reading."""
-        req, fx, fy = self.request(sigma, dsdx, dsdy, fx, fy)
+        req, fx, fy = self.request(sigma, dsdx, dsdy, fx, fy, slopes)
         B.check(lib().td_solve(ctypes.byref(req), _stream_handle(stream)), "td_solve")
         return fx, fy
 
@@ -220,12 +227,13 @@ class Batch:
 
     def solve(self, fields: List[tuple], outs: Optional[List[tuple]] = None,
               use_graph: bool = False, stream=None):
-        """fields[k] = (sigma, dsdx, dsdy) for plan k; returns [(fx, fy)]."""
+        """fields[k] = (sigma, dsdx, dsdy[, slopes]) for plan k; returns
+        [(fx, fy)]."""
         reqs = (B.td_request * len(self.plans))()
         keep, res = [], []
         for k, (p, f) in enumerate(zip(self.plans, fields)):
             fx, fy = (outs[k] if outs is not None else (None, None))
-            r, fx, fy = p.request(f[0], f[1], f[2], fx, fy)
+            r, fx, fy = p.request(f[0], f[1], f[2], fx, fy, f[3] if len(f) > 3 else "given")
             keep.append(r)
             reqs[k] = r
             res.append((fx, fy))
@@ -267,8 +275,8 @@ class Server:
                 "td_server_set_queue_limit")
 
     def submit(self, plan: Plan, sigma, dsdx=None, dsdy=None, fx=None, fy=None,
-               queue_if_full: bool = True):
-        req, fx, fy = plan.request(sigma, dsdx, dsdy, fx, fy)
+               queue_if_full: bool = True, slopes="given"):
+        req, fx, fy = plan.request(sigma, dsdx, dsdy, fx, fy, slopes)
         t = ctypes.c_uint64()
         B.check(lib().td_server_submit(self.handle, ctypes.byref(req), 1 if queue_if_full else 0,
                                        ctypes.byref(t)), "td_server_submit")

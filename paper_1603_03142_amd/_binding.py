@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libthindisk.so")
 
 TD_OK, TD_EINVAL, TD_EALIGN, TD_ENEST, TD_ENOMEM, TD_EDEVICE, TD_EBUSY, TD_EUNSUPPORTED = range(8)
 TD_F32, TD_F64 = 0, 1
+TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE = 0, 1
 TD_MAX_LEVELS = 8
 TD_MAX_PATCHES = 8
 
@@ -57,7 +58,7 @@ VPP = ctypes.POINTER(ctypes.c_void_p)
 
 class td_request(ctypes.Structure):
     _fields_ = [("plan", VP), ("sigma", VPP), ("dsdx", VPP), ("dsdy", VPP), ("fx", VPP),
-                ("fy", VPP)]
+                ("fy", VPP), ("slopes", ctypes.c_int32)]
 
 
 _lib = None
@@ -154,13 +155,13 @@ def _ptr_array(tensors: Optional[Sequence]):
     return ctypes.cast(arr, VPP), arr
 
 
-def make_request(plan_handle, sigma, dsdx, dsdy, fx, fy):
+def make_request(plan_handle, sigma, dsdx, dsdy, fx, fy, slopes=TD_SLOPES_GIVEN):
     keep = []
     ps, a = _ptr_array(sigma); keep.append(a)
     px, a = _ptr_array(dsdx); keep.append(a)
     py, a = _ptr_array(dsdy); keep.append(a)
     pfx, a = _ptr_array(fx); keep.append(a)
     pfy, a = _ptr_array(fy); keep.append(a)
-    r = td_request(plan_handle, ps, px, py, pfx, pfy)
+    r = td_request(plan_handle, ps, px, py, pfx, pfy, slopes)
     r._keep = keep
     return r

@@ -922,6 +922,10 @@ td_status validate_jobs(td_plan* P)
         std::map<int64_t, std::vector<char>> rows_written;
         for (auto& j : g.rowfwd) {
             if (j.lvl < 0 || j.lvl >= P->nlevels || j.f < 0 || j.f > 2) return bad("row source");
+            // slope fields are scaled by their level's cell side, which the
+            // row kernel's in-place slope estimate (per-cell differences)
+            // takes for granted
+            if (j.scale != (j.f == 0 ? 1.0 : P->lv[j.lvl].h)) return bad("row scale");
             if (j.row0 < 0 || j.nrow < 1 || j.nrow > 2 * g.C[P_ROWFWD] || j.row0 + j.nrow > j.ld)
                 return bad("row range");
             if (!in_ws(j.out, (int64_t)H * j.ld)) return bad("row output");
@@ -1036,8 +1040,6 @@ td_status plan_geometry(td_plan* P, const td_hierarchy* h, td_dtype dt)
         level_window(h, l, &g.ox, &g.oy, &g.nx, &g.ny);
         g.M = fft_len(std::max(g.nx, g.ny));
         g.h = hh;
-        if (dt == TD_F64 && g.M > 2048)
-            return fail(TD_EUNSUPPORTED, "FP64 plans support at most 1024 cells per level window side");
         LevelPatches lp;
         memset(&lp, 0, sizeof(lp));
         for (int k = 0; k < h->npatches; ++k) {
@@ -1269,17 +1271,29 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
     return TD_OK;
 }
 
-td_status fill_ptrs(const td_request& q, int npatches, std::vector<void*>& v, size_t base)
+td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v, size_t base)
 {
     if (!q.sigma || !q.fx || !q.fy) return fail(TD_EINVAL, "sigma, fx and fy are required");
-    for (int l = 0; l < npatches; ++l) {
+    if (q.slopes != TD_SLOPES_GIVEN && q.slopes != TD_SLOPES_ESTIMATE)
+        return fail(TD_EINVAL, "slopes must be TD_SLOPES_GIVEN or TD_SLOPES_ESTIMATE");
+    if (q.slopes == TD_SLOPES_ESTIMATE && (q.dsdx || q.dsdy))
+        return fail(TD_EINVAL, "dsdx and dsdy must be NULL with TD_SLOPES_ESTIMATE");
+    const uintptr_t align = P.dt == TD_F64 ? 8 : 4;
+    for (int l = 0; l < P.npatches; ++l) {
         if (!q.sigma[l] || !q.fx[l] || !q.fy[l])
             return fail(TD_EINVAL, "NULL sigma/fx/fy pointer of patch " + std::to_string(l));
-        v[base + 5 * l + 0] = (void*)q.sigma[l];
-        v[base + 5 * l + 1] = q.dsdx ? (void*)q.dsdx[l] : nullptr;
-        v[base + 5 * l + 2] = q.dsdy ? (void*)q.dsdy[l] : nullptr;
-        v[base + 5 * l + 3] = q.fx[l];
-        v[base + 5 * l + 4] = q.fy[l];
+        void* f[5] = {(void*)q.sigma[l], q.dsdx ? (void*)q.dsdx[l] : nullptr,
+                      q.dsdy ? (void*)q.dsdy[l] : nullptr, q.fx[l], q.fy[l]};
+        for (int i = 0; i < 5; ++i) {
+            if ((uintptr_t)f[i] % align)
+                return fail(TD_EINVAL, "field pointer of patch " + std::to_string(l) +
+                                           " is not aligned to its element size");
+            v[base + 5 * l + i] = f[i];
+        }
+        // estimated slopes: the slope slots carry the sigma pointer, tagged
+        // in bit 0 (clear in every element-aligned pointer)
+        if (q.slopes == TD_SLOPES_ESTIMATE)
+            v[base + 5 * l + 1] = v[base + 5 * l + 2] = (void*)((uintptr_t)f[0] | 1u);
     }
     return TD_OK;
 }
@@ -1431,10 +1445,10 @@ extern "C" td_status td_solve(const td_request* req, void* stream)
     DeviceGuard g(P->ctx->device);
     hipStream_t st = (hipStream_t)stream;
     std::vector<void*> v(5 * P->npatches, nullptr);
-    TD_TRY(fill_ptrs(*req, P->npatches, v, 0));
+    TD_TRY(fill_ptrs(*req, *P, v, 0));
     if (!P->ws) TD_TRY(P->ctx->alloc(P->ws_bytes, &P->ws));
     // one solve: the field pointers travel in the kernel arguments
-    static_assert(5 * TD_MAX_LEVELS <= TD_KARG_PTRS, "kernel-argument pointer table too small");
+    static_assert(5 * TD_MAX_PATCHES <= TD_KARG_PTRS, "kernel-argument pointer table too small");
     FieldPtrs fp{};
     fp.n = (int32_t)v.size();
     for (size_t i = 0; i < v.size(); ++i) fp.p[i] = v[i];
@@ -1504,7 +1518,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
     std::vector<void*> v(B->nslots, nullptr);
     for (size_t k = 0; k < B->plans.size(); ++k) {
         if (reqs[k].plan != B->plans[k]) return fail(TD_EINVAL, "request plan does not match the batch");
-        TD_TRY(fill_ptrs(reqs[k], B->plans[k]->npatches, v, B->mem[k].slot_base));
+        TD_TRY(fill_ptrs(reqs[k], *B->plans[k], v, B->mem[k].slot_base));
     }
     if (use_graph && !B->exec) {
         // Capture once on a private stream; the pointer-table copy stays
@@ -1776,7 +1790,7 @@ extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32
     Ticket T;
     T.plan = req->plan;
     T.ptrs.assign(5 * P->npatches, nullptr);
-    TD_TRY(fill_ptrs(*req, P->npatches, T.ptrs, 0));
+    TD_TRY(fill_ptrs(*req, *P, T.ptrs, 0));
     T.need = (P->ws_bytes + 255) & ~size_t(255);
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->ctx->budget && T.need > S->ctx->budget) {

@@ -147,6 +147,23 @@ __device__ __forceinline__ bool covered(gpatches L, int i, int j)
 
 // C = blockDim/(M/8) complex sequences; sequence p carries stored rows
 // row0 + 2p (real part) and row0 + 2p + 1 (imaginary part).
+// Estimated slope of cell (i, j) of an n x n patch times the cell side,
+// i.e. the slope in per-cell units that the slope fields carry after their
+// scaling by the source level's h: half the centred difference of the
+// neighbouring values along x (f == 1) or y (f == 2), the one-sided
+// difference in the patch's first and last column / row, 0 when n == 1.
+template <typename T>
+__device__ __forceinline__ T cell_slope(const T* __restrict__ s, int n, int i, int j, int f)
+{
+    const int c = f == 1 ? i : j;
+    const ptrdiff_t st = f == 1 ? 1 : (ptrdiff_t)n;
+    const T* p = s + (ptrdiff_t)j * n + i;
+    if (n == 1) return (T)0;
+    if (c == 0) return (T)((double)p[st] - (double)p[0]);
+    if (c == n - 1) return (T)((double)p[0] - (double)p[-st]);
+    return (T)(0.5 * ((double)p[st] - (double)p[-st]));
+}
+
 template <typename T, int M>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> segs,
                                                   const void* const* __restrict__ ptrs,
@@ -177,14 +194,20 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
         T a = 0, b = 0;
         for (int k = 0; k < np; ++k) {
             const int slot = slot_base + L->pslot[k] + J.f;
-            const T* src = reinterpret_cast<const T*>(fp.n ? fp.p[slot] : ptrs[slot]);
+            // a slope slot tagged in bit 0 holds the patch's sigma: estimate
+            // the slope from it (uniform over the workgroup)
+            const uintptr_t raw = (uintptr_t)(fp.n ? fp.p[slot] : ptrs[slot]);
+            const T* src = reinterpret_cast<const T*>(raw & ~(uintptr_t)1);
+            const bool est = raw & 1;
             const int n = L->pn[k], i = scol - L->pi0[k];
             if (!src || i < 0 || i >= n) continue;
             const int j0 = sr0 - L->pj0[k], j1 = sr1 - L->pj0[k];
             if (s0 < rend && j0 >= 0 && j0 < n && !covered(L, scol, sr0))
-                a = (T)(J.scale * (double)src[(size_t)j0 * n + i]);
+                a = est ? cell_slope(src, n, i, j0, J.f)
+                        : (T)(J.scale * (double)src[(size_t)j0 * n + i]);
             if (s0 + 1 < rend && j1 >= 0 && j1 < n && !covered(L, scol, sr1))
-                b = (T)(J.scale * (double)src[(size_t)j1 * n + i]);
+                b = est ? cell_slope(src, n, i, j1, J.f)
+                        : (T)(J.scale * (double)src[(size_t)j1 * n + i]);
         }
         buf[p * SP + lds_pos(lc)] = cpx<T>{a, b};
     }

@@ -39,8 +39,10 @@ struct SegTable {
 };
 
 // Field pointers of a launch: by value in the kernel arguments (n > 0, one
-// solve of up to TD_MAX_LEVELS levels: 5 per level -- sigma, dsdx, dsdy, fx,
-// fy) or, for batches, in a device table (n == 0).
+// solve of up to TD_MAX_PATCHES patches: 5 per patch -- sigma, dsdx, dsdy,
+// fx, fy) or, for batches, in a device table (n == 0).  A slope slot whose
+// bit 0 is set holds the patch's sigma pointer (bit cleared): the slope is
+// estimated from sigma instead of read.
 #define TD_KARG_PTRS 40
 struct FieldPtrs {
     int32_t n;

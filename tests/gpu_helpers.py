@@ -1,11 +1,17 @@
 """Shared helpers of the GPU parity tests: seeded inputs from ``synth``,
 solves through the C ABI, comparison with the oracle."""
 import math
+import zlib
 
 import numpy as np
 
 import oracle
 import synth
+
+
+def name_seed(name: str) -> int:
+    """A seed fixed by a case name (the built-in str hash varies per process)."""
+    return zlib.crc32(name.encode()) % 1000
 
 
 def rand_fields(hier, seed, slopes=True):
@@ -26,12 +32,12 @@ def to_dev(arrs, dtype):
             else None for a in arrs]
 
 
-def gpu_solve(ctx, hier, sig, dx, dy, dtype="f64", plan=None):
+def gpu_solve(ctx, hier, sig, dx, dy, dtype="f64", plan=None, slopes="given"):
     import torch
     td = torch.float64 if dtype == "f64" else torch.float32
     if plan is None:
         plan = ctx.plan(hier, dtype)
-    fx, fy = plan.solve(to_dev(sig, td), to_dev(dx, td), to_dev(dy, td))
+    fx, fy = plan.solve(to_dev(sig, td), to_dev(dx, td), to_dev(dy, td), slopes=slopes)
     torch.cuda.synchronize()
     return [a.double().cpu().numpy() for a in fx], [a.double().cpu().numpy() for a in fy]
 

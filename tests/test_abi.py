@@ -31,6 +31,30 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in L.td_version()
 
 
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes structs and constants of the binding have the header's
+    layout and values (a C probe compiled against the header with gcc)."""
+    from paper_1603_03142_amd import _binding as B
+    probe = tmp_path / "probe.c"
+    probe.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "thindisk.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu %d %d %d %d\\n", sizeof(td_patch), sizeof(td_hierarchy),'
+        " offsetof(td_hierarchy, patches), sizeof(td_request), offsetof(td_request, fy),"
+        " offsetof(td_request, slopes), TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE, TD_MAX_PATCHES,"
+        " TD_MAX_LEVELS);\n  return 0;\n}\n")
+    exe = tmp_path / "probe"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(probe), "-o",
+                    str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(B.td_patch), ctypes.sizeof(B.td_hierarchy), B.td_hierarchy.patches.offset,
+            ctypes.sizeof(B.td_request), B.td_request.fy.offset, B.td_request.slopes.offset,
+            B.TD_SLOPES_GIVEN, B.TD_SLOPES_ESTIMATE, B.TD_MAX_PATCHES, B.TD_MAX_LEVELS]
+    assert got == want
+
+
 def _check(levels, ratio=2, h0=2 / 16, patches=None):
     """levels: one (n, ox, oy) patch per level; patches: (level, n, ox, oy)."""
     from paper_1603_03142_amd import _binding as B

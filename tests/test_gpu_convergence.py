@@ -1,16 +1,20 @@
-"""Convergence study of the paper's Examples 1 and 2 with the FP64 GPU path,
-N = 32 ... 1024 cells per side on every level (Section 3, Tables 1 and 2).
+"""The convergence study of Section 3 with the FP64 GPU path, N = 32 ... 1024
+cells per side (Example 4 to 512: its level-2 window at N = 1024 would
+exceed the 2048-cell limit), slopes estimated from sigma inside the solve (TD_SLOPES_ESTIMATE):
+Tables 1-5, every printed column, and the benefit of refinement quoted for
+Example 1 at N = 512.
 
-Surface density sigma_{D5}, alpha = 0.85, sigma0 = 1: point values and the
-analytic gradient at cell centres (the readings under which the oracle
-reproduces the tables at N <= 64).  Reference force: the appendix's
-potential-density pair, F_R = -dPhi/dR evaluated with mpmath at dense radii
-and interpolated by cubic splines inside and outside the disk edge
-(interpolation error below 2e-12, against E1 >= 8.7e-7 here).
+Densities: sigma_{D5} (alpha = 0.85) for Examples 1-2, sigma_{D2} (alpha =
+0.85) on Example 1's grids for Table 5, two sigma_{D5} disks (alpha =
+sqrt(2)/4, centres (+-1/2, 0)) for Examples 3-4; point values at cell
+centres.  Reference force: the appendix's potential-density pairs, F_R =
+-dPhi/dR by mpmath at dense radii, cubic splines inside and outside the
+disk edge in sqrt|r - alpha| (interpolation error below 1e-10 for the disks
+here, against errors >= 8.7e-7).
 
-E1 = unweighted mean of |error| over active cells of all levels; E1_R uses
-the radial component (x Fx + y Fy) / r.  The paper's E1 columns are the
-golden fixtures; E2 and E_inf are printed, not asserted (parity unpinned).
+Norms over the active cells of all levels: E1 (mean), E2 (root mean
+square), Einf (max) of |F_x - F_x^exact| and of the radial component (Tables
+1, 2, 5) or of F_y (Tables 3, 4).
 """
 import math
 import os
@@ -24,8 +28,8 @@ from gpu_helpers import gpu_solve
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-ALPHA = 0.85
 NS = (32, 64, 128, 256, 512, 1024)
+COLS = ("E1_x", "E2_x", "Einf_x", "E1_2", "E2_2", "Einf_2")
 
 
 def _golden(name):
@@ -33,23 +37,28 @@ def _golden(name):
     for line in open(os.path.join(GOLDEN, name)):
         if line.startswith("#") or not line.strip():
             continue
-        n, e1x, e1r = line.split()
-        rows[int(n)] = (float(e1x), float(e1r))
+        v = line.split()
+        rows[int(v[0])] = np.array([float(t) for t in v[1:]])
     return rows
 
 
-@pytest.fixture(scope="module")
-def radial():
+def _radial(dn, alpha, rmax):
+    """F_R(r) by cubic splines in t = sqrt|r - alpha| on each side of the
+    disk edge: the force's half-integer powers of (alpha - r) there become
+    smooth in t."""
     from scipy.interpolate import CubicSpline
     from oracle import analytic
-    ri = np.linspace(0.0, ALPHA, 1201)
-    ro = np.linspace(ALPHA, 1.45, 2401)
-    fi = np.array([float(analytic.radial_force(5, r, ALPHA)) if r > 0 else 0.0 for r in ri])
-    fo = np.array([float(analytic.radial_force(5, r, ALPHA)) for r in ro])
-    si, so = CubicSpline(ri, fi), CubicSpline(ro, fo)
+    ti = np.linspace(0.0, math.sqrt(alpha), 1601)
+    to = np.linspace(0.0, math.sqrt(rmax - alpha), 2401)
+    fi = np.array([float(analytic.radial_force(dn, alpha - t * t, alpha)) if t * t < alpha
+                   else 0.0 for t in ti])
+    fo = np.array([float(analytic.radial_force(dn, alpha + t * t, alpha)) for t in to])
+    si, so = CubicSpline(ti, fi), CubicSpline(to, fo)
 
     def f(r):
-        return np.where(r <= ALPHA, si(np.minimum(r, ALPHA)), so(np.maximum(r, ALPHA)))
+        inside = r <= alpha
+        return np.where(inside, si(np.sqrt(np.maximum(alpha - r, 0.0))),
+                        so(np.sqrt(np.maximum(r - alpha, 0.0))))
     return f
 
 
@@ -61,46 +70,103 @@ def ctx():
     c.close()
 
 
-def _errors(ctx, radial, example, n):
-    hier = synth.example_hierarchy(example, n)
-    sig, dx, dy = synth.sample_fields(hier, synth.disk_dn(5, ALPHA), "analytic",
-                                      synth.disk_dn_gradient(5, ALPHA))
-    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, "f64")
-    ex, eR = [], []
+@pytest.fixture(scope="module")
+def radials():
+    return {5: _radial(5, 0.85, 1.45), 2: _radial(2, 0.85, 1.45),
+            "two": _radial(5, synth.TWO_DISK_ALPHA, 2.0)}
+
+
+def _density(example, dn):
+    if example in (3, 4):
+        return synth.two_disks(), synth.TWO_DISKS, "two"
+    return synth.disk_dn(dn, 0.85), ((0.0, 0.0),), dn
+
+
+def _errors(ctx, radials, example, n, dn=5, dtype="f64", region=None, hier=None):
+    """The six norms; ``region`` (x0, x1) restricts them to cells whose
+    centres lie in [x0, x1]^2."""
+    hier = hier or synth.example_hierarchy(example, n)
+    fn, disks, key = _density(example, dn)
+    sig = [fn(*synth.cell_centres(hier, p)) for p in hier.patches]
+    gx, gy = gpu_solve(ctx, hier, sig, None, None, dtype, slopes="estimate")
+    radial = radials[key]
+    e1, e2 = [], []
     for k, p in enumerate(hier.patches):
         X, Y = synth.cell_centres(hier, p)
         act = ~synth.covered_mask(hier, p)
+        if region is not None:
+            act &= (X > region[0]) & (X < region[1]) & (Y > region[0]) & (Y < region[1])
         x, y = X[act], Y[act]
-        r = np.hypot(x, y)
-        fr = radial(r)
-        ax, ay = fr * x / r, fr * y / r
-        ex.append(np.abs(gx[k][act] - ax))
-        eR.append(np.abs((x * (gx[k][act] - ax) + y * (gy[k][act] - ay)) / r))
-    ex, eR = np.concatenate(ex), np.concatenate(eR)
-    return {"E1x": ex.mean(), "E2x": math.sqrt((ex ** 2).mean()), "Einfx": ex.max(),
-            "E1R": eR.mean()}
+        ax, ay = np.zeros(x.shape), np.zeros(x.shape)
+        for cx, cy in disks:
+            r = np.hypot(x - cx, y - cy)
+            fr = radial(r)
+            ax += fr * (x - cx) / r
+            ay += fr * (y - cy) / r
+        ex, ey = gx[k][act] - ax, gy[k][act] - ay
+        e1.append(np.abs(ex))
+        e2.append(np.abs(ey) if example in (3, 4) else np.abs((x * ex + y * ey) / np.hypot(x, y)))
+    out = []
+    for e in (np.concatenate(e1), np.concatenate(e2)):
+        out += [e.mean(), math.sqrt((e * e).mean()), e.max()]
+    return np.array(out)
 
 
-@pytest.mark.parametrize("example,golden", [(1, "table1_example1_e1.txt"),
-                                            (2, "table2_example2_e1.txt")])
-def test_paper_tables_e1(ctx, radial, example, golden):
-    tab = _golden(golden)
-    res = {n: _errors(ctx, radial, example, n) for n in NS}
-    print(f"\nExample {example}: N, E1_x (paper), E1_R (paper), E2_x, Einf_x, order E1_x")
-    for i, n in enumerate(NS):
-        e = res[n]
-        order = math.log2(res[NS[i - 1]]["E1x"] / e["E1x"]) if i else float("nan")
-        print(f"  {n:5d} {e['E1x']:.4e} ({tab[n][0]:.3e})  {e['E1R']:.4e} ({tab[n][1]:.3e})"
-              f"  {e['E2x']:.4e} {e['Einfx']:.4e}  {order:.3f}")
-    for i, n in enumerate(NS):
-        e = res[n]
-        # second order throughout
+# (example, sigma_{D_n}, fixture, sizes)
+TABLES = {
+    "table1": (1, 5, "table1_example1.txt", NS),
+    "table2": (2, 5, "table2_example2.txt", NS),
+    "table3": (3, 5, "table3_example3.txt", NS),   # level-1 window 1.5 N cells
+    "table4": (4, 5, "table4_example4.txt", NS[:5]),  # level-2 window 3 N cells
+    "table5": (1, 2, "table5_d2.txt", NS),
+}
+
+# Relative agreement with the printed values.  The E1 / E2 columns agree to
+# about 1% at N = 32 and to the printed digits from N = 256 on; Einf (one
+# cell, at a patch edge) to 2%.  Example 4's level-1 patches are snapped to
+# the lattice (a reading): its refined regions differ slightly, worth a few
+# percent in E1 / E2.
+TOL = {"table1": (0.012, 0.005, 0.02), "table2": (0.012, 0.005, 0.02),
+       "table3": (0.02, 0.01, 0.02), "table5": (0.015, 0.01, 0.02),
+       "table4": (0.05, 0.05, 0.03)}
+
+
+@pytest.mark.parametrize("name", sorted(TABLES))
+def test_paper_table(ctx, radials, name):
+    example, dn, fixture, ns = TABLES[name]
+    tab = _golden(fixture)
+    res = {n: _errors(ctx, radials, example, n, dn) for n in ns}
+    print(f"\n{name}: N, then (ours / paper) for " + ", ".join(COLS))
+    for n in ns:
+        print(f"  {n:5d} " + "  ".join(f"{a:.4e}/{b:.3e}" for a, b in zip(res[n], tab[n])))
+    print("  orders E1_x: " + " ".join(f"{math.log2(res[a][0] / res[b][0]):.3f}"
+                                       for a, b in zip(ns, ns[1:])))
+    small, large, einf = TOL[name]
+    for i, n in enumerate(ns):
         if i:
-            assert 1.9 < math.log2(res[NS[i - 1]]["E1x"] / e["E1x"]) < 2.1
-        # the paper's E1 columns (printed to 4 digits): about 2% apart at
-        # N = 32, converging to the printed digits as N grows (the residual
-        # at small N is the paper's unstated slope estimate near the level
-        # interfaces, a term that vanishes faster than the error itself)
-        tol = 0.03 if n <= 64 else 0.006 if n <= 256 else 0.002
-        assert e["E1x"] == pytest.approx(tab[n][0], rel=tol), (example, n)
-        assert e["E1R"] == pytest.approx(tab[n][1], rel=1.5 * tol), (example, n)
+            assert 1.85 < math.log2(res[ns[i - 1]][0] / res[n][0]) < 2.15, (name, n)
+        t = small if n <= 64 else large
+        for c in (0, 1, 3, 4):
+            assert res[n][c] == pytest.approx(tab[n][c], rel=t), (name, n, COLS[c])
+        for c in (2, 5):
+            assert res[n][c] == pytest.approx(tab[n][c], rel=einf), (name, n, COLS[c])
+
+
+def test_refinement_benefit(ctx, radials):
+    """Example 1 at N = 512 over [-1/2, 1/2]^2: log2 of the error ratio
+    without / with the refined level, against the three numbers the paper
+    quotes (L1, L2, Linf); Linf gets worse with refinement (the interface),
+    L1 and L2 better by about 1.6."""
+    with open(os.path.join(GOLDEN, "refinement_benefit.txt")) as f:
+        want = np.array([float(v) for v in
+                         [l for l in f if l.strip() and not l.startswith("#")][0].split()])
+    n = 512
+    ref = _errors(ctx, radials, 1, n, region=(-0.5, 0.5))
+    base = synth.nested_hierarchy(-1.0, -1.0, 2.0 / n, 2, [(n, 0, 0)])
+    noref = _errors(ctx, radials, 1, n, region=(-0.5, 0.5), hier=base)
+    gain = np.log2(noref / ref)
+    print(f"\nrefinement benefit (x: L1 L2 Linf | radial: L1 L2 Linf): "
+          + " ".join(f"{g:.3f}" for g in gain) + f"   paper: {want}")
+    # the quoted numbers are those of the radial force (reading); the
+    # x-force's differ by up to 0.04
+    np.testing.assert_allclose(gain[3:], want, atol=0.015)

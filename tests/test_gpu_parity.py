@@ -11,8 +11,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import (covered_are_zero, gpu_solve, rand_fields, rel_l2, rel_l2_full,
-                         sampled)
+from gpu_helpers import (covered_are_zero, gpu_solve, name_seed, rand_fields, rel_l2,
+                         rel_l2_full, sampled)
 
 pytestmark = pytest.mark.gpu
 
@@ -100,13 +100,60 @@ HIERS = {
 @pytest.mark.parametrize("name", sorted(HIERS))
 def test_full_field_parity(ctx, name, dtype):
     hier = HIERS[name]
-    sig, dx, dy = rand_fields(hier, seed=hash(name) % 1000)
+    sig, dx, dy = rand_fields(hier, seed=name_seed(name))
     ox, oy = oracle.forces(hier, sig, dx, dy)
     gx, gy = gpu_solve(ctx, hier, sig, dx, dy, dtype)
     err = rel_l2_full(hier, gx, gy, ox, oy)
     print(f"{name} {dtype} rel-L2 {err:.3e}")
     assert err <= TOL[dtype]
     assert covered_are_zero(hier, gx, gy)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name", sorted(HIERS))
+def test_estimated_slopes_parity(ctx, name, dtype):
+    """TD_SLOPES_ESTIMATE (slopes from sigma inside the solve) against the
+    oracle's estimate fed to the oracle's direct sum.  Random sigma in every
+    cell, covered cells included (their values enter their neighbours'
+    slopes); patches one and two cells wide take the degenerate branches."""
+    hier = HIERS[name]
+    sig, _, _ = rand_fields(hier, seed=name_seed(name) + 1, slopes=False)
+    dx, dy = oracle.slopes(hier, sig)
+    ox, oy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = gpu_solve(ctx, hier, sig, None, None, dtype, slopes="estimate")
+    if max(np.abs(a).max() for a in ox + oy) == 0:
+        # one cell, slope 0: the cell's force on itself vanishes by symmetry
+        assert max(np.abs(a).max() for a in gx + gy) <= 1e-12 * np.abs(sig[0]).max()
+        return
+    err = rel_l2_full(hier, gx, gy, ox, oy)
+    print(f"{name} {dtype} estimated slopes rel-L2 {err:.3e}")
+    assert err <= TOL[dtype]
+    assert covered_are_zero(hier, gx, gy)
+
+
+def test_estimated_slopes_request_errors(ctx):
+    """Slopes passed together with TD_SLOPES_ESTIMATE, an unknown mode, or a
+    field pointer not aligned to the element size: TD_EINVAL, nothing
+    launched."""
+    import ctypes
+    import torch
+    from paper_1603_03142_amd import _binding as B
+    hier = HIERS["2lev_20_12"]
+    plan = ctx.plan(hier, "f64")
+    sig = [torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda") for p in hier.patches]
+    fx, fy = plan.outputs()
+    for dsdx, mode in ((sig, B.TD_SLOPES_ESTIMATE), (None, 7), (None, -1)):
+        req = B.make_request(plan.handle, sig, dsdx, None, fx, fy, mode)
+        assert B.lib().td_solve(ctypes.byref(req), None) == B.TD_EINVAL
+    flat = torch.zeros(sum(p.n * p.n for p in hier.patches) + 1, dtype=torch.float64,
+                       device="cuda")
+    odd = [flat, flat]
+    req = B.make_request(plan.handle, odd, None, None, fx, fy, B.TD_SLOPES_GIVEN)
+    ptrs = (ctypes.c_void_p * 2)(flat.data_ptr() + 4, flat.data_ptr())
+    req.sigma = ctypes.cast(ptrs, B.VPP)
+    assert B.lib().td_solve(ctypes.byref(req), None) == B.TD_EINVAL
+    assert b"aligned" in B.lib().td_last_error()
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

@@ -1,13 +1,8 @@
 """Several patches per level (Section 2.1: the grids Omega^l_k, k > 0), through
 the C ABI: parity with the oracle on random multi-patch hierarchies and on
-the paper's Examples 3 and 4, and Example 3's convergence table.
-
-Examples 3/4: two sigma_{D5} disks (alpha = sqrt(2)/4) at (+-1/2, 0).  The
-reference force is the sum of the two disks' analytic forces (appendix pair,
-mpmath, splined as in the Example 1-2 study).  Example 3's patches lie on the
-lattices exactly, so Table 3 is a pin; Example 4's level-1 patches, as
-printed, lie on no 2^k lattice and are snapped (synth.example_hierarchy), so
-Table 4 is compared with a wider tolerance (that geometry is a reading)."""
+the paper's Examples 3 and 4 (two sigma_{D5} disks, alpha = sqrt(2)/4, at
+(+-1/2, 0)).  Their error tables are reproduced with the other convergence
+tables of Section 3 in the convergence module."""
 import math
 import os
 
@@ -64,6 +59,19 @@ def test_random_patches_parity(ctx, dtype, tol):
     assert multi >= 4
 
 
+def test_random_patches_estimated_slopes(ctx):
+    """Slopes estimated from sigma on multi-patch hierarchies: every patch
+    uses its own values only, one-sided at its own edges (patches of one
+    level that touch do not see each other)."""
+    for seed, n0, levels, per, ratio in SEEDS[:5]:
+        hier = synth.random_patches(seed, n0=n0, levels=levels, per_level=per, ratio=ratio)
+        sig, _, _ = rand_fields(hier, 70 + seed, slopes=False)
+        dx, dy = oracle.slopes(hier, sig)
+        ox, oy = oracle.forces(hier, sig, dx, dy)
+        gx, gy = gpu_solve(ctx, hier, sig, None, None, "f64", slopes="estimate")
+        assert rel_l2_full(hier, gx, gy, ox, oy) <= 1e-12, seed
+
+
 @pytest.mark.parametrize("example", [3, 4])
 def test_examples_vs_oracle(ctx, example):
     hier = synth.example_hierarchy(example, 32)
@@ -71,72 +79,3 @@ def test_examples_vs_oracle(ctx, example):
     ox, oy = oracle.forces(hier, sig, dx, dy)
     gx, gy = gpu_solve(ctx, hier, sig, dx, dy, "f64")
     assert rel_l2_full(hier, gx, gy, ox, oy) <= 1e-12
-
-
-def _golden(name):
-    rows = {}
-    for line in open(os.path.join(GOLDEN, name)):
-        if line.startswith("#") or not line.strip():
-            continue
-        n, a, b = line.split()
-        rows[int(n)] = (float(a), float(b))
-    return rows
-
-
-def _errors(ctx, radial, example, n, dtype):
-    hier = synth.example_hierarchy(example, n)
-    sig, dx, dy = synth.sample_fields(hier, synth.two_disks(), "analytic", synth.two_disks_gradient())
-    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, dtype)
-    ex, ey = [], []
-    for k, p in enumerate(hier.patches):
-        X, Y = synth.cell_centres(hier, p)
-        act = ~synth.covered_mask(hier, p)
-        x, y = X[act], Y[act]
-        ax = np.zeros(x.shape)
-        ay = np.zeros(x.shape)
-        for cx, cy in synth.TWO_DISKS:
-            r = np.hypot(x - cx, y - cy)
-            fr = radial(r)
-            ax += fr * (x - cx) / r
-            ay += fr * (y - cy) / r
-        ex.append(np.abs(gx[k][act] - ax))
-        ey.append(np.abs(gy[k][act] - ay))
-    return np.concatenate(ex).mean(), np.concatenate(ey).mean()
-
-
-def test_table3_e1(ctx, radial):
-    """Example 3, N = 32 ... 1024 (FP64 to 512; FP32 at 1024, whose level-1
-    window of 1536 cells needs transforms beyond the FP64 limit)."""
-    tab = _golden("table3_example3_e1.txt")
-    ns = (32, 64, 128, 256, 512, 1024)
-    res = {n: _errors(ctx, radial, 3, n, "f64" if n <= 512 else "f32") for n in ns}
-    print("\nExample 3: N, E1_x (paper), E1_y (paper), order E1_x")
-    for i, n in enumerate(ns):
-        order = math.log2(res[ns[i - 1]][0] / res[n][0]) if i else float("nan")
-        print(f"  {n:5d} {res[n][0]:.4e} ({tab[n][0]:.3e})  {res[n][1]:.4e} ({tab[n][1]:.3e})  {order:.3f}")
-    for i, n in enumerate(ns):
-        if i:
-            assert 1.9 < math.log2(res[ns[i - 1]][0] / res[n][0]) < 2.1
-        # within 2% of the printed E1 from N = 64 on (7% at N = 32, where the
-        # paper's unstated slope estimate at the patch edges weighs most)
-        tol = 0.07 if n == 32 else 0.02
-        assert res[n][0] == pytest.approx(tab[n][0], rel=tol), n
-        assert res[n][1] == pytest.approx(tab[n][1], rel=tol), n
-
-
-def test_table4_e1_snapped(ctx, radial):
-    """Example 4 with the level-1 patches snapped to the lattice: second
-    order, E1 near Table 4 (the refined regions differ slightly).  FP64 to
-    N = 256, FP32 at 512 (level-2 window of 1536 cells)."""
-    tab = _golden("table4_example4_e1.txt")
-    ns = (32, 64, 128, 256, 512)
-    res = {n: _errors(ctx, radial, 4, n, "f64" if n <= 256 else "f32") for n in ns}
-    print("\nExample 4 (snapped level-1 patches): N, E1_x (paper), E1_y (paper)")
-    for n in ns:
-        print(f"  {n:5d} {res[n][0]:.4e} ({tab[n][0]:.3e})  {res[n][1]:.4e} ({tab[n][1]:.3e})")
-    for i, n in enumerate(ns):
-        if i:
-            assert 1.85 < math.log2(res[ns[i - 1]][0] / res[n][0]) < 2.15
-        # within 3% of Table 4 at every N despite the snapped level-1 edges
-        assert res[n][0] == pytest.approx(tab[n][0], rel=0.05), n
-        assert res[n][1] == pytest.approx(tab[n][1], rel=0.05), n

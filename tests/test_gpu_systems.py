@@ -62,9 +62,12 @@ def test_batch_equals_single_solves(ctx, use_graph):
     hiers = _mix()
     plans = [ctx.plan(h, "f32") for h in hiers]
     fields = [_dev_fields(h, 100 + k, "f32")[0] for k, h in enumerate(hiers)]
+    # every other member estimates its slopes from sigma (tagged slots in the
+    # batch's device pointer table)
+    fields = [f if k % 2 == 0 else (f[0], None, None, "estimate") for k, f in enumerate(fields)]
     single = []
     for p, f in zip(plans, fields):
-        fx, fy = p.solve(*f)
+        fx, fy = p.solve(*f[:3], slopes=f[3] if len(f) > 3 else "given")
         single.append((fx, fy))
     torch.cuda.synchronize()
     batch = td.Batch(ctx, plans)
@@ -200,17 +203,19 @@ def test_fp32_vs_fp64_full_field(ctx):
     assert err <= 1e-5
 
 
-def test_largest_level_f32(ctx):
-    """One 2048^2 level (transform length 4096): sampled targets."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_largest_level(ctx, dtype):
+    """One 2048^2 level (transform length 4096, the largest; in FP64 the
+    passes hold 136 KiB of LDS per workgroup): sampled targets."""
     n = 2048
     hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / n, 2, [(n, 0, 0)])
     fn = synth.disk_dn(2, 0.9)
     sig, dx, dy = synth.sample_fields(hier, fn, "central")
-    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, "f32")
+    gx, gy = gpu_solve(ctx, hier, sig, dx, dy, dtype)
     tg = synth.sample_targets(hier, 12, seed=13)
     ox, oy = oracle.forces(hier, sig, dx, dy, tg)
     sx, sy = sampled(hier, gx, gy, tg)
-    assert rel_l2(sx, sy, ox, oy) <= 1e-5
+    assert rel_l2(sx, sy, ox, oy) <= {"f32": 1e-5, "f64": 1e-12}[dtype]
 
 
 def test_autotuned_plans_keep_parity(tmp_path):
