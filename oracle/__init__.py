@@ -6,9 +6,10 @@ package never imports the product package: the two share only the seeded
 input generators in ``synth``.
 
 Contents:
-  * ``direct_sum.c`` -- plain long-double O(cells^2) direct sum of the
-    second-order cell-integral formulae (Section 2.1), plus the 1-D
-    generalized convolutions of Section 2.2 written out as sums;
+  * ``direct_sum.c`` -- plain long-double O(cells^2) direct sums of the
+    second-order cell-integral formulae (Section 2.1) for the force and for
+    the potential, plus the 1-D generalized convolutions of Section 2.2
+    written out as sums;
   * ``analytic`` -- potential-density pairs of the generalized Maclaurin
     disks (appendix) for the convergence pins;
   * ``slope_estimate.slopes`` (also ``oracle.slopes``) -- in-cell slopes
@@ -57,6 +58,10 @@ def lib():
                                         ctypes.POINTER(dp), ctypes.c_int, ip, ip, ip, dp, dp,
                                         ctypes.c_int]
             L.oracle_forces.restype = ctypes.c_int
+            L.oracle_cell_potential.argtypes = [ctypes.c_double] * 4 + [dp]
+            L.oracle_cell_potential.restype = None
+            L.oracle_potential.argtypes = L.oracle_forces.argtypes[:-3] + [dp, ctypes.c_int]
+            L.oracle_potential.restype = ctypes.c_int
             L.oracle_genconv1d.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp,
                                            ctypes.c_int, dp, ctypes.c_int]
             L.oracle_genconv1d.restype = None
@@ -80,6 +85,23 @@ def cell_integrals(ua: float, ub: float, va: float, vb: float) -> np.ndarray:
     return out
 
 
+def cell_potential_integrals(ua: float, ub: float, va: float, vb: float) -> np.ndarray:
+    """[P0, Px, Py] = integrals of 1/r, (u - uc)/r, (v - vc)/r over the cell
+    [ua,ub]x[va,vb] relative to a target at the origin (the potential's
+    kernel, eq. eqnPhixy0, with the linear density of eq. eqnSigma)."""
+    out = np.zeros(3)
+    lib().oracle_cell_potential(float(ua), float(ub), float(va), float(vb), _dp(out))
+    return out
+
+
+def potential(hier, sigma, dsdx=None, dsdy=None, targets=None, nthreads: int = 0):
+    """Direct-sum potential Phi = -sum over active source cells of the
+    integral of sigma / rho (G = 1).  Arguments as for ``forces``; returns a
+    list of phi arrays per patch, or a flat array for ``targets``.  Covered
+    targets get 0."""
+    return _direct(hier, sigma, dsdx, dsdy, targets, nthreads, potential=True)
+
+
 def forces(hier, sigma, dsdx=None, dsdy=None, targets=None, nthreads: int = 0):
     """Direct-sum forces.
 
@@ -88,6 +110,10 @@ def forces(hier, sigma, dsdx=None, dsdy=None, targets=None, nthreads: int = 0):
     for every cell of every patch (returns lists of (fx, fy) arrays per
     patch), or a (patch, i, j) triple of int arrays (returns flat fx, fy).
     Covered targets get 0."""
+    return _direct(hier, sigma, dsdx, dsdy, targets, nthreads, potential=False)
+
+
+def _direct(hier, sigma, dsdx, dsdy, targets, nthreads, potential):
     P = len(hier.patches)
     level = np.array([p.level for p in hier.patches], np.int32)
     n = np.array([p.n for p in hier.patches], np.int32)
@@ -120,19 +146,24 @@ def forces(hier, sigma, dsdx=None, dsdy=None, targets=None, nthreads: int = 0):
         tp, ti, tj = (np.ascontiguousarray(t, dtype=np.int32) for t in targets)
     fx = np.zeros(len(tp))
     fy = np.zeros(len(tp))
-    rc = lib().oracle_forces(P, _ip(level), _ip(n), _ip(ox), _ip(oy), hier.x0, hier.y0,
-                             hier.h0, hier.ratio, ps, px, py, len(tp), _ip(tp), _ip(ti),
-                             _ip(tj), _dp(fx), _dp(fy), int(nthreads))
+    geo = (P, _ip(level), _ip(n), _ip(ox), _ip(oy), hier.x0, hier.y0, hier.h0, hier.ratio,
+           ps, px, py, len(tp), _ip(tp), _ip(ti), _ip(tj))
+    if potential:
+        rc = lib().oracle_potential(*geo, _dp(fx), int(nthreads))
+    else:
+        rc = lib().oracle_forces(*geo, _dp(fx), _dp(fy), int(nthreads))
     if rc != 0:
-        raise ValueError("oracle_forces: malformed target list")
-    if not full:
-        return fx, fy
-    outx, outy, o = [], [], 0
-    for p in hier.patches:
-        outx.append(fx[o:o + p.n * p.n].reshape(p.n, p.n))
-        outy.append(fy[o:o + p.n * p.n].reshape(p.n, p.n))
-        o += p.n * p.n
-    return outx, outy
+        raise ValueError("oracle: malformed target list")
+
+    def per_patch(a):
+        out, o = [], 0
+        for p in hier.patches:
+            out.append(a[o:o + p.n * p.n].reshape(p.n, p.n))
+            o += p.n * p.n
+        return out
+    if potential:
+        return fx if not full else per_patch(fx)
+    return (fx, fy) if not full else (per_patch(fx), per_patch(fy))
 
 
 def genconv1d(mode: int, m: int, b, c, na: int) -> np.ndarray:

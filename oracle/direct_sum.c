@@ -30,6 +30,19 @@
  *   - a level-l cell is active iff no level-(l+1) patch covers it; covered
  *     targets get force 0.
  *
+ * The potential itself (eq. eqnPhixy0, Green's function -1/rho, G = 1) is
+ * summed the same way:
+ *
+ *     Phi(t) = - sum over every active source cell c of
+ *              integral_c sigma(xbar, ybar) / rho dxbar dybar,
+ *
+ * with the cell integrals of 1/rho, (xbar - x_c)/rho and (ybar - y_c)/rho
+ * written as four-corner differences of their antiderivatives
+ *     a(u, v)  = u ln(v + r) + v ln(u + r)        (d^2 a / du dv = 1 / r)
+ *     bx(u, v) = v r / 2 + (u^2 / 2) ln(v + r)    (d^2 bx / du dv = u / r)
+ *     by(u, v) = u r / 2 + (v^2 / 2) ln(u + r)    (d^2 by / du dv = v / r)
+ * each term taken as 0 where its factor u, v (or u^2, v^2) is 0, its limit.
+ *
  * Arithmetic: every antiderivative in x87 long double; per-target sums in
  * long double with Neumaier compensation; results rounded to double.
  */
@@ -112,6 +125,44 @@ void oracle_cell_integrals(double ua, double ub, double va, double vb, double ou
     for (int k = 0; k < 6; ++k) out[k] = (double)o[k];
 }
 
+/* Antiderivatives of the potential integrands at one corner (u, v). */
+typedef struct { ld a, bx, by; } pcorner_t;
+
+static pcorner_t pcorner_eval(ld u, ld v)
+{
+    pcorner_t c;
+    ld r = sqrtl(u * u + v * v);
+    ld lv = (u != 0) ? log_b_plus_r(u, v, r) : 0;   /* ln(v + r), used only times u */
+    ld lu = (v != 0) ? log_b_plus_r(v, u, r) : 0;   /* ln(u + r), used only times v */
+    c.a = u * lv + v * lu;
+    c.bx = v * r / 2 + u * u / 2 * lv;
+    c.by = u * r / 2 + v * v / 2 * lu;
+    return c;
+}
+
+/* Potential cell integrals of [ua,ub] x [va,vb] relative to the target:
+ *   out[0] P0 = int 1 / r,  out[1] Px = int (u - uc) / r,
+ *   out[2] Py = int (v - vc) / r.                                         */
+static void cell_potential_ld(ld ua, ld ub, ld va, ld vb, ld out[3])
+{
+    pcorner_t bb = pcorner_eval(ub, vb), ab = pcorner_eval(ua, vb);
+    pcorner_t ba = pcorner_eval(ub, va), aa = pcorner_eval(ua, va);
+    ld uc = (ua + ub) / 2, vc = (va + vb) / 2;
+#define CORNER_DIFF(f) ((bb.f - ab.f) - (ba.f - aa.f))
+    ld p0 = CORNER_DIFF(a);
+    out[0] = p0;
+    out[1] = CORNER_DIFF(bx) - uc * p0;
+    out[2] = CORNER_DIFF(by) - vc * p0;
+#undef CORNER_DIFF
+}
+
+void oracle_cell_potential(double ua, double ub, double va, double vb, double out[3])
+{
+    ld o[3];
+    cell_potential_ld(ua, ub, va, vb, o);
+    for (int k = 0; k < 3; ++k) out[k] = (double)o[k];
+}
+
 /* Neumaier-compensated long-double accumulator. */
 typedef struct { ld s, c; } acc_t;
 static void acc_add(acc_t* a, ld x)
@@ -140,7 +191,8 @@ static int cell_covered(int npatch, const int* level, const int* n, const int* o
 }
 
 /*
- * Direct-sum forces at a list of targets.
+ * Direct sums at a list of targets: forces (what = 0: out0 = fx, out1 = fy)
+ * or the potential (what = 1: out0 = phi, out1 unused, may be NULL).
  *   npatch patches; patch p is on level level[p], has n[p] x n[p] cells of
  *   side h0 / ratio^level[p], lower-left corner at
  *   (x0 + ox[p] h, y0 + oy[p] h).
@@ -150,11 +202,11 @@ static int cell_covered(int npatch, const int* level, const int* n, const int* o
  *   the force; a covered target receives 0.
  * Returns 0, or -1 on a malformed target index.
  */
-int oracle_forces(int npatch, const int* level, const int* n, const int* ox, const int* oy,
-                  double x0, double y0, double h0, int ratio,
-                  const double* const* sigma, const double* const* dsdx,
-                  const double* const* dsdy, int ntarget, const int* tpatch,
-                  const int* ti, const int* tj, double* fx, double* fy, int nthreads)
+static int direct_sum(int what, int npatch, const int* level, const int* n, const int* ox,
+                      const int* oy, double x0, double y0, double h0, int ratio,
+                      const double* const* sigma, const double* const* dsdx,
+                      const double* const* dsdy, int ntarget, const int* tpatch,
+                      const int* ti, const int* tj, double* fx, double* fy, int nthreads)
 {
     for (int k = 0; k < ntarget; ++k) {
         int q = tpatch[k];
@@ -196,7 +248,7 @@ int oracle_forces(int npatch, const int* level, const int* n, const int* ox, con
         int q = tpatch[k];
         if (!active[base[q] + (size_t)tj[k] * n[q] + ti[k]]) {
             fx[k] = 0;
-            fy[k] = 0;
+            if (fy) fy[k] = 0;
             continue;
         }
         ld xt = xl[q] + (ti[k] + (ld)0.5) * hp[q];
@@ -213,21 +265,30 @@ int oracle_forces(int npatch, const int* level, const int* n, const int* ox, con
                     size_t idx = (size_t)j * n[p] + i;
                     if (!active[base[p] + idx]) continue;
                     ld ua = xl[p] + i * h - xt, ub = xl[p] + (i + 1) * h - xt;
-                    ld c[6];
-                    cell_integrals_ld(ua, ub, va, vb, c);
                     ld sg = s[idx];
                     ld gx = sx ? sx[idx] : 0, gy = sy ? sy[idx] : 0;
-                    acc_add(&ax, sg * c[0]);
-                    acc_add(&ax, gx * c[1]);
-                    acc_add(&ax, gy * c[2]);
-                    acc_add(&ay, sg * c[3]);
-                    acc_add(&ay, gy * c[4]);
-                    acc_add(&ay, gx * c[5]);
+                    if (what == 0) {
+                        ld c[6];
+                        cell_integrals_ld(ua, ub, va, vb, c);
+                        acc_add(&ax, sg * c[0]);
+                        acc_add(&ax, gx * c[1]);
+                        acc_add(&ax, gy * c[2]);
+                        acc_add(&ay, sg * c[3]);
+                        acc_add(&ay, gy * c[4]);
+                        acc_add(&ay, gx * c[5]);
+                    } else {
+                        /* Phi = - sum sigma / rho: the Green's function -1/rho */
+                        ld c[3];
+                        cell_potential_ld(ua, ub, va, vb, c);
+                        acc_add(&ax, -sg * c[0]);
+                        acc_add(&ax, -gx * c[1]);
+                        acc_add(&ax, -gy * c[2]);
+                    }
                 }
             }
         }
         fx[k] = (double)(ax.s + ax.c);
-        fy[k] = (double)(ay.s + ay.c);
+        if (fy) fy[k] = (double)(ay.s + ay.c);
     }
     free(hp);
     free(xl);
@@ -235,6 +296,26 @@ int oracle_forces(int npatch, const int* level, const int* n, const int* ox, con
     free(active);
     free(base);
     return 0;
+}
+
+int oracle_forces(int npatch, const int* level, const int* n, const int* ox, const int* oy,
+                  double x0, double y0, double h0, int ratio,
+                  const double* const* sigma, const double* const* dsdx,
+                  const double* const* dsdy, int ntarget, const int* tpatch,
+                  const int* ti, const int* tj, double* fx, double* fy, int nthreads)
+{
+    return direct_sum(0, npatch, level, n, ox, oy, x0, y0, h0, ratio, sigma, dsdx, dsdy,
+                      ntarget, tpatch, ti, tj, fx, fy, nthreads);
+}
+
+int oracle_potential(int npatch, const int* level, const int* n, const int* ox,
+                     const int* oy, double x0, double y0, double h0, int ratio,
+                     const double* const* sigma, const double* const* dsdx,
+                     const double* const* dsdy, int ntarget, const int* tpatch,
+                     const int* ti, const int* tj, double* phi, int nthreads)
+{
+    return direct_sum(1, npatch, level, n, ox, oy, x0, y0, h0, ratio, sigma, dsdx, dsdy,
+                      ntarget, tpatch, ti, tj, phi, NULL, nthreads);
 }
 
 /*

@@ -199,6 +199,133 @@ def test_telescoping_linear_density(name):
 
 
 # ---------------------------------------------------------------------------
+# the potential (eq. eqnPhixy0, Green's function -1/rho): cell integrals and
+# whole-domain sums
+# ---------------------------------------------------------------------------
+
+def quad_cell_potential(ua, ub, va, vb, dps=25):
+    """[P0, Px, Py] by 2-D quadrature of 1/r, (u - uc)/r, (v - vc)/r."""
+    uc, vc = (ua + ub) / 2, (va + vb) / 2
+    with mp.workdps(dps):
+        fs = [lambda u, v: 1 / mp.sqrt(u * u + v * v),
+              lambda u, v: (u - uc) / mp.sqrt(u * u + v * v),
+              lambda u, v: (v - vc) / mp.sqrt(u * u + v * v)]
+        return np.array([float(mp.quad(f, [ua, ub], [va, vb])) for f in fs])
+
+
+@pytest.mark.parametrize("cell", CELLS)
+def test_potential_cell_integrals_match_quadrature(cell):
+    got = oracle.cell_potential_integrals(*cell)
+    want = quad_cell_potential(*cell)
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-13 * np.abs(want).max())
+
+
+def test_potential_closed_forms():
+    """Self cell of side h: int 1/r over [-h/2,h/2]^2 = 4 h asinh(1) (polar
+    form, 8 int_0^{pi/4} (h/2)/cos); moments 0 by symmetry.  Unit square with
+    the target at a corner: 2 asinh(1)."""
+    for h in (1.0, 0.125, 3.0):
+        c = oracle.cell_potential_integrals(-h / 2, h / 2, -h / 2, h / 2)
+        assert c[0] == pytest.approx(4 * h * math.asinh(1.0), rel=1e-15)
+        assert c[1] == 0.0 and c[2] == 0.0
+    assert oracle.cell_potential_integrals(0.0, 1.0, 0.0, 1.0)[0] == pytest.approx(
+        2 * math.asinh(1.0), rel=1e-15)
+
+
+def test_potential_gradient_is_the_force_kernel():
+    """d/dx_t of each potential cell integral is the force integral of the
+    same field (F = -grad Phi): P0 -> I0, Px -> Ixx, Py -> Ixy, and along y
+    P0 -> J0, Px -> Jyx, Py -> Jyy.  Central differences in the target
+    position against the (quadrature-pinned) force integrals."""
+    rng = np.random.default_rng(11)
+    eps = 1e-5
+    for _ in range(12):
+        ua, va = rng.uniform(-6, 6, 2)
+        w = rng.uniform(0.3, 2)
+        f = oracle.cell_integrals(ua, ua + w, va, va + w)
+        # moving the target by +eps shifts the cell's relative coordinates
+        # by -eps; the cell centre (and so the moment arm) moves with them
+        px = lambda d: oracle.cell_potential_integrals(ua - d, ua + w - d, va, va + w)
+        py = lambda d: oracle.cell_potential_integrals(ua, ua + w, va - d, va + w - d)
+        dx = (px(eps) - px(-eps)) / (2 * eps)
+        dy = (py(eps) - py(-eps)) / (2 * eps)
+        scale = np.abs(f).max()
+        np.testing.assert_allclose(dx, f[[0, 1, 2]], atol=1e-7 * scale)
+        np.testing.assert_allclose(dy, f[[3, 5, 4]], atol=1e-7 * scale)
+
+
+def domain_potential_polar(xt, yt, L, R, B, T):
+    """int 1/r, int u/r, int v/r over [L,R]x[B,T] about an interior target,
+    in polar form: int rho dt, int cos rho^2/2 dt, int sin rho^2/2 dt."""
+    with mp.workdps(25):
+        def rho(t):
+            c, s = mp.cos(t), mp.sin(t)
+            cands = []
+            if c > 0: cands.append((R - xt) / c)
+            if c < 0: cands.append((L - xt) / c)
+            if s > 0: cands.append((T - yt) / s)
+            if s < 0: cands.append((B - yt) / s)
+            return min(cands)
+        corners = sorted(float(mp.atan2(cy - yt, cx - xt)) % (2 * math.pi)
+                         for cx in (L, R) for cy in (B, T))
+        pts = [0.0] + corners + [2 * math.pi]
+        f = lambda g: float(mp.quad(g, pts))
+        return (f(rho), f(lambda t: mp.cos(t) * rho(t) ** 2 / 2),
+                f(lambda t: mp.sin(t) * rho(t) ** 2 / 2))
+
+
+@pytest.mark.parametrize("name", sorted(HIERS))
+def test_potential_telescoping_linear_density(name):
+    """Linear sigma with exact slopes: the potential summed over the active
+    cells of every level equals minus the whole-domain integral."""
+    hier = HIERS[name]
+    a, b, c = 0.7, -1.3, 0.45
+    sig, _, _ = synth.sample_fields(hier, lambda X, Y: a + b * X + c * Y, "none")
+    dx = [np.full_like(s, b) for s in sig]
+    dy = [np.full_like(s, c) for s in sig]
+    p0 = hier.patches[0]
+    L, B = hier.x0, hier.y0
+    Rr, T = L + p0.n * hier.h0, B + p0.n * hier.h0
+    rng = np.random.default_rng(5)
+    tp, ti, tj = [], [], []
+    for k, p in enumerate(hier.patches):
+        act = np.argwhere(~synth.covered_mask(hier, p))
+        for j, i in act[rng.choice(len(act), size=min(3, len(act)), replace=False)]:
+            tp.append(k); ti.append(i); tj.append(j)
+    phi = oracle.potential(hier, sig, dx, dy, (np.array(tp), np.array(ti), np.array(tj)))
+    for k in range(len(tp)):
+        p = hier.patches[tp[k]]
+        h = hier.h(p.level)
+        xl, yl = hier.lower_left(p)
+        xt, yt = xl + (ti[k] + 0.5) * h, yl + (tj[k] + 0.5) * h
+        q0, qu, qv = domain_potential_polar(xt, yt, L, Rr, B, T)
+        want = -(a * q0 + b * (qu + xt * q0) + c * (qv + yt * q0))
+        assert phi[k] == pytest.approx(want, rel=1e-11, abs=1e-12)
+
+
+def test_potential_converges_to_the_appendix_pair():
+    """sigma_{D5} (alpha = 0.85) on Example 1's two levels, slopes estimated
+    from sigma: the potential's mean error against the appendix's analytic
+    Phi falls about 4x per halving of h (second order)."""
+    errs = []
+    for n in (16, 32):
+        hier = synth.example_hierarchy(1, n)
+        sig, _, _ = synth.sample_fields(hier, synth.disk_dn(5, 0.85), "none")
+        dx, dy = oracle.slopes(hier, sig)
+        phi = oracle.potential(hier, sig, dx, dy)
+        e = []
+        for k, p in enumerate(hier.patches):
+            X, Y = synth.cell_centres(hier, p)
+            act = ~synth.covered_mask(hier, p)
+            R = np.hypot(X[act], Y[act])
+            exact = np.array([float(analytic.potential(5, r, 0.85)) for r in R])
+            e.append(np.abs(phi[k][act] - exact))
+        errs.append(np.concatenate(e).mean())
+    assert 3.6 < errs[0] / errs[1] < 4.4
+    assert errs[1] < 1e-3
+
+
+# ---------------------------------------------------------------------------
 # invariants of the direct sum
 # ---------------------------------------------------------------------------
 
