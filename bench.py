@@ -4,8 +4,10 @@
 One step = one full force solve (every pass of the hot path) of the workload:
   two nested levels of 256 x 256 cells, ratio 2, the fine level covering the
   central [-1/2,1/2]^2 of the [-1,1]^2 base; sigma = Maclaurin disk R = 0.8
-  plus a Gaussian clump (amplitude 5, width 0.03) at (0.2, 0.1); slopes by
-  central differences of the analytic sigma; FP32 FFT passes with
+  plus a Gaussian clump (amplitude 5, width 0.03) at (0.2, 0.1); sigma in,
+  the in-cell slopes estimated from it inside the solve (centred
+  differences, one-sided at patch edges; --slopes given passes central
+  differences of the analytic sigma instead); FP32 FFT passes with
   FP64-built kernel spectra.
 Inputs are resident in HBM before the timed region; kernel spectra are
 resident (plan built beforehand).  Prints one JSON line.
@@ -13,7 +15,7 @@ resident (plan built beforehand).  Prints one JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
                   [--workload two-level-256|single-64|four-level-512|example3-512|
                               example1-1024|batch-64|serve]
-                  [--mode eager|graph] [--no-cpu] [--tune DB]
+                  [--mode eager|graph] [--slopes estimate|given] [--no-cpu] [--tune DB]
 
 Other workloads: batch-64 = 64 independent disks (base N in {64..512}, 1-3
 nested levels, random aligned refinement, generalized Maclaurin sigma) solved
@@ -37,12 +39,12 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # HBM bytes per launch of a pass, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs
 # of this script, each scaled by the ratio of a plain copy kernel's known
 # bytes to what the same counter read for it.  Keyed by (workload, dtype,
-# pass) and tied to the SHA-256 of the kernel source they were taken on: a
+# slopes mode, pass) and tied to the SHA-256 of the kernel source they were taken on: a
 # changed kernel reports null until it is profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "col"): (29334564, "80bc9ef33b8e1f5d"),
-    ("two-level-256", "f32", "row_inv"): (7590181, "80bc9ef33b8e1f5d"),
-    ("two-level-256", "f32", "row_fwd"): (10503532, "80bc9ef33b8e1f5d"),
+    ("two-level-256", "f32", "given", "col"): (29334564, "80bc9ef33b8e1f5d"),
+    ("two-level-256", "f32", "given", "row_inv"): (7590181, "80bc9ef33b8e1f5d"),
+    ("two-level-256", "f32", "given", "row_fwd"): (10503532, "80bc9ef33b8e1f5d"),
 }
 
 
@@ -55,8 +57,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name, dtype, pass_name):
-    rec = TRAFFIC.get((workload_name, dtype, pass_name))
+def measured_traffic(workload_name, dtype, slopes, pass_name):
+    rec = TRAFFIC.get((workload_name, dtype, slopes, pass_name))
     if rec is None or rec[1] != kernel_source_hash():
         return None
     return rec[0]
@@ -93,6 +95,20 @@ def workload(name):
     return hier, fn
 
 
+def host_fields(synth, hier, fn, slopes):
+    """sigma per patch, and the slope fields when they are passed in."""
+    if slopes == "estimate":
+        s, _, _ = synth.sample_fields(hier, fn, "none")
+        return s, None, None
+    return synth.sample_fields(hier, fn, "central")
+
+
+def dev_fields(torch, tdt, arrs, slopes):
+    dev = lambda a: None if a is None else [torch.as_tensor(x, dtype=tdt, device="cuda")
+                                            for x in a]
+    return (*[dev(a) for a in arrs], slopes)
+
+
 def run_batch(args, td, torch, synth):
     """64 independent hierarchies per step, one batched launch set."""
     import numpy as np
@@ -103,10 +119,9 @@ def run_batch(args, td, torch, synth):
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
     plans, fields = [], []
     for hier, fn in disks:
-        s, x, y = synth.sample_fields(hier, fn, "central")
-        dev = lambda arrs: [torch.as_tensor(a, dtype=tdt, device="cuda") for a in arrs]
         plans.append(ctx.plan(hier, args.dtype))
-        fields.append((dev(s), dev(x), dev(y)))
+        fields.append(dev_fields(torch, tdt, host_fields(synth, hier, fn, args.slopes),
+                                 args.slopes))
     batch = td.Batch(ctx, plans)
     outs = [p.outputs() for p in plans]
     use_graph = args.mode == "graph"
@@ -127,7 +142,8 @@ def run_batch(args, td, torch, synth):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "batch-64", "hierarchies": len(plans), "cells_per_step": cells,
-                   "mode": args.mode, "workspace_bytes": batch.footprint()},
+                   "mode": args.mode, "slopes": args.slopes,
+                   "workspace_bytes": batch.footprint()},
         "roofline": None, "cpu_baseline": None,
     }
 
@@ -150,18 +166,17 @@ def run_serve(args, td, torch, synth):
     for k in range(ntypes):
         _, hier, (order, alpha, fseed) = reqs[k % len(reqs)]
         fn = synth.request_sigma(order, alpha, fseed, hier.h0)
-        s, x, y = synth.sample_fields(hier, fn, "central")
-        dev = lambda arrs: [torch.as_tensor(a, dtype=tdt, device="cuda") for a in arrs]
         plan = ctx.plan(hier, args.dtype)
         outs = [plan.outputs() for _ in range(2)]
-        types.append((plan, (dev(s), dev(x), dev(y)), outs))
+        types.append((plan, dev_fields(torch, tdt, host_fields(synth, hier, fn, args.slopes),
+                                       args.slopes), outs))
         log(f"planned type {k}: levels {len(hier.patches)} n {hier.patches[0].n} "
             f"workspace {plan.footprint()[0] / 2**30:.2f} GiB ({time.perf_counter() - tp:.1f} s)")
     srv = td.Server(ctx, max_inflight=args.inflight, max_batch=args.max_batch)
     srv.set_queue_limit(args.queue_limit)
     # warm-up: each type once
     for plan, f, outs in types:
-        srv.submit(plan, *f, *outs[0])
+        srv.submit(plan, *f[:3], *outs[0], slopes=f[3])
         srv.drain()
     log(f"warm-up done ({time.perf_counter() - tp:.1f} s)")
     torch.cuda.synchronize()
@@ -177,7 +192,8 @@ def run_serve(args, td, torch, synth):
             pass
         plan, f, outs = types[pick[k]]
         try:
-            tk, _, _ = srv.submit(plan, *f, *outs[k % 2], queue_if_full=False)
+            tk, _, _ = srv.submit(plan, *f[:3], *outs[k % 2], queue_if_full=False,
+                                  slopes=f[3])
             tickets.append((tk, plan.cells))
         except td.TdError as e:
             if e.status != 6:  # TD_EBUSY: the bounded queue is full
@@ -220,7 +236,7 @@ def run_serve(args, td, torch, synth):
         "config": {"workload": "serve", "offered_rate": args.rate, "duration_s": args.duration,
                    "request_types": ntypes, "max_inflight": args.inflight,
                    "max_batch": args.max_batch, "queue_limit": args.queue_limit,
-                   "hbm_budget_gb": args.budget_gb},
+                   "hbm_budget_gb": args.budget_gb, "slopes": args.slopes},
         "serving": {"offered": len(arrivals), "admitted": len(tickets), "refused": refused,
                     "arrival_window_s": t_arr, "wall_s": el,
                     "sustained_req_per_s": len(tickets) / el,
@@ -239,6 +255,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="two-level-256")
     ap.add_argument("--mode", default="eager", choices=["eager", "graph"])
+    ap.add_argument("--slopes", default="estimate", choices=["estimate", "given"],
+                    help="estimate: sigma in, slopes from it inside the solve; given: "
+                         "central differences of the analytic sigma passed in")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tune", metavar="DB", default=None,
@@ -276,10 +295,9 @@ def main():
         print(json.dumps(out), flush=True)
         return
     hier, fn = workload(args.workload)
-    sig, dx, dy = synth.sample_fields(hier, fn, "central")
+    sig, dx, dy = host_fields(synth, hier, fn, args.slopes)
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
-    dev = lambda arrs: [torch.as_tensor(a, dtype=tdt, device="cuda") for a in arrs]
-    S, DX, DY = dev(sig), dev(dx), dev(dy)
+    S, DX, DY, SL = dev_fields(torch, tdt, (sig, dx, dy), args.slopes)
 
     ctx = td.Context(0)
     tune_s = None
@@ -296,9 +314,9 @@ def main():
 
     if args.mode == "graph":
         batch = td.Batch(ctx, [plan])
-        step = lambda: batch.solve([(S, DX, DY)], [(FX, FY)], use_graph=True, stream=stream)
+        step = lambda: batch.solve([(S, DX, DY, SL)], [(FX, FY)], use_graph=True, stream=stream)
     else:
-        step = lambda: plan.solve(S, DX, DY, FX, FY, stream=stream)
+        step = lambda: plan.solve(S, DX, DY, FX, FY, stream=stream, slopes=SL)
 
     # warm-up with every pass timed (eager): per-pass breakdown and the
     # dominant pass, which alone is timed over the measured region
@@ -329,7 +347,7 @@ def main():
 
     # roofline of the dominant pass (algorithmic bytes / mean launch time)
     roof = None
-    traffic = plan.traffic()
+    traffic = plan.traffic(args.slopes)
     if passes:
         ms, launches = passes[dom]
         per_launch_s = ms / 1000.0 / max(launches, 1)
@@ -338,7 +356,7 @@ def main():
         achieved = bytes_per_launch / per_launch_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, args.dtype, dom),
+                "traffic": measured_traffic(args.workload, args.dtype, args.slopes, dom),
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
                 "alg_bytes_per_launch": int(bytes_per_launch),
                 "passes_us_per_solve_warmup": {p: round(1000.0 * warm[p][0] / args.warmup, 2)
@@ -348,18 +366,17 @@ def main():
     # throughout) on the same workload, for the speed-up of this run over it
     fp64 = None
     if not args.no_fp64_leg and not (args.dtype == "f64" and args.mode == "eager"):
-        S64, DX64, DY64 = ([torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in arrs]
-                           for arrs in (sig, dx, dy))
+        S64, DX64, DY64, _ = dev_fields(torch, torch.float64, (sig, dx, dy), args.slopes)
         ctx64 = td.Context(0)
         plan64 = ctx64.plan(hier, "f64")
         FX64, FY64 = plan64.outputs()
         k64 = max(3, args.steps // 4)
         for _ in range(3):
-            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream)
+            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream, slopes=SL)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k64):
-            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream)
+            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream, slopes=SL)
         torch.cuda.synchronize()
         el64 = time.perf_counter() - t0
         v64 = cells * k64 / el64
@@ -374,6 +391,8 @@ def main():
     acc = None
     if not args.no_cpu:
         import oracle
+        if args.slopes == "estimate":
+            dx, dy = oracle.slopes(hier, sig)
         nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         probe = synth.sample_targets(hier, 8, seed=1)
         tp0 = time.perf_counter()
@@ -411,7 +430,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "levels": hier.nlevels,
                    "patches": [[p.level, p.n] for p in hier.patches], "ratio": hier.ratio,
-                   "cells_per_solve": cells, "mode": args.mode,
+                   "cells_per_solve": cells, "mode": args.mode, "slopes": args.slopes,
                    "plan_build_s": round(plan_s, 3), "autotune_s": tune_s},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -18,6 +18,12 @@
  * eqnbnmn) for pairs of levels of different resolution.  F_y follows by
  * exchanging x and y.
  *
+ * A plan can compute the potential instead (td_plan_create_quantity with
+ * TD_POTENTIAL): Phi(t) = - sum over active c of integral_c sigma / |rbar -
+ * r_t| (eq. eqnPhixy0, Green's function -1/rho, G = 1), whose cell
+ * integrals are the four-corner differences of u ln(v+r) + v ln(u+r),
+ * v r/2 + (u^2/2) ln(v+r) and its exchange, through the same convolutions.
+ *
  * Conventions
  *   - Level l holds one or more square patches of cells of side
  *     h0 / ratio^l (ratio 2, 3 or 4); level 0 is a single patch.  A patch's
@@ -156,13 +162,26 @@ td_status td_hierarchy_snap(td_hierarchy* inout, td_patch* patches, const double
 
 /* ---------------------------------------------------------------- plans */
 
+/* What a plan's solves compute. */
+#define TD_FORCE 0       /* Fx into fx, Fy into fy (Section 2.1)              */
+#define TD_POTENTIAL 1   /* Phi into fx (eq. eqnPhixy0); fy may be NULL, else
+                            it receives 0 */
+
 /* Validate the hierarchy, build (or find resident) the kernel spectra for
  * every level pair, and allocate the plan's workspace.  The kernel tables
  * (cell integrals of every offset and polyphase phase) are generated on the
  * GPU in FP64 and transformed in FP64; TD_F32 plans use them rounded to
- * FP32.  Synchronous. */
+ * FP32.  Synchronous.  td_plan_create makes a TD_FORCE plan. */
 td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_dtype dtype,
                          td_plan** out);
+/* As td_plan_create, for quantity TD_FORCE or TD_POTENTIAL (TD_EINVAL
+ * otherwise).  A potential plan has its own resident spectra (the three
+ * potential tables; the second component's tables are zero, so a potential
+ * solve costs what a force solve does); its solves write Phi, in units of
+ * sigma times length, into the fx outputs.  Force and potential plans may
+ * share a batch or a server. */
+td_status td_plan_create_quantity(td_context* ctx, const td_hierarchy* h, td_dtype dtype,
+                                  int32_t quantity, td_plan** out);
 /* Host-only planning: validate the hierarchy, build every job list of the
  * plan that td_plan_create would build (default launch shapes) and prove
  * on the host that each job's reads and writes stay inside its workspace,
@@ -238,15 +257,17 @@ td_status td_server_destroy(td_server* s);
 
 /* ---------------------------------------------------------------- diagnostics */
 
-/* Write the dimensionless FP64 kernel table of one level pair kind into
- * host memory: out[6][M][M] (I0, Ixx, Ixy, J0, Jyy, Jyx), entry [ny][nx] is
- * the cell integral for a lattice offset (output - input) of
- * (nx or nx-M, ny or ny-M), in units of the finer cell side; kind = 1 (same
- * level), 2 (finer source, ratio m), 3 (coarser source, ratio m); (kx, ky)
- * the polyphase phase.  Case-3 slope entries include the 1/m factor that
- * converts the coarse source's slope scaling.  Synchronous; for tests. */
-td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m, int32_t kx,
-                          int32_t ky, double* out_host);
+/* Write the FP64 kernel table of one level pair kind into host memory:
+ * out[6][M][M], entry [ny][nx] is the cell integral for a lattice offset
+ * (output - input) of (nx or nx-M, ny or ny-M), in units of the finer cell
+ * side; kind = 1 (same level), 2 (finer source, ratio m), 3 (coarser
+ * source, ratio m); (kx, ky) the polyphase phase.  TD_FORCE: I0, Ixx, Ixy,
+ * J0, Jyy, Jyx, Case-3 slope entries with the factor 1/m that converts the
+ * coarse source's slope scaling.  TD_POTENTIAL: P0 = int 1/r, Px = int
+ * (u-uc)/r, Py = int (v-vc)/r and three zero planes, Case-3 entries with
+ * 1/m (slopes 1/m^2).  Synchronous; for tests. */
+td_status td_kernel_table(td_context* ctx, int32_t quantity, int32_t M, int32_t kind, int32_t m,
+                          int32_t kx, int32_t ky, double* out_host);
 
 /* The timed launch kinds of a solve, in launch order. */
 #define TD_NPASS 4   /* row_fwd, col, row_inv, row_inv_accumulate */
@@ -263,12 +284,14 @@ td_status td_timing_enable(td_context* ctx, int pass_mask);
 td_status td_timing_read(td_context* ctx, double* ms, int64_t* launches);
 
 /* Algorithmic HBM bytes one solve of the plan moves in each pass (array of
- * TD_NPASS): row_fwd reads every source value in range and writes its row
- * spectra; col reads every row-spectrum plane and every stored kernel plane
- * once and writes every column output once; row_inv reads its column
- * outputs once per target row that uses them and writes (or reads and
- * writes, when accumulating) every force value. */
-td_status td_plan_traffic(const td_plan* plan, double* bytes);
+ * TD_NPASS), for requests with the given slopes mode: row_fwd reads every
+ * source value in range (sigma only with TD_SLOPES_ESTIMATE, whose slope
+ * jobs re-read sigma) and writes its row spectra; col reads every
+ * row-spectrum plane and every stored kernel plane once and writes every
+ * column output once; row_inv reads its column outputs once per target row
+ * that uses them and writes (or reads and writes, when accumulating) every
+ * force value.  TD_EINVAL for an unknown slopes mode. */
+td_status td_plan_traffic(const td_plan* plan, int32_t slopes, double* bytes);
 
 const char* td_status_string(td_status s);
 const char* td_last_error(void);

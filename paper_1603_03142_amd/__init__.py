@@ -21,6 +21,7 @@ __all__ = ["Context", "Plan", "Batch", "Server", "TdError", "lib", "version"]
 
 _DT = {"f32": B.TD_F32, "f64": B.TD_F64}
 _SLOPES = {"given": B.TD_SLOPES_GIVEN, "estimate": B.TD_SLOPES_ESTIMATE}
+_QUANTITY = {"force": B.TD_FORCE, "potential": B.TD_POTENTIAL}
 
 
 def version() -> str:
@@ -85,8 +86,10 @@ class Context:
                 "td_context_usage")
         return a.value, b.value
 
-    def plan(self, hier, dtype: str = "f32") -> "Plan":
-        return Plan(self, hier, dtype)
+    def plan(self, hier, dtype: str = "f32", quantity: str = "force") -> "Plan":
+        """quantity "force" (solves return (fx, fy)) or "potential" (solves
+        return (phi, None))."""
+        return Plan(self, hier, dtype, quantity)
 
     def autotune(self, dtype: str = "f32", max_M: int = 2048, db_path: Optional[str] = None):
         B.check(lib().td_autotune(self.handle, _DT[dtype], max_M,
@@ -109,10 +112,11 @@ class Context:
         B.check(lib().td_timing_read(self.handle, ms, n), "td_timing_read")
         return {p: (ms[i], n[i]) for i, p in enumerate(self.PASSES)}
 
-    def kernel_table(self, M: int, kind: int, m: int = 1, kx: int = 0, ky: int = 0):
+    def kernel_table(self, M: int, kind: int, m: int = 1, kx: int = 0, ky: int = 0,
+                     quantity: str = "force"):
         import numpy as np
         out = np.zeros((6, M, M))
-        B.check(lib().td_kernel_table(self.handle, M, kind, m, kx, ky,
+        B.check(lib().td_kernel_table(self.handle, _QUANTITY[quantity], M, kind, m, kx, ky,
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                 "td_kernel_table")
         return out
@@ -136,19 +140,23 @@ class Plan:
     """td_plan for one hierarchy and dtype; field lists are per patch, in the
     hierarchy's patch order."""
 
-    def __init__(self, ctx: Context, hier, dtype: str = "f32"):
+    def __init__(self, ctx: Context, hier, dtype: str = "f32", quantity: str = "force"):
         if dtype not in _DT:
             raise ValueError("dtype must be 'f32' or 'f64'")
+        if quantity not in _QUANTITY:
+            raise ValueError(f"quantity must be one of {sorted(_QUANTITY)}")
         self.ctx = ctx
         self.dtype = dtype
+        self.quantity = quantity
         self.hier = hier
         h = B.make_hierarchy(hier)
         self.npatches = h.npatches
         self.sizes = [h.patches[k].n for k in range(h.npatches)]
         self.nlevels = 1 + max(h.patches[k].level for k in range(h.npatches))
         handle = ctypes.c_void_p()
-        B.check(lib().td_plan_create(ctx.handle, ctypes.byref(h), _DT[dtype],
-                                     ctypes.byref(handle)), "td_plan_create")
+        B.check(lib().td_plan_create_quantity(ctx.handle, ctypes.byref(h), _DT[dtype],
+                                              _QUANTITY[quantity], ctypes.byref(handle)),
+                "td_plan_create_quantity")
         self.handle = handle
         torch = _torch()
         self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
@@ -163,10 +171,11 @@ class Plan:
                 "td_plan_footprint")
         return a.value, b.value
 
-    def traffic(self):
-        """{pass: algorithmic HBM bytes per solve}."""
+    def traffic(self, slopes="given"):
+        """{pass: algorithmic HBM bytes per solve} for requests with this
+        slopes mode."""
         b = (ctypes.c_double * len(Context.PASSES))()
-        B.check(lib().td_plan_traffic(self.handle, b), "td_plan_traffic")
+        B.check(lib().td_plan_traffic(self.handle, _SLOPES[slopes], b), "td_plan_traffic")
         return {p: b[i] for i, p in enumerate(Context.PASSES)}
 
     def close(self):
@@ -184,6 +193,8 @@ class Plan:
         torch = _torch()
         dev = torch.device("cuda", self.ctx.device)
         fx = [torch.empty((n, n), dtype=self.torch_dtype, device=dev) for n in self.sizes]
+        if self.quantity == "potential":
+            return fx, None
         fy = [torch.empty((n, n), dtype=self.torch_dtype, device=dev) for n in self.sizes]
         return fx, fy
 
@@ -196,10 +207,11 @@ class Plan:
         _check_fields(self, sigma, "sigma")
         _check_fields(self, dsdx, "dsdx", required=False)
         _check_fields(self, dsdy, "dsdy", required=False)
-        if fx is None or fy is None:
+        pot = self.quantity == "potential"
+        if fx is None or (fy is None and not pot):
             fx, fy = self.outputs()
         _check_fields(self, fx, "fx")
-        _check_fields(self, fy, "fy")
+        _check_fields(self, fy, "fy", required=not pot)
         req = B.make_request(self.handle, sigma, dsdx, dsdy, fx, fy, mode)
         req._tensors = (sigma, dsdx, dsdy, fx, fy)
         return req, fx, fy

@@ -17,13 +17,15 @@ LIB_PATH = os.path.join(_HERE, "libthindisk.so")
 TD_OK, TD_EINVAL, TD_EALIGN, TD_ENEST, TD_ENOMEM, TD_EDEVICE, TD_EBUSY, TD_EUNSUPPORTED = range(8)
 TD_F32, TD_F64 = 0, 1
 TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE = 0, 1
+TD_FORCE, TD_POTENTIAL = 0, 1
 TD_MAX_LEVELS = 8
 TD_MAX_PATCHES = 8
 
 # Every entry point the header declares.
 EXPORTS = [
     "td_context_create", "td_context_destroy", "td_context_usage", "td_hierarchy_check",
-    "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_footprint", "td_plan_destroy", "td_solve",
+    "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_create_quantity",
+    "td_plan_footprint", "td_plan_destroy", "td_solve",
     "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_destroy",
     "td_autotune", "td_timing_enable", "td_timing_read", "td_plan_traffic", "td_server_create", "td_server_set_queue_limit", "td_server_submit", "td_server_poll", "td_server_drain",
     "td_server_cancel", "td_server_stats", "td_server_destroy", "td_kernel_table",
@@ -88,6 +90,8 @@ def lib():
                                    ctypes.POINTER(ctypes.c_double)], S),
             "td_plan_create": ([VP, ctypes.POINTER(td_hierarchy), ctypes.c_int,
                                 ctypes.POINTER(VP)], S),
+            "td_plan_create_quantity": ([VP, ctypes.POINTER(td_hierarchy), ctypes.c_int,
+                                         ctypes.c_int32, ctypes.POINTER(VP)], S),
             "td_plan_footprint": ([VP, sz, sz], S),
             "td_plan_check": ([ctypes.POINTER(td_hierarchy), ctypes.c_int, sz], S),
             "td_plan_destroy": ([VP], S),
@@ -107,12 +111,12 @@ def lib():
             "td_server_stats": ([VP, u64, u64, u64, u64, u64, u64], S),
             "td_server_destroy": ([VP], S),
             "td_kernel_table": ([VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                 ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)], S),
             "td_timing_enable": ([VP, ctypes.c_int], S),
             "td_timing_read": ([VP, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64)], S),
-            "td_plan_traffic": ([VP, ctypes.POINTER(ctypes.c_double)], S),
+            "td_plan_traffic": ([VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)], S),
             "td_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "td_last_error": ([], ctypes.c_char_p),
             "td_version": ([], ctypes.c_char_p),

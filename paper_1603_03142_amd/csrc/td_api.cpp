@@ -135,7 +135,7 @@ struct td_context {
     std::atomic<size_t> spectra_bytes{0};
     std::recursive_mutex mu;
     std::map<int, void*> tw32, tw64;
-    std::map<std::tuple<int, int, int, int>, SpecEntry> spectra;  // (M, kind, m, dtype)
+    std::map<std::tuple<int, int, int, int, int>, SpecEntry> spectra;  // (M, kind, m, dtype, family)
     std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> shape
     hipStream_t stream = nullptr;                                 // plan-time work
     std::vector<void*> allocs;
@@ -258,14 +258,16 @@ SegTable<Job> single_seg(const Job* jobs, int n, int slot_base, const void* aux,
     return s;
 }
 
-// Build (once per context) the kernel spectra of one (M, kind, m, dtype).
+// Build (once per context) the kernel spectra of one (M, kind, m, dtype,
+// family); family 1 holds the potential tables (P0, Px, Py, zero planes).
 // Stored phases: kind 1 -> (0,0); kinds 2/3 -> (kx, ky) in [0, hp)^2 with
 // hp = ceil(m/2), the others being mirror images (for odd m the middle
 // phase of each axis is its own mirror).  Layout [phase][X][M/2+1][M].
-td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const SpecEntry** out)
+td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int family,
+                  const SpecEntry** out)
 {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    auto key = std::make_tuple(M, kind, m, (int)dt);
+    auto key = std::make_tuple(M, kind, m, (int)dt, family);
     auto it = ctx->spectra.find(key);
     if (it != ctx->spectra.end()) {
         *out = &it->second;
@@ -318,6 +320,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
                 j.row0 = r0;
                 j.nrow = std::min(2 * C, M - r0);
                 j.scale = 1.0;
+                j.est_scale = 1.0;
                 j.out = (int64_t)(X * NCOL * (size_t)M * 16);
                 jobs.push_back(j);
             }
@@ -336,6 +339,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
         tj.m = (kind == 1) ? 1 : m;
         tj.kx = p % hp;
         tj.ky = p / hp;
+        tj.family = family;
         tj.out = (double*)table;
         hipError_t he = launch_table(tj, ctx->stream);
         if (he == hipSuccess)
@@ -345,8 +349,9 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, const Sp
         const int Cs = std::max(1, std::min(shape_C(default_shape(P_ROWINV, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
         void* dst = (char*)e.ptr + (size_t)p * per_phase * elem_size(dt);
         if (he == hipSuccess)
-            he = dt == TD_F64 ? launch_spec_col<double>(M, Cs, rows, dst, tw64, quarter, ctx->stream)
-                              : launch_spec_col<float>(M, Cs, rows, dst, tw64, quarter, ctx->stream);
+            he = dt == TD_F64
+                     ? launch_spec_col<double>(M, Cs, rows, dst, tw64, quarter | (family << 1), ctx->stream)
+                     : launch_spec_col<float>(M, Cs, rows, dst, tw64, quarter | (family << 1), ctx->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
         if (he != hipSuccess) st = fail(TD_EDEVICE, std::string("kernel-table build: ") + hipGetErrorString(he));
     }
@@ -542,6 +547,7 @@ struct td_plan {
     td_context* ctx = nullptr;
     bool dry = false;          // host-only planning: no spectra, no device memory
     td_dtype dt = TD_F32;
+    int quantity = TD_FORCE;   // TD_FORCE (Fx, Fy) or TD_POTENTIAL (Phi into fx)
     int ratio = 2;
     int nlevels = 0;
     int npatches = 0;
@@ -620,7 +626,7 @@ const void* phase_kernels(const SpecEntry* e, int m, int kx, int ky, size_t per_
 // whose address is never dereferenced.
 td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out)
 {
-    if (!P->dry) return spectra(P->ctx, M, kind, m, P->dt, out);
+    if (!P->dry) return spectra(P->ctx, M, kind, m, P->dt, P->quantity, out);
     static SpecEntry fake;
     const int hp = kind == 1 ? 1 : (m + 1) / 2;
     fake.ptr = (void*)(uintptr_t)4096;
@@ -628,6 +634,19 @@ td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out
     fake.bytes = (size_t)hp * hp * 6 * (M / 2 + 1) * (size_t)M * elem_size(P->dt);
     *out = &fake;
     return TD_OK;
+}
+
+// Multipliers of a row-forward job reading field f of a level with cell side
+// h.  The force tables are dimensionless: sigma enters as read, a given slope
+// as h * slope, an estimated one (already per cell) as it is.  The potential
+// carries one more length and the sign of the Green's function -1/rho, so
+// every multiplier takes a further -h (the tables are in units of the pair's
+// finer cell; Case-3 tables absorb the ratio to a coarser source's h).
+void row_scales(const td_plan* P, double h, int f, RowFwdJob* j)
+{
+    const double q = P->quantity == TD_POTENTIAL ? -h : 1.0;
+    j->scale = f == 0 ? q : q * h;
+    j->est_scale = q;
 }
 
 // Emit every job of a plan (workspace addresses as byte offsets) and the
@@ -703,7 +722,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 j.ld = G.ny;
                 j.row0 = r0;
                 j.nrow = std::min(R, G.ny - r0);
-                j.scale = f == 0 ? 1.0 : G.h;
+                row_scales(P, G.h, f, &j);
                 j.out = ptr(own_in[l] + f * plane);
                 g.rowfwd.push_back(j);
             }
@@ -734,7 +753,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                             j.ld = nr;
                             j.row0 = r0;
                             j.nrow = std::min(R, nr - r0);
-                            j.scale = f == 0 ? 1.0 : S.h;
+                            row_scales(P, S.h, f, &j);
                             j.out = ptr(in);
                             g.rowfwd.push_back(j);
                         }
@@ -744,6 +763,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     }
     // ---- pass 2: column transforms, products and inverse column
     // transforms, per lattice
+    const int fam = P->quantity == TD_POTENTIAL ? 8 : 0;  // kernel family bit
     for (int t = 0; t < L; ++t) {
         const LevelG& G = P->lv[t];
         Group& g = group_for(P->groups, G.M);
@@ -756,7 +776,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             const SpecEntry* k1 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
             for (int f = 0; f < 3; ++f)
-                g.colins.push_back({ptr(own_in[t] + f * H * G.ny), k1->ptr, G.ny, 0, f, 4});
+                g.colins.push_back({ptr(own_in[t] + f * H * G.ny), k1->ptr, G.ny, 0, f, 4 | fam});
             for (int s = t + 1; s < L; ++s) {
                 const LevelG& S = P->lv[s];
                 const int m = ipow(r, s - t), nr = ph_nr[s][t];
@@ -774,7 +794,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                     const void* kern = phase_kernels(k2, m, kx, ky, per_phase * es, &flip);
                     for (int f = 0; f < 3; ++f)
                         g.colins.push_back({ptr(ph_in[s][t] + ((size_t)phase * 3 + f) * H * nr), kern,
-                                            nr, lr_lo, f, flip});
+                                            nr, lr_lo, f, flip | fam});
                 }
             }
             const int out0 = (int)g.colouts.size();
@@ -801,7 +821,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 const void* kern = phase_kernels(k3, m, kx, ky, per_phase * es, &flip);
                 for (int comp = 0; comp < 2; ++comp)
                     g.colouts.push_back({ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld), kern, ld,
-                                         floor_div(T.oy, m) - G.oy, comp, flip});
+                                         floor_div(T.oy, m) - G.oy, comp, flip | fam});
             }
             const int nout = (int)g.colouts.size() - out0;
             const int chunk = 16 * Gs;
@@ -925,7 +945,11 @@ td_status validate_jobs(td_plan* P)
             // slope fields are scaled by their level's cell side, which the
             // row kernel's in-place slope estimate (per-cell differences)
             // takes for granted
-            if (j.scale != (j.f == 0 ? 1.0 : P->lv[j.lvl].h)) return bad("row scale");
+            {
+                RowFwdJob w;
+                row_scales(P, P->lv[j.lvl].h, j.f, &w);
+                if (j.scale != w.scale || j.est_scale != w.est_scale) return bad("row scale");
+            }
             if (j.row0 < 0 || j.nrow < 1 || j.nrow > 2 * g.C[P_ROWFWD] || j.row0 + j.nrow > j.ld)
                 return bad("row range");
             if (!in_ws(j.out, (int64_t)H * j.ld)) return bad("row output");
@@ -939,7 +963,9 @@ td_status validate_jobs(td_plan* P)
         for (size_t i = 0; i < g.colins.size(); ++i) {
             const ColIn& I = g.colins[i];
             if (I.ld < 1 || I.lr_first < 0 || I.lr_first + I.ld > M) return bad("col input rows");
-            if (I.f < 0 || I.f > 2 || I.flip < 0 || I.flip > 4) return bad("col input kernel");
+            if (I.f < 0 || I.f > 2 || (I.flip & ~8) < 0 || (I.flip & ~8) > 4 ||
+                ((I.flip >> 3) & 1) != (P->quantity == TD_POTENTIAL ? 1 : 0))
+                return bad("col input kernel");
             if (!in_ws(I.in, (int64_t)H * I.ld)) return bad("col input plane");
             auto it = rows_written.find(I.in);
             if (it == rows_written.end() || (int)it->second.size() < I.ld) return bad("col reads unwritten rows");
@@ -950,7 +976,9 @@ td_status validate_jobs(td_plan* P)
         for (auto& O : g.colouts) {
             if (O.out_ld < 1 || O.out_lr_first < 0 || O.out_lr_first + O.out_ld > M) return bad("col output rows");
             if (!in_ws(O.out, (int64_t)H * O.out_ld)) return bad("col output plane");
-            if (O.comp < 0 || O.comp > 1 || O.flip < 0 || O.flip > 3) return bad("col output kernel");
+            if (O.comp < 0 || O.comp > 1 || (O.flip & ~8) < 0 || (O.flip & ~8) > 3 ||
+                (O.kern && ((O.flip >> 3) & 1) != (P->quantity == TD_POTENTIAL ? 1 : 0)))
+                return bad("col output kernel");
         }
         std::map<int64_t, std::pair<int, std::vector<char>>> out_written;  // ld, columns
         for (auto& j : g.col) {
@@ -1273,17 +1301,20 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
 
 td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v, size_t base)
 {
-    if (!q.sigma || !q.fx || !q.fy) return fail(TD_EINVAL, "sigma, fx and fy are required");
+    const bool pot = P.quantity == TD_POTENTIAL;  // fx receives Phi; fy optional
+    if (!q.sigma || !q.fx || (!q.fy && !pot))
+        return fail(TD_EINVAL, pot ? "sigma and fx are required" : "sigma, fx and fy are required");
     if (q.slopes != TD_SLOPES_GIVEN && q.slopes != TD_SLOPES_ESTIMATE)
         return fail(TD_EINVAL, "slopes must be TD_SLOPES_GIVEN or TD_SLOPES_ESTIMATE");
     if (q.slopes == TD_SLOPES_ESTIMATE && (q.dsdx || q.dsdy))
         return fail(TD_EINVAL, "dsdx and dsdy must be NULL with TD_SLOPES_ESTIMATE");
     const uintptr_t align = P.dt == TD_F64 ? 8 : 4;
     for (int l = 0; l < P.npatches; ++l) {
-        if (!q.sigma[l] || !q.fx[l] || !q.fy[l])
+        void* fyl = q.fy ? q.fy[l] : nullptr;
+        if (!q.sigma[l] || !q.fx[l] || (!fyl && !pot))
             return fail(TD_EINVAL, "NULL sigma/fx/fy pointer of patch " + std::to_string(l));
         void* f[5] = {(void*)q.sigma[l], q.dsdx ? (void*)q.dsdx[l] : nullptr,
-                      q.dsdy ? (void*)q.dsdy[l] : nullptr, q.fx[l], q.fy[l]};
+                      q.dsdy ? (void*)q.dsdy[l] : nullptr, q.fx[l], fyl};
         for (int i = 0; i < 5; ++i) {
             if ((uintptr_t)f[i] % align)
                 return fail(TD_EINVAL, "field pointer of patch " + std::to_string(l) +
@@ -1362,13 +1393,22 @@ extern "C" td_status td_context_usage(const td_context* c, size_t* in_use, size_
 extern "C" td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_dtype dt,
                                     td_plan** out)
 {
+    return td_plan_create_quantity(ctx, h, dt, TD_FORCE, out);
+}
+
+extern "C" td_status td_plan_create_quantity(td_context* ctx, const td_hierarchy* h, td_dtype dt,
+                                             int32_t quantity, td_plan** out)
+{
     if (!ctx || !out) return fail(TD_EINVAL, "NULL argument");
     *out = nullptr;
     if (dt != TD_F32 && dt != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
+    if (quantity != TD_FORCE && quantity != TD_POTENTIAL)
+        return fail(TD_EINVAL, "quantity must be TD_FORCE or TD_POTENTIAL");
     TD_TRY(td_hierarchy_check(h));
     DeviceGuard dg(ctx->device);
     std::unique_ptr<td_plan> P(new td_plan());
     P->ctx = ctx;
+    P->quantity = quantity;
     TD_TRY(plan_geometry(P.get(), h, dt));
     size_t elems = 0;
     td_status st = build_jobs(P.get(), &elems, true);
@@ -2021,10 +2061,12 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
 // public: diagnostics
 // ===========================================================================
 
-extern "C" td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, int32_t m,
-                                     int32_t kx, int32_t ky, double* out_host)
+extern "C" td_status td_kernel_table(td_context* ctx, int32_t quantity, int32_t M, int32_t kind,
+                                     int32_t m, int32_t kx, int32_t ky, double* out_host)
 {
     if (!ctx || !out_host) return fail(TD_EINVAL, "NULL argument");
+    if (quantity != TD_FORCE && quantity != TD_POTENTIAL)
+        return fail(TD_EINVAL, "quantity must be TD_FORCE or TD_POTENTIAL");
     if (M < 16 || M > 4096 || (M & (M - 1))) return fail(TD_EINVAL, "M must be a power of two in 16..4096");
     if (kind < 1 || kind > 3) return fail(TD_EINVAL, "kind must be 1, 2 or 3");
     if (kind == 1) m = 1;
@@ -2041,6 +2083,7 @@ extern "C" td_status td_kernel_table(td_context* ctx, int32_t M, int32_t kind, i
     j.m = m;
     j.kx = kx;
     j.ky = ky;
+    j.family = quantity == TD_POTENTIAL ? 1 : 0;
     j.out = (double*)d;
     hipError_t e = launch_table(j, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -2083,9 +2126,11 @@ extern "C" td_status td_timing_read(td_context* ctx, double* ms, int64_t* launch
     return TD_OK;
 }
 
-extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
+extern "C" td_status td_plan_traffic(const td_plan* P, int32_t slopes, double* bytes)
 {
     if (!P || !bytes) return fail(TD_EINVAL, "NULL argument");
+    if (slopes != TD_SLOPES_GIVEN && slopes != TD_SLOPES_ESTIMATE)
+        return fail(TD_EINVAL, "slopes must be TD_SLOPES_GIVEN or TD_SLOPES_ESTIMATE");
     const double cs = (double)elem_size(P->dt), rs = cs / 2;
     for (int p = 0; p < NTIMED; ++p) bytes[p] = 0;
     for (auto& g : P->groups) {
@@ -2103,7 +2148,9 @@ extern "C" td_status td_plan_traffic(const td_plan* P, double* bytes)
                 const int sr = j.m * (j.lr_first + r) + j.row_off;
                 rows += (sr >= 0 && sr < S.ny) ? 1 : 0;
             }
-            bytes[P_ROWFWD] += (double)rows * cols * rs + (double)H * j.nrow * cs;
+            // estimated slopes re-read sigma's values (counted with sigma)
+            const bool reads = j.f == 0 || slopes == TD_SLOPES_GIVEN;
+            bytes[P_ROWFWD] += (reads ? (double)rows * cols * rs : 0.0) + (double)H * j.nrow * cs;
         }
         // col: every input plane, every stored kernel plane it multiplies
         // (real quarter planes for same-level kernels) and every output

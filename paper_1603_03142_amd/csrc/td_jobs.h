@@ -45,7 +45,8 @@ struct RowFwdJob {
     int32_t row0;       // first stored row of this job
     int32_t nrow;       // rows of this job
     int32_t pad;
-    double scale;       // multiplies every value (slope scaling)
+    double scale;       // multiplies every value read (sigma, or a given slope)
+    double est_scale;   // multiplies a slope estimated from sigma (per-cell units)
     int64_t out;        // workspace byte offset: complex [M/2+1][ld]
 };
 
@@ -57,7 +58,8 @@ struct ColIn {
     const void* kern;    // stored kernel spectra of the level pair (see kern_at)
     int32_t ld, lr_first;
     int32_t f;           // field: 0 sigma, 1 dsdx, 2 dsdy
-    int32_t flip;        // mirror / layout bits of the stored spectrum
+    int32_t flip;        // bits 0/1: x/y mirror, 2: quarter-real layout,
+                         // 3: potential kernel family (parities P0, Px, Py)
 };
 
 // One output plane of the column pass: the inverse column FFT of a sum of
@@ -67,8 +69,8 @@ struct ColOut {
     int64_t out;         // workspace offset
     const void* kern;    // Case-3' outputs: the phase's stored kernel spectra
     int32_t out_ld, out_lr_first;
-    int32_t comp;        // 0: Fx, 1: Fy
-    int32_t flip;        // Case-3' outputs: mirror bits of the phase
+    int32_t comp;        // 0: Fx (or the potential), 1: Fy
+    int32_t flip;        // Case-3' outputs: mirror bits of the phase (as ColIn)
 };
 
 // Columns [kx0, kx0 + ncol) of one job; a workgroup holds C columns x G
@@ -119,7 +121,7 @@ struct RowInvTables {
 // real M x M tables [X][ny][nx].
 struct TableJob {
     int32_t M, kind, m, kx, ky;
-    int32_t pad;
+    int32_t family;     // 0: force tables; 1: potential (P0, Px, Py, then zeros)
     double* out;
 };
 

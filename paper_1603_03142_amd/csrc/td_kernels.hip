@@ -78,7 +78,40 @@ __device__ void cell_integrals(double ua, double ub, double va, double vb, doubl
     out[5] = -rr - uc * j0;
 }
 
-// Entry (nx, ny) of the six M x M tables of one phase.  The lattice offset
+// Potential cell integrals of [ua,ub] x [va,vb] (target at the origin):
+// P0 = int 1/r, Px = int (u-uc)/r, Py = int (v-vc)/r, for the Green's
+// function -1/rho of eq. eqnPhixy0 (the sign is applied with the scale).
+// Antiderivatives u ln(v+r) + v ln(u+r), v r/2 + (u^2/2) ln(v+r) and their
+// exchange, regrouped like the force integrals: the ln-differences at fixed
+// u (A) and fixed v (B), and the r-differences at fixed v or u in product
+// form.
+__device__ void cell_potential(double ua, double ub, double va, double vb, double* out)
+{
+    double Aa = branch_diff(ua, va, vb), Ab = branch_diff(ub, va, vb);
+    double Ba = branch_diff(va, ua, ub), Bb = branch_diff(vb, ua, ub);
+    // [u ln(v+r)] and [v ln(u+r)]; a zero factor gives its limit 0
+    double su = (ub != 0 ? ub * Ab : 0.0) - (ua != 0 ? ua * Aa : 0.0);
+    double sv = (vb != 0 ? vb * Bb : 0.0) - (va != 0 ? va * Ba : 0.0);
+    double p0 = su + sv;
+    double raa = sqrt(ua * ua + va * va), rab = sqrt(ua * ua + vb * vb);
+    double rba = sqrt(ub * ub + va * va), rbb = sqrt(ub * ub + vb * vb);
+    // [v r] = vb (r_bb - r_ab) - va (r_ba - r_aa), r-differences at fixed v
+    double dux = (ub - ua) * (ub + ua);
+    double vr = dux * (vb / (rbb + rab) - va / (rba + raa));
+    // [u r] = ub (r_bb - r_ba) - ua (r_ab - r_aa), at fixed u
+    double dvy = (vb - va) * (vb + va);
+    double ur = dvy * (ub / (rbb + rba) - ua / (rab + raa));
+    // [u^2 ln(v+r)] and [v^2 ln(u+r)]
+    double su2 = (ub != 0 ? ub * ub * Ab : 0.0) - (ua != 0 ? ua * ua * Aa : 0.0);
+    double sv2 = (vb != 0 ? vb * vb * Bb : 0.0) - (va != 0 ? va * va * Ba : 0.0);
+    double uc = 0.5 * (ua + ub), vc = 0.5 * (va + vb);
+    out[0] = p0;
+    out[1] = 0.5 * (vr + su2) - uc * p0;
+    out[2] = 0.5 * (ur + sv2) - vc * p0;
+}
+
+// Entry (nx, ny) of the six M x M tables of one phase (family 1: the three
+// potential tables, then three zero planes).  The lattice offset
 // (output - input) is n = nx or nx - M; n = M/2 is never used and is 0.
 //   kind 1 (same level):      cell [-n - 1/2, -n + 1/2]              (width 1)
 //   kind 2 (finer source, m): cell [-m n + k - m/2, ... + 1]          (width 1)
@@ -106,10 +139,21 @@ __global__ void k_table(TableJob J)
             va = -J.m * sy - J.ky - 0.5;
             w = J.m;
         }
-        cell_integrals(ua, ua + w, va, va + w, v);
-        if (J.kind == 3) {
-            const double inv = 1.0 / J.m;
-            v[1] *= inv; v[2] *= inv; v[4] *= inv; v[5] *= inv;
+        if (J.family == 0) {
+            cell_integrals(ua, ua + w, va, va + w, v);
+            if (J.kind == 3) {
+                const double inv = 1.0 / J.m;
+                v[1] *= inv; v[2] *= inv; v[4] *= inv; v[5] *= inv;
+            }
+        } else {
+            // the potential carries one more length than the force: a
+            // coarser source's inputs are scaled by its own cell side, m
+            // times the table unit, hence 1/m (1/m^2 for the slopes)
+            cell_potential(ua, ua + w, va, va + w, v);
+            if (J.kind == 3) {
+                const double inv = 1.0 / J.m;
+                v[0] *= inv; v[1] *= inv * inv; v[2] *= inv * inv;
+            }
         }
     }
     const size_t plane = (size_t)M * M;
@@ -153,15 +197,15 @@ __device__ __forceinline__ bool covered(gpatches L, int i, int j)
 // neighbouring values along x (f == 1) or y (f == 2), the one-sided
 // difference in the patch's first and last column / row, 0 when n == 1.
 template <typename T>
-__device__ __forceinline__ T cell_slope(const T* __restrict__ s, int n, int i, int j, int f)
+__device__ __forceinline__ double cell_slope(const T* __restrict__ s, int n, int i, int j, int f)
 {
     const int c = f == 1 ? i : j;
     const ptrdiff_t st = f == 1 ? 1 : (ptrdiff_t)n;
     const T* p = s + (ptrdiff_t)j * n + i;
-    if (n == 1) return (T)0;
-    if (c == 0) return (T)((double)p[st] - (double)p[0]);
-    if (c == n - 1) return (T)((double)p[0] - (double)p[-st]);
-    return (T)(0.5 * ((double)p[st] - (double)p[-st]));
+    if (n == 1) return 0.0;
+    if (c == 0) return (double)p[st] - (double)p[0];
+    if (c == n - 1) return (double)p[0] - (double)p[-st];
+    return 0.5 * ((double)p[st] - (double)p[-st]);
 }
 
 template <typename T, int M>
@@ -203,10 +247,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
             if (!src || i < 0 || i >= n) continue;
             const int j0 = sr0 - L->pj0[k], j1 = sr1 - L->pj0[k];
             if (s0 < rend && j0 >= 0 && j0 < n && !covered(L, scol, sr0))
-                a = est ? cell_slope(src, n, i, j0, J.f)
+                a = est ? (T)(J.est_scale * cell_slope(src, n, i, j0, J.f))
                         : (T)(J.scale * (double)src[(size_t)j0 * n + i]);
             if (s0 + 1 < rend && j1 >= 0 && j1 < n && !covered(L, scol, sr1))
-                b = est ? cell_slope(src, n, i, j1, J.f)
+                b = est ? (T)(J.est_scale * cell_slope(src, n, i, j1, J.f))
                         : (T)(J.scale * (double)src[(size_t)j1 * n + i]);
         }
         buf[p * SP + lds_pos(lc)] = cpx<T>{a, b};
@@ -243,6 +287,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
 // written as bit masks of the negative entries.
 __host__ __device__ constexpr int sign_x(int X) { return ((0x25 >> X) & 1) ? -1 : 1; }
 __host__ __device__ constexpr int sign_y(int X) { return ((0x2C >> X) & 1) ? -1 : 1; }
+// Potential family (flip bit 3): P0 even in both axes, Px odd in x, Py odd
+// in y; the zero planes 3-5 take any sign.
+__host__ __device__ constexpr int sign_x(int X, int fam) { return fam ? (X == 1 ? -1 : 1) : sign_x(X); }
+__host__ __device__ constexpr int sign_y(int X, int fam) { return fam ? (X == 2 ? -1 : 1) : sign_y(X); }
 // Kernel feeding output component c (0: Fx, 1: Fy) from field f (sigma,
 // dsdx, dsdy): I0, Ixx, Ixy for Fx and J0, Jyx, Jyy for Fy.
 __host__ __device__ constexpr int kern_of(int c, int f) { return c == 0 ? f : 3 + (3 - f) % 3; }
@@ -278,10 +326,11 @@ __device__ __forceinline__ void kern_column(cpx<T>* kv, const void* Kv, int X, i
                                             int lane)
 {
     constexpr int TPS = M / 8, H = M / 2 + 1;
+    const int fam = (flip >> 3) & 1;
     if (flip & 4) {
         gptr<T> R = (gptr<T>)Kv + ((size_t)X * H + kx) * H;
-        const T sy = (T)sign_y(X);
-        const bool imag = sign_x(X) * sign_y(X) < 0;
+        const T sy = (T)sign_y(X, fam);
+        const bool imag = sign_x(X, fam) * sign_y(X, fam) < 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             T v;
@@ -296,9 +345,10 @@ __device__ __forceinline__ void kern_column(cpx<T>* kv, const void* Kv, int X, i
         }
     } else {
         gptr<cpx<T>> K = (gptr<cpx<T>>)Kv + ((size_t)X * H + kx) * M;
-        const bool rev = flip == 1 || flip == 2;
-        const T s = (T)(((flip & 1) ? sign_x(X) : 1) * ((flip & 2) ? sign_y(X) : 1));
-        const T si = (flip & 1) ? -s : s;  // x-mirrors conjugate
+        const int mir = flip & 3;
+        const bool rev = mir == 1 || mir == 2;
+        const T s = (T)(((mir & 1) ? sign_x(X, fam) : 1) * ((mir & 2) ? sign_y(X, fam) : 1));
+        const T si = (mir & 1) ? -s : s;  // x-mirrors conjugate
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int ky = lane + q * TPS;
@@ -684,7 +734,8 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
 template <typename TO, int M>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* __restrict__ rows,
                                                    void* __restrict__ out_v,
-                                                   const cpx<double>* __restrict__ tw_g, int quarter)
+                                                   const cpx<double>* __restrict__ tw_g,
+                                                   int quarter)  // bit 0: layout, bit 1: family
 {
     cpx<TO>* out = reinterpret_cast<cpx<TO>*>(out_v);
     TO* outq = reinterpret_cast<TO*>(out_v);
@@ -712,11 +763,12 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
         const int c = i / M, ky = i % M;
         if (kx0 + c >= NCOL) continue;
         const cpx<double> v = buf[c * SP + lds_pos(ky)];
-        if (!quarter) {
+        if (!(quarter & 1)) {
             out[((size_t)X * NCOL + kx0 + c) * M + ky] = cpx<TO>{(TO)(v.re * sc), (TO)(v.im * sc)};
         } else if (ky <= M / 2) {
             // same-level kernel: real (s_x s_y = +1) or imaginary spectrum
-            const double r = (sign_x(X) * sign_y(X) > 0) ? v.re : v.im;
+            const int fam = (quarter >> 1) & 1;
+            const double r = (sign_x(X, fam) * sign_y(X, fam) > 0) ? v.re : v.im;
             outq[((size_t)X * NCOL + kx0 + c) * NCOL + ky] = (TO)(r * sc);
         }
     }

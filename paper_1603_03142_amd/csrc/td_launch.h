@@ -60,6 +60,8 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
                           void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st);
+// quarter: bit 0 = quarter-real layout (same-level spectra), bit 1 = the
+// potential kernel family (its parities decide real vs imaginary planes)
 template <typename TO>
 hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void* tw64,
                            int quarter, hipStream_t st);

@@ -42,7 +42,8 @@ def test_binding_structs_match_header(tmp_path):
         '  printf("%zu %zu %zu %zu %zu %zu %d %d %d %d\\n", sizeof(td_patch), sizeof(td_hierarchy),'
         " offsetof(td_hierarchy, patches), sizeof(td_request), offsetof(td_request, fy),"
         " offsetof(td_request, slopes), TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE, TD_MAX_PATCHES,"
-        " TD_MAX_LEVELS);\n  return 0;\n}\n")
+        " TD_MAX_LEVELS);\n"
+        '  printf("%d %d\\n", TD_FORCE, TD_POTENTIAL);\n  return 0;\n}\n')
     exe = tmp_path / "probe"
     import subprocess
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(probe), "-o",
@@ -51,7 +52,8 @@ def test_binding_structs_match_header(tmp_path):
                                           text=True).stdout.split()]
     want = [ctypes.sizeof(B.td_patch), ctypes.sizeof(B.td_hierarchy), B.td_hierarchy.patches.offset,
             ctypes.sizeof(B.td_request), B.td_request.fy.offset, B.td_request.slopes.offset,
-            B.TD_SLOPES_GIVEN, B.TD_SLOPES_ESTIMATE, B.TD_MAX_PATCHES, B.TD_MAX_LEVELS]
+            B.TD_SLOPES_GIVEN, B.TD_SLOPES_ESTIMATE, B.TD_MAX_PATCHES, B.TD_MAX_LEVELS,
+            B.TD_FORCE, B.TD_POTENTIAL]
     assert got == want
 
 

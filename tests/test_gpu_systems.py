@@ -254,6 +254,10 @@ def test_timing_and_traffic(ctx):
         assert t[p][1] == 3 and t[p][0] > 0
     tr = plan.traffic()
     assert all(tr[p] > 0 for p in ("row_fwd", "col", "row_inv"))
+    # estimated slopes read sigma only: less in the row pass, the rest equal
+    te = plan.traffic("estimate")
+    assert te["row_fwd"] < tr["row_fwd"]
+    assert all(te[p] == tr[p] for p in ("col", "row_inv", "row_inv_acc"))
     ws, spec = plan.footprint()
     assert ws > 0 and spec > 0
 
