@@ -53,7 +53,8 @@ def lib():
             L.oracle_cell_integrals.argtypes = [ctypes.c_double] * 4 + [dp]
             L.oracle_cell_integrals.restype = None
             L.oracle_forces.argtypes = [ctypes.c_int, ip, ip, ip, ip, ctypes.c_double,
-                                        ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int,
                                         ctypes.POINTER(dp), ctypes.POINTER(dp),
                                         ctypes.POINTER(dp), ctypes.c_int, ip, ip, ip, dp, dp,
                                         ctypes.c_int]
@@ -146,7 +147,8 @@ def _direct(hier, sigma, dsdx, dsdy, targets, nthreads, potential):
         tp, ti, tj = (np.ascontiguousarray(t, dtype=np.int32) for t in targets)
     fx = np.zeros(len(tp))
     fy = np.zeros(len(tp))
-    geo = (P, _ip(level), _ip(n), _ip(ox), _ip(oy), hier.x0, hier.y0, hier.h0, hier.ratio,
+    geo = (P, _ip(level), _ip(n), _ip(ox), _ip(oy), hier.x0, hier.y0, hier.h0,
+           float(getattr(hier, "aspect", 1.0)), hier.ratio,
            ps, px, py, len(tp), _ip(tp), _ip(ti), _ip(tj))
     if potential:
         rc = lib().oracle_potential(*geo, _dp(fx), int(nthreads))

@@ -194,8 +194,8 @@ static int cell_covered(int npatch, const int* level, const int* n, const int* o
  * Direct sums at a list of targets: forces (what = 0: out0 = fx, out1 = fy)
  * or the potential (what = 1: out0 = phi, out1 unused, may be NULL).
  *   npatch patches; patch p is on level level[p], has n[p] x n[p] cells of
- *   side h0 / ratio^level[p], lower-left corner at
- *   (x0 + ox[p] h, y0 + oy[p] h).
+ *   width h = h0 / ratio^level[p] and height aspect * h, lower-left corner
+ *   at (x0 + ox[p] h, y0 + oy[p] aspect h).
  *   sigma[p], dsdx[p], dsdy[p]: n[p]*n[p] doubles, row-major [j][i] (x
  *   fastest); dsdx / dsdy arrays may be NULL pointers (slope 0).
  *   Targets: (tpatch[k], ti[k], tj[k]) cell centres.  fx[k], fy[k] receive
@@ -203,7 +203,7 @@ static int cell_covered(int npatch, const int* level, const int* n, const int* o
  * Returns 0, or -1 on a malformed target index.
  */
 static int direct_sum(int what, int npatch, const int* level, const int* n, const int* ox,
-                      const int* oy, double x0, double y0, double h0, int ratio,
+                      const int* oy, double x0, double y0, double h0, double aspect, int ratio,
                       const double* const* sigma, const double* const* dsdx,
                       const double* const* dsdy, int ntarget, const int* tpatch,
                       const int* ti, const int* tj, double* fx, double* fy, int nthreads)
@@ -217,12 +217,14 @@ static int direct_sum(int what, int npatch, const int* level, const int* n, cons
     ld* hp = (ld*)malloc(sizeof(ld) * (size_t)npatch);
     ld* xl = (ld*)malloc(sizeof(ld) * (size_t)npatch);
     ld* yl = (ld*)malloc(sizeof(ld) * (size_t)npatch);
+    ld* hq = (ld*)malloc(sizeof(ld) * (size_t)npatch);
     for (int p = 0; p < npatch; ++p) {
         ld h = h0;
         for (int l = 0; l < level[p]; ++l) h /= ratio;
         hp[p] = h;
+        hq[p] = h * (ld)aspect;
         xl[p] = (ld)x0 + ox[p] * h;
-        yl[p] = (ld)y0 + oy[p] * h;
+        yl[p] = (ld)y0 + oy[p] * hq[p];
     }
     /* Active flags of every source cell. */
     size_t total = 0;
@@ -252,15 +254,15 @@ static int direct_sum(int what, int npatch, const int* level, const int* n, cons
             continue;
         }
         ld xt = xl[q] + (ti[k] + (ld)0.5) * hp[q];
-        ld yt = yl[q] + (tj[k] + (ld)0.5) * hp[q];
+        ld yt = yl[q] + (tj[k] + (ld)0.5) * hq[q];
         acc_t ax = {0, 0}, ay = {0, 0};
         for (int p = 0; p < npatch; ++p) {
-            ld h = hp[p];
+            ld h = hp[p], hy = hq[p];
             const double* s = sigma[p];
             const double* sx = dsdx ? dsdx[p] : NULL;
             const double* sy = dsdy ? dsdy[p] : NULL;
             for (int j = 0; j < n[p]; ++j) {
-                ld va = yl[p] + j * h - yt, vb = yl[p] + (j + 1) * h - yt;
+                ld va = yl[p] + j * hy - yt, vb = yl[p] + (j + 1) * hy - yt;
                 for (int i = 0; i < n[p]; ++i) {
                     size_t idx = (size_t)j * n[p] + i;
                     if (!active[base[p] + idx]) continue;
@@ -291,6 +293,7 @@ static int direct_sum(int what, int npatch, const int* level, const int* n, cons
         if (fy) fy[k] = (double)(ay.s + ay.c);
     }
     free(hp);
+    free(hq);
     free(xl);
     free(yl);
     free(active);
@@ -299,22 +302,22 @@ static int direct_sum(int what, int npatch, const int* level, const int* n, cons
 }
 
 int oracle_forces(int npatch, const int* level, const int* n, const int* ox, const int* oy,
-                  double x0, double y0, double h0, int ratio,
+                  double x0, double y0, double h0, double aspect, int ratio,
                   const double* const* sigma, const double* const* dsdx,
                   const double* const* dsdy, int ntarget, const int* tpatch,
                   const int* ti, const int* tj, double* fx, double* fy, int nthreads)
 {
-    return direct_sum(0, npatch, level, n, ox, oy, x0, y0, h0, ratio, sigma, dsdx, dsdy,
+    return direct_sum(0, npatch, level, n, ox, oy, x0, y0, h0, aspect, ratio, sigma, dsdx, dsdy,
                       ntarget, tpatch, ti, tj, fx, fy, nthreads);
 }
 
 int oracle_potential(int npatch, const int* level, const int* n, const int* ox,
-                     const int* oy, double x0, double y0, double h0, int ratio,
+                     const int* oy, double x0, double y0, double h0, double aspect, int ratio,
                      const double* const* sigma, const double* const* dsdx,
                      const double* const* dsdy, int ntarget, const int* tpatch,
                      const int* ti, const int* tj, double* phi, int nthreads)
 {
-    return direct_sum(1, npatch, level, n, ox, oy, x0, y0, h0, ratio, sigma, dsdx, dsdy,
+    return direct_sum(1, npatch, level, n, ox, oy, x0, y0, h0, aspect, ratio, sigma, dsdx, dsdy,
                       ntarget, tpatch, ti, tj, phi, NULL, nthreads);
 }
 

@@ -38,10 +38,9 @@ def _diff_along(s: np.ndarray, h: float, axis: int) -> np.ndarray:
 
 def slopes(hier, sigma):
     """(dsdx, dsdy): one float64 [n][n] array per patch, row-major [y][x] like
-    ``sigma``; h is the patch's own cell side."""
+    ``sigma``; h is the patch's own cell width (x) or height (y)."""
     dsdx, dsdy = [], []
     for p, s in zip(hier.patches, sigma):
-        h = hier.h(p.level)
-        dsdx.append(_diff_along(s, h, axis=1))
-        dsdy.append(_diff_along(s, h, axis=0))
+        dsdx.append(_diff_along(s, hier.h(p.level), axis=1))
+        dsdy.append(_diff_along(s, hier.h(p.level) * getattr(hier, "aspect", 1.0), axis=0))
     return dsdx, dsdy

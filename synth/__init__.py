@@ -50,17 +50,22 @@ class Hierarchy:
     h0: float
     ratio: int
     patches: List[Patch]
+    aspect: float = 1.0  # cell height / cell width, the same on every level
 
     @property
     def nlevels(self) -> int:
         return 1 + max(p.level for p in self.patches)
 
     def h(self, level: int) -> float:
+        """Cell width (x side) on ``level``."""
         return self.h0 / (self.ratio ** level)
 
+    def hy(self, level: int) -> float:
+        """Cell height (y side) on ``level``."""
+        return self.h(level) * self.aspect
+
     def lower_left(self, p: Patch) -> Tuple[float, float]:
-        h = self.h(p.level)
-        return self.x0 + p.ox * h, self.y0 + p.oy * h
+        return self.x0 + p.ox * self.h(p.level), self.y0 + p.oy * self.hy(p.level)
 
     @property
     def cells(self) -> int:
@@ -72,10 +77,10 @@ class Hierarchy:
 
 
 def nested_hierarchy(x0: float, y0: float, h0: float, ratio: int,
-                     levels: Sequence[Tuple[int, int, int]]) -> Hierarchy:
+                     levels: Sequence[Tuple[int, int, int]], aspect: float = 1.0) -> Hierarchy:
     """One patch per level; ``levels[l] = (n, ox, oy)``."""
     return Hierarchy(x0, y0, h0, ratio,
-                     [Patch(l, n, ox, oy) for l, (n, ox, oy) in enumerate(levels)])
+                     [Patch(l, n, ox, oy) for l, (n, ox, oy) in enumerate(levels)], aspect)
 
 
 def snap_offsets(x0: float, y0: float, h0: float, ratio: int, n_levels: Sequence[int],
@@ -194,11 +199,10 @@ def total(*fs):
 # ----------------------------------------------------------------------------
 
 def cell_centres(hier: Hierarchy, p: Patch) -> Tuple[np.ndarray, np.ndarray]:
-    h = hier.h(p.level)
     xl, yl = hier.lower_left(p)
     i = np.arange(p.n, dtype=np.float64)
-    xc = xl + (i + 0.5) * h
-    yc = yl + (i + 0.5) * h
+    xc = xl + (i + 0.5) * hier.h(p.level)
+    yc = yl + (i + 0.5) * hier.hy(p.level)
     X, Y = np.meshgrid(xc, yc)  # [j][i]
     return X, Y
 
@@ -230,11 +234,11 @@ def sample_fields(hier: Hierarchy, sigma_fn: Callable, slopes: str = "central",
     sig, dx, dy = [], [], []
     for p in hier.patches:
         X, Y = cell_centres(hier, p)
-        h = hier.h(p.level)
+        h, hy = hier.h(p.level), hier.hy(p.level)
         sig.append(np.ascontiguousarray(sigma_fn(X, Y), dtype=np.float64))
         if slopes == "central":
             dx.append(np.ascontiguousarray((sigma_fn(X + h, Y) - sigma_fn(X - h, Y)) / (2 * h)))
-            dy.append(np.ascontiguousarray((sigma_fn(X, Y + h) - sigma_fn(X, Y - h)) / (2 * h)))
+            dy.append(np.ascontiguousarray((sigma_fn(X, Y + hy) - sigma_fn(X, Y - hy)) / (2 * hy)))
         elif slopes == "analytic":
             gx, gy = grad_fn(X, Y)
             dx.append(np.ascontiguousarray(gx, dtype=np.float64))

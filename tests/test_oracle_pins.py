@@ -161,6 +161,10 @@ HIERS = {
     "three": synth.nested_hierarchy(-1.0, -1.0, 2 / 8, 2, [(8, 0, 0), (8, 4, 2), (6, 10, 8)]),
     "ratio3": synth.nested_hierarchy(-1.0, -1.0, 2 / 9, 3, [(9, 0, 0), (9, 6, 9), (9, 24, 33)]),
     "two_patches": synth.random_patches(4, n0=12, levels=3, per_level=2, ratio=2),
+    # rectangular cells (height = aspect x width on every level)
+    "aspect_half": synth.nested_hierarchy(-1.0, -0.5, 2 / 10, 2, [(10, 0, 0), (8, 6, 4)], 0.5),
+    "aspect_1p7": synth.nested_hierarchy(-1.0, -1.7, 2 / 8, 2,
+                                         [(8, 0, 0), (8, 4, 2), (6, 10, 8)], 1.7),
 }
 
 
@@ -178,7 +182,7 @@ def test_telescoping_linear_density(name):
     dy = [np.full_like(s, c) for s in sig]
     p0 = hier.patches[0]
     L, B = hier.x0, hier.y0
-    Rr, T = L + p0.n * hier.h0, B + p0.n * hier.h0
+    Rr, T = L + p0.n * hier.h0, B + p0.n * hier.hy(0)
     rng = np.random.default_rng(2)
     tp, ti, tj = [], [], []
     for k, p in enumerate(hier.patches):
@@ -188,9 +192,8 @@ def test_telescoping_linear_density(name):
     fx, fy = oracle.forces(hier, sig, dx, dy, (np.array(tp), np.array(ti), np.array(tj)))
     for k in range(len(tp)):
         p = hier.patches[tp[k]]
-        h = hier.h(p.level)
         xl, yl = hier.lower_left(p)
-        xt, yt = xl + (ti[k] + 0.5) * h, yl + (tj[k] + 0.5) * h
+        xt, yt = xl + (ti[k] + 0.5) * hier.h(p.level), yl + (tj[k] + 0.5) * hier.hy(p.level)
         i0, j0, uu, vv, uv = domain_integrals_polar(xt, yt, L, Rr, B, T)
         wx = a * i0 + b * (uu + xt * i0) + c * (uv + yt * i0)
         wy = a * j0 + c * (vv + yt * j0) + b * (uv + xt * j0)
@@ -285,7 +288,7 @@ def test_potential_telescoping_linear_density(name):
     dy = [np.full_like(s, c) for s in sig]
     p0 = hier.patches[0]
     L, B = hier.x0, hier.y0
-    Rr, T = L + p0.n * hier.h0, B + p0.n * hier.h0
+    Rr, T = L + p0.n * hier.h0, B + p0.n * hier.hy(0)
     rng = np.random.default_rng(5)
     tp, ti, tj = [], [], []
     for k, p in enumerate(hier.patches):
@@ -295,9 +298,8 @@ def test_potential_telescoping_linear_density(name):
     phi = oracle.potential(hier, sig, dx, dy, (np.array(tp), np.array(ti), np.array(tj)))
     for k in range(len(tp)):
         p = hier.patches[tp[k]]
-        h = hier.h(p.level)
         xl, yl = hier.lower_left(p)
-        xt, yt = xl + (ti[k] + 0.5) * h, yl + (tj[k] + 0.5) * h
+        xt, yt = xl + (ti[k] + 0.5) * hier.h(p.level), yl + (tj[k] + 0.5) * hier.hy(p.level)
         q0, qu, qv = domain_potential_polar(xt, yt, L, Rr, B, T)
         want = -(a * q0 + b * (qu + xt * q0) + c * (qv + yt * q0))
         assert phi[k] == pytest.approx(want, rel=1e-11, abs=1e-12)
@@ -552,6 +554,37 @@ def test_analytic_slopes_miss_the_printed_einf():
 def _quad(hier, a, bx, by, cxx, cyy):
     return [a + bx * X + by * Y + cxx * X * X + cyy * Y * Y
             for X, Y in (synth.cell_centres(hier, p) for p in hier.patches)]
+
+
+def test_rectangular_cells_transpose():
+    """Exchanging x and y maps a grid of cells w x aw onto one of cells
+    aw x w (aspect 1/a, patch offsets exchanged): the forces exchange with
+    the fields transposed, the potential is transposed."""
+    a = 0.6
+    hier = synth.nested_hierarchy(-1.0, -0.7, 2 / 10, 2, [(10, 0, 0), (8, 6, 4)], a)
+    tr = synth.Hierarchy(hier.y0, hier.x0, hier.h0 * a, 2,
+                         [synth.Patch(p.level, p.n, p.oy, p.ox) for p in hier.patches], 1 / a)
+    sig, dx, dy = _rand_fields(hier, 21)
+    T = lambda arrs: [np.ascontiguousarray(x.T) for x in arrs]
+    fx, fy = oracle.forces(hier, sig, dx, dy)
+    gx, gy = oracle.forces(tr, T(sig), T(dy), T(dx))
+    phi = oracle.potential(hier, sig, dx, dy)
+    psi = oracle.potential(tr, T(sig), T(dy), T(dx))
+    for k in range(2):
+        np.testing.assert_allclose(gx[k], fy[k].T, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(gy[k], fx[k].T, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(psi[k], phi[k].T, rtol=1e-12, atol=1e-13)
+
+
+def test_slope_estimate_rectangular_cells():
+    """With cells of height a w, the y-differences divide by a w: a linear
+    density is still reproduced exactly."""
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2 / 9, 3, [(9, 0, 0), (9, 6, 9)], 1.8)
+    sig = _quad(hier, 0.3, 0.9, -2.2, 0.0, 0.0)
+    dx, dy = oracle.slopes(hier, sig)
+    for k in range(2):
+        np.testing.assert_allclose(dx[k], 0.9, rtol=1e-12)
+        np.testing.assert_allclose(dy[k], -2.2, rtol=1e-12)
 
 
 def test_slope_estimate_linear_exact():
