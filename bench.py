@@ -345,6 +345,19 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     value = cells * args.steps / elapsed
 
+    # latency of one solve on an idle device: enqueue to completion, each
+    # solve synchronised (after the timed region, so it does not change it)
+    lat = []
+    for _ in range(max(50, min(400, args.steps))):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat) * 1e3
+    latency = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "samples": len(lat),
+               "how": "single solves, each from enqueue to completion (host clock), device idle"}
+
     # roofline of the dominant pass (algorithmic bytes / mean launch time)
     roof = None
     traffic = plan.traffic(args.slopes)
@@ -432,6 +445,7 @@ def main():
                    "patches": [[p.level, p.n] for p in hier.patches], "ratio": hier.ratio,
                    "cells_per_solve": cells, "mode": args.mode, "slopes": args.slopes,
                    "plan_build_s": round(plan_s, 3), "autotune_s": tune_s},
+        "latency": latency,
         "roofline": roof,
         "cpu_baseline": cpu,
         "rel_l2_vs_oracle_sampled": acc,

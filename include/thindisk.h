@@ -25,10 +25,11 @@
  * v r/2 + (u^2/2) ln(v+r) and its exchange, through the same convolutions.
  *
  * Conventions
- *   - Level l holds one or more square patches of cells of side
- *     h0 / ratio^l (ratio 2, 3 or 4); level 0 is a single patch.  A patch's
- *     lower-left corner is (x0 + ox h_l, y0 + oy h_l): ox, oy are integer
- *     offsets in level-l cells from the level-0 origin.  Every patch of
+ *   - Level l holds one or more patches of n x n cells of width
+ *     h_l = h0 / ratio^l and height aspect * h_l (ratio 2, 3 or 4; the same
+ *     refinement ratio in x and y); level 0 is a single patch.  A patch's
+ *     lower-left corner is (x0 + ox h_l, y0 + oy aspect h_l): ox, oy are
+ *     integer offsets in level-l cells from the level-0 origin.  Every patch of
  *     level l+1 lies inside one patch of level l with its edges on level-l
  *     nodes (Section 2.1: integer ratio between nested levels).
  *   - A cell covered by a patch of level l+1 is not part of level l's
@@ -89,10 +90,13 @@ typedef struct {
  * first; every per-patch array of a request follows this order. */
 typedef struct {
     double x0, y0;           /* lower-left corner of level 0              */
-    double h0;               /* level-0 cell side                         */
+    double h0;               /* level-0 cell width (x side)               */
     int32_t ratio;           /* refinement ratio between levels: 2, 3, 4  */
     int32_t npatches;        /* 1 .. TD_MAX_PATCHES                       */
     const td_patch* patches; /* [npatches], grouped by level              */
+    double aspect;           /* cell height / width, every level (Section
+                                2.1 allows different x and y spacings);
+                                0 = square cells, else in [1/64, 64]      */
 } td_hierarchy;
 
 #define TD_MAX_LEVELS 8
@@ -260,14 +264,15 @@ td_status td_server_destroy(td_server* s);
 /* Write the FP64 kernel table of one level pair kind into host memory:
  * out[6][M][M], entry [ny][nx] is the cell integral for a lattice offset
  * (output - input) of (nx or nx-M, ny or ny-M), in units of the finer cell
- * side; kind = 1 (same level), 2 (finer source, ratio m), 3 (coarser
- * source, ratio m); (kx, ky) the polyphase phase.  TD_FORCE: I0, Ixx, Ixy,
+ * width (the cell height is aspect widths; 0 = square); kind = 1 (same
+ * level), 2 (finer source, ratio m), 3 (coarser source, ratio m); (kx, ky)
+ * the polyphase phase.  TD_FORCE: I0, Ixx, Ixy,
  * J0, Jyy, Jyx, Case-3 slope entries with the factor 1/m that converts the
  * coarse source's slope scaling.  TD_POTENTIAL: P0 = int 1/r, Px = int
  * (u-uc)/r, Py = int (v-vc)/r and three zero planes, Case-3 entries with
  * 1/m (slopes 1/m^2).  Synchronous; for tests. */
-td_status td_kernel_table(td_context* ctx, int32_t quantity, int32_t M, int32_t kind, int32_t m,
-                          int32_t kx, int32_t ky, double* out_host);
+td_status td_kernel_table(td_context* ctx, int32_t quantity, double aspect, int32_t M,
+                          int32_t kind, int32_t m, int32_t kx, int32_t ky, double* out_host);
 
 /* The timed launch kinds of a solve, in launch order. */
 #define TD_NPASS 4   /* row_fwd, col, row_inv, row_inv_accumulate */

@@ -113,10 +113,11 @@ class Context:
         return {p: (ms[i], n[i]) for i, p in enumerate(self.PASSES)}
 
     def kernel_table(self, M: int, kind: int, m: int = 1, kx: int = 0, ky: int = 0,
-                     quantity: str = "force"):
+                     quantity: str = "force", aspect: float = 1.0):
         import numpy as np
         out = np.zeros((6, M, M))
-        B.check(lib().td_kernel_table(self.handle, _QUANTITY[quantity], M, kind, m, kx, ky,
+        B.check(lib().td_kernel_table(self.handle, _QUANTITY[quantity], float(aspect), M, kind,
+                                      m, kx, ky,
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                 "td_kernel_table")
         return out

@@ -51,7 +51,7 @@ class td_patch(ctypes.Structure):
 class td_hierarchy(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("h0", ctypes.c_double),
                 ("ratio", ctypes.c_int32), ("npatches", ctypes.c_int32),
-                ("patches", ctypes.POINTER(td_patch))]
+                ("patches", ctypes.POINTER(td_patch)), ("aspect", ctypes.c_double)]
 
 
 VP = ctypes.c_void_p
@@ -110,8 +110,8 @@ def lib():
             "td_server_cancel": ([VP, ctypes.c_uint64], S),
             "td_server_stats": ([VP, u64, u64, u64, u64, u64, u64], S),
             "td_server_destroy": ([VP], S),
-            "td_kernel_table": ([VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+            "td_kernel_table": ([VP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)], S),
             "td_timing_enable": ([VP, ctypes.c_int], S),
             "td_timing_read": ([VP, ctypes.POINTER(ctypes.c_double),
@@ -147,7 +147,8 @@ def make_hierarchy(hier):
         pats = [(l, n, ox, oy) for l, (n, ox, oy) in enumerate(hier.levels)]
     arr = (td_patch * len(pats))(*[td_patch(*p) for p in pats])
     h = td_hierarchy(float(hier.x0), float(hier.y0), float(hier.h0), int(hier.ratio), len(pats),
-                     ctypes.cast(arr, ctypes.POINTER(td_patch)))
+                     ctypes.cast(arr, ctypes.POINTER(td_patch)),
+                     float(getattr(hier, "aspect", 1.0)))
     h._keep = arr
     return h
 

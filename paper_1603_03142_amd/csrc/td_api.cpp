@@ -135,7 +135,8 @@ struct td_context {
     std::atomic<size_t> spectra_bytes{0};
     std::recursive_mutex mu;
     std::map<int, void*> tw32, tw64;
-    std::map<std::tuple<int, int, int, int, int>, SpecEntry> spectra;  // (M, kind, m, dtype, family)
+    // (M, kind, m, dtype, family, aspect)
+    std::map<std::tuple<int, int, int, int, int, double>, SpecEntry> spectra;
     std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> shape
     hipStream_t stream = nullptr;                                 // plan-time work
     std::vector<void*> allocs;
@@ -264,10 +265,10 @@ SegTable<Job> single_seg(const Job* jobs, int n, int slot_base, const void* aux,
 // hp = ceil(m/2), the others being mirror images (for odd m the middle
 // phase of each axis is its own mirror).  Layout [phase][X][M/2+1][M].
 td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int family,
-                  const SpecEntry** out)
+                  double aspect, const SpecEntry** out)
 {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    auto key = std::make_tuple(M, kind, m, (int)dt, family);
+    auto key = std::make_tuple(M, kind, m, (int)dt, family, aspect);
     auto it = ctx->spectra.find(key);
     if (it != ctx->spectra.end()) {
         *out = &it->second;
@@ -340,6 +341,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int fami
         tj.kx = p % hp;
         tj.ky = p / hp;
         tj.family = family;
+        tj.aspect = aspect;
         tj.out = (double*)table;
         hipError_t he = launch_table(tj, ctx->stream);
         if (he == hipSuccess)
@@ -429,6 +431,9 @@ extern "C" td_status td_hierarchy_check(const td_hierarchy* h)
 {
     int L = 0;
     TD_TRY(patch_levels(h, &L));
+    if (!std::isfinite(h->aspect) || h->aspect < 0 ||
+        (h->aspect != 0 && (h->aspect < 1.0 / 64 || h->aspect > 64)))
+        return fail(TD_EINVAL, "aspect must be 0 (square cells) or in [1/64, 64]");
     if (h->ratio < 2 || h->ratio > 4)
         return fail(TD_EUNSUPPORTED, "refinement ratio must be 2, 3 or 4");
     if (!(h->h0 > 0) || !std::isfinite(h->h0) || !std::isfinite(h->x0) || !std::isfinite(h->y0))
@@ -487,15 +492,16 @@ extern "C" td_status td_hierarchy_snap(td_hierarchy* h, td_patch* patches, const
         if (patches[l].level != l) return fail(TD_EINVAL, "snap takes one patch per level, patch l on level l");
     patches[0].ox = patches[0].oy = 0;
     double hh = h->h0;
+    const double asp = h->aspect > 0 ? h->aspect : 1.0;
     for (int l = 1; l < h->npatches; ++l) {
         const int r = h->ratio, n = patches[l].n, pn = patches[l - 1].n;
         if (n % r) return fail(TD_EALIGN, "child size must be a multiple of the ratio");
         const int span = n / r;
         if (span > pn) return fail(TD_ENEST, "child wider than its parent");
-        const double px0 = h->x0 + patches[l - 1].ox * hh, py0 = h->y0 + patches[l - 1].oy * hh;
+        const double px0 = h->x0 + patches[l - 1].ox * hh, py0 = h->y0 + patches[l - 1].oy * hh * asp;
         const double ext = n * hh / r;
         long kx = (long)std::floor((cx[l - 1] - ext / 2 - px0) / hh + 0.5);
-        long ky = (long)std::floor((cy[l - 1] - ext / 2 - py0) / hh + 0.5);
+        long ky = (long)std::floor((cy[l - 1] - ext * asp / 2 - py0) / (hh * asp) + 0.5);
         kx = std::min<long>(std::max<long>(kx, 0), pn - span);
         ky = std::min<long>(std::max<long>(ky, 0), pn - span);
         patches[l].ox = r * (patches[l - 1].ox + (int)kx);
@@ -548,6 +554,7 @@ struct td_plan {
     bool dry = false;          // host-only planning: no spectra, no device memory
     td_dtype dt = TD_F32;
     int quantity = TD_FORCE;   // TD_FORCE (Fx, Fy) or TD_POTENTIAL (Phi into fx)
+    double aspect = 1.0;       // cell height / width
     int ratio = 2;
     int nlevels = 0;
     int npatches = 0;
@@ -626,7 +633,7 @@ const void* phase_kernels(const SpecEntry* e, int m, int kx, int ky, size_t per_
 // whose address is never dereferenced.
 td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out)
 {
-    if (!P->dry) return spectra(P->ctx, M, kind, m, P->dt, P->quantity, out);
+    if (!P->dry) return spectra(P->ctx, M, kind, m, P->dt, P->quantity, P->aspect, out);
     static SpecEntry fake;
     const int hp = kind == 1 ? 1 : (m + 1) / 2;
     fake.ptr = (void*)(uintptr_t)4096;
@@ -636,17 +643,19 @@ td_status plan_spectra(td_plan* P, int M, int kind, int m, const SpecEntry** out
     return TD_OK;
 }
 
-// Multipliers of a row-forward job reading field f of a level with cell side
-// h.  The force tables are dimensionless: sigma enters as read, a given slope
-// as h * slope, an estimated one (already per cell) as it is.  The potential
-// carries one more length and the sign of the Green's function -1/rho, so
-// every multiplier takes a further -h (the tables are in units of the pair's
-// finer cell; Case-3 tables absorb the ratio to a coarser source's h).
+// Multipliers of a row-forward job reading field f of a level with cell
+// width h (height aspect h).  The force tables are dimensionless, in units of
+// the cell width: sigma enters as read, a given slope as h * slope (x and y
+// alike), an estimated one (a difference per cell) as it is along x and
+// divided by the aspect along y.  The potential carries one more length and
+// the sign of the Green's function -1/rho, so every multiplier takes a
+// further -h (the tables are in units of the pair's finer cell; Case-3
+// tables absorb the ratio to a coarser source's h).
 void row_scales(const td_plan* P, double h, int f, RowFwdJob* j)
 {
     const double q = P->quantity == TD_POTENTIAL ? -h : 1.0;
     j->scale = f == 0 ? q : q * h;
-    j->est_scale = q;
+    j->est_scale = f == 2 ? q / P->aspect : q;
 }
 
 // Emit every job of a plan (workspace addresses as byte offsets) and the
@@ -1061,6 +1070,7 @@ td_status plan_geometry(td_plan* P, const td_hierarchy* h, td_dtype dt)
     P->x0 = h->x0;
     P->y0 = h->y0;
     P->h0 = h->h0;
+    P->aspect = h->aspect > 0 ? h->aspect : 1.0;
     P->id = g_plan_ids++;
     double hh = h->h0;
     for (int l = 0; l < L; ++l) {
@@ -2061,10 +2071,13 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
 // public: diagnostics
 // ===========================================================================
 
-extern "C" td_status td_kernel_table(td_context* ctx, int32_t quantity, int32_t M, int32_t kind,
-                                     int32_t m, int32_t kx, int32_t ky, double* out_host)
+extern "C" td_status td_kernel_table(td_context* ctx, int32_t quantity, double aspect, int32_t M,
+                                     int32_t kind, int32_t m, int32_t kx, int32_t ky,
+                                     double* out_host)
 {
     if (!ctx || !out_host) return fail(TD_EINVAL, "NULL argument");
+    if (!std::isfinite(aspect) || aspect < 0 || (aspect != 0 && (aspect < 1.0 / 64 || aspect > 64)))
+        return fail(TD_EINVAL, "aspect must be 0 (square cells) or in [1/64, 64]");
     if (quantity != TD_FORCE && quantity != TD_POTENTIAL)
         return fail(TD_EINVAL, "quantity must be TD_FORCE or TD_POTENTIAL");
     if (M < 16 || M > 4096 || (M & (M - 1))) return fail(TD_EINVAL, "M must be a power of two in 16..4096");
@@ -2084,6 +2097,7 @@ extern "C" td_status td_kernel_table(td_context* ctx, int32_t quantity, int32_t 
     j.kx = kx;
     j.ky = ky;
     j.family = quantity == TD_POTENTIAL ? 1 : 0;
+    j.aspect = aspect > 0 ? aspect : 1.0;
     j.out = (double*)d;
     hipError_t e = launch_table(j, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

@@ -122,6 +122,7 @@ struct RowInvTables {
 struct TableJob {
     int32_t M, kind, m, kx, ky;
     int32_t family;     // 0: force tables; 1: potential (P0, Px, Py, then zeros)
+    double aspect;      // cell height / width (v coordinates in units of the width)
     double* out;
 };
 

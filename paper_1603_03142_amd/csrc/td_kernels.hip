@@ -139,8 +139,11 @@ __global__ void k_table(TableJob J)
             va = -J.m * sy - J.ky - 0.5;
             w = J.m;
         }
+        // rectangular cells: y offsets and heights in units of the width
+        const double a = J.aspect, wa = w * a;
+        va *= a;
         if (J.family == 0) {
-            cell_integrals(ua, ua + w, va, va + w, v);
+            cell_integrals(ua, ua + w, va, va + wa, v);
             if (J.kind == 3) {
                 const double inv = 1.0 / J.m;
                 v[1] *= inv; v[2] *= inv; v[4] *= inv; v[5] *= inv;
@@ -149,7 +152,7 @@ __global__ void k_table(TableJob J)
             // the potential carries one more length than the force: a
             // coarser source's inputs are scaled by its own cell side, m
             // times the table unit, hence 1/m (1/m^2 for the slopes)
-            cell_potential(ua, ua + w, va, va + w, v);
+            cell_potential(ua, ua + w, va, va + wa, v);
             if (J.kind == 3) {
                 const double inv = 1.0 / J.m;
                 v[0] *= inv; v[1] *= inv * inv; v[2] *= inv * inv;

@@ -43,6 +43,7 @@ def test_binding_structs_match_header(tmp_path):
         " offsetof(td_hierarchy, patches), sizeof(td_request), offsetof(td_request, fy),"
         " offsetof(td_request, slopes), TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE, TD_MAX_PATCHES,"
         " TD_MAX_LEVELS);\n"
+        '  printf("%zu\\n", offsetof(td_hierarchy, aspect));\n'
         '  printf("%d %d\\n", TD_FORCE, TD_POTENTIAL);\n  return 0;\n}\n')
     exe = tmp_path / "probe"
     import subprocess
@@ -53,16 +54,17 @@ def test_binding_structs_match_header(tmp_path):
     want = [ctypes.sizeof(B.td_patch), ctypes.sizeof(B.td_hierarchy), B.td_hierarchy.patches.offset,
             ctypes.sizeof(B.td_request), B.td_request.fy.offset, B.td_request.slopes.offset,
             B.TD_SLOPES_GIVEN, B.TD_SLOPES_ESTIMATE, B.TD_MAX_PATCHES, B.TD_MAX_LEVELS,
-            B.TD_FORCE, B.TD_POTENTIAL]
+            B.td_hierarchy.aspect.offset, B.TD_FORCE, B.TD_POTENTIAL]
     assert got == want
 
 
-def _check(levels, ratio=2, h0=2 / 16, patches=None):
+def _check(levels, ratio=2, h0=2 / 16, patches=None, aspect=0.0):
     """levels: one (n, ox, oy) patch per level; patches: (level, n, ox, oy)."""
     from paper_1603_03142_amd import _binding as B
     pats = patches if patches is not None else [(l, *lv) for l, lv in enumerate(levels)]
     arr = (B.td_patch * len(pats))(*[B.td_patch(*p) for p in pats])
-    h = B.td_hierarchy(-1.0, -1.0, h0, ratio, len(pats), ctypes.cast(arr, ctypes.POINTER(B.td_patch)))
+    h = B.td_hierarchy(-1.0, -1.0, h0, ratio, len(pats), ctypes.cast(arr, ctypes.POINTER(B.td_patch)),
+                       aspect)
     return B.lib().td_hierarchy_check(ctypes.byref(h))
 
 
@@ -77,6 +79,11 @@ def test_hierarchy_validation_codes():
     assert _check([(16, 0, 0), (34, 0, 0)]) == B.TD_ENEST           # wider than parent
     assert _check([(16, 2, 0)]) == B.TD_EINVAL                      # level-0 offset
     assert _check([(16, 0, 0)], ratio=5) == B.TD_EUNSUPPORTED
+    # rectangular cells: aspect 0 (square) or in [1/64, 64]
+    assert _check([(16, 0, 0), (8, 4, 4)], aspect=0.5) == B.TD_OK
+    assert _check([(16, 0, 0)], aspect=64.0) == B.TD_OK
+    for bad in (-1.0, 100.0, 1e-3, float("nan"), float("inf")):
+        assert _check([(16, 0, 0)], aspect=bad) == B.TD_EINVAL, bad
     assert _check([(18, 0, 0), (15, 12, 21)], ratio=3) == B.TD_OK
     assert _check([(18, 0, 0), (15, 12, 20)], ratio=3) == B.TD_EALIGN       # off the lattice
     assert _check([(9, 0, 0), (9, 3, 3), (9, 9, 9), (9, 27, 27)], ratio=3) == B.TD_EUNSUPPORTED  # 27x

@@ -66,13 +66,47 @@ def test_kernel_table_vs_oracle(ctx, M, kind, m, kx, ky):
     np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-14 * m * scale)
 
 
+@pytest.mark.parametrize("quantity", ["force", "potential"])
+@pytest.mark.parametrize("M,kind,m,kx,ky,aspect", [(16, 1, 1, 0, 0, 0.5), (32, 2, 2, 1, 0, 2.5),
+                                                   (16, 3, 3, 2, 1, 0.3), (32, 3, 4, 0, 3, 1.7)])
+def test_kernel_table_rectangular_cells(ctx, M, kind, m, kx, ky, aspect, quantity):
+    """Tables of cells of height aspect x width (v in units of the width)."""
+    got = ctx.kernel_table(M, kind, m, kx, ky, quantity=quantity, aspect=aspect)
+    want = np.zeros_like(got)
+    for ny in range(M):
+        for nx in range(M):
+            if nx == M // 2 or ny == M // 2:
+                continue
+            sx = nx if nx < M // 2 else nx - M
+            sy = ny if ny < M // 2 else ny - M
+            if kind == 1:
+                ua, va, w = -sx - 0.5, -sy - 0.5, 1.0
+            elif kind == 2:
+                ua, va, w = -m * sx + kx - m / 2, -m * sy + ky - m / 2, 1.0
+            else:
+                ua, va, w = -m * sx - kx - 0.5, -m * sy - ky - 0.5, float(m)
+            va *= aspect
+            if quantity == "force":
+                c = oracle.cell_integrals(ua, ua + w, va, va + w * aspect)
+                if kind == 3:
+                    c[[1, 2, 4, 5]] /= m
+                want[:, ny, nx] = c
+            else:
+                c = oracle.cell_potential_integrals(ua, ua + w, va, va + w * aspect)
+                if kind == 3:
+                    c = c / np.array([m, m * m, m * m])
+                want[:3, ny, nx] = c
+    scale = np.abs(want).max()
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-14 * m * max(aspect, 1) * scale)
+
+
 # ---------------------------------------------------------------------------
 # whole solves, full field
 # ---------------------------------------------------------------------------
 
-def H(levels, ratio=2, n0=None, x0=-1.0, y0=-1.0):
+def H(levels, ratio=2, n0=None, x0=-1.0, y0=-1.0, aspect=1.0):
     n0 = n0 or levels[0][0]
-    return synth.nested_hierarchy(x0, y0, 2.0 / n0, ratio, levels)
+    return synth.nested_hierarchy(x0, y0, 2.0 / n0, ratio, levels, aspect)
 
 
 HIERS = {
@@ -93,6 +127,9 @@ HIERS = {
     # odd ratio (m = 3, 9)
     "ratio3_2lev": H([(18, 0, 0), (15, 12, 21)], ratio=3),
     "ratio3_3lev": H([(12, 0, 0), (18, 9, 6), (27, 36, 30)], ratio=3),
+    # rectangular cells (height = aspect x width)
+    "aspect_0p5_3lev": H([(20, 0, 0), (16, 10, 8), (12, 26, 22)], aspect=0.5, y0=-0.5),
+    "aspect_2p5_ratio3": H([(12, 0, 0), (18, 9, 6)], ratio=3, aspect=2.5, y0=-2.5),
 }
 
 

@@ -26,9 +26,9 @@ def ctx():
     c.close()
 
 
-def H(levels, ratio=2, n0=None):
+def H(levels, ratio=2, n0=None, aspect=1.0):
     n0 = n0 or levels[0][0]
-    return synth.nested_hierarchy(-1.0, -1.0, 2.0 / n0, ratio, levels)
+    return synth.nested_hierarchy(-1.0, -1.0, 2.0 / n0, ratio, levels, aspect)
 
 
 HIERS = {
@@ -40,6 +40,7 @@ HIERS = {
     "4lev": H([(16, 0, 0), (16, 8, 8), (16, 24, 20), (8, 60, 52)]),
     "ratio3_3lev": H([(12, 0, 0), (18, 9, 6), (27, 36, 30)], ratio=3),
     "ratio4_deep": H([(6, 0, 0), (20, 4, 4), (44, 44, 44)], ratio=4),
+    "aspect_0p6": H([(24, 0, 0), (18, 8, 20), (10, 30, 48)], aspect=0.6),
 }
 
 
