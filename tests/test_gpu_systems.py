@@ -193,6 +193,25 @@ def test_config3_sampled_f32(ctx):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("workload,count,dtype,tol", [
+    ("two-level-256", 256, "f32", 1e-5), ("two-level-256", 128, "f64", 1e-12),
+    ("four-level-512", 48, "f32", 1e-5), ("example1-1024", 32, "f32", 1e-5)])
+def test_bench_configuration_sampled(ctx, workload, count, dtype, tol):
+    """The configurations bench.py times, as it times them: sigma in, the
+    slopes estimated inside the solve; oracle on sampled targets with the
+    oracle's own slope estimate of the same sigma."""
+    import bench
+    hier, fn = bench.workload(workload)
+    sig, _, _ = synth.sample_fields(hier, fn, "none")
+    gx, gy = gpu_solve(ctx, hier, sig, None, None, dtype, slopes="estimate")
+    tg = synth.sample_targets(hier, count, seed=17)
+    ox, oy = oracle.forces(hier, sig, *oracle.slopes(hier, sig), tg)
+    sx, sy = sampled(hier, gx, gy, tg)
+    err = rel_l2(sx, sy, ox, oy)
+    print(f"{workload} {dtype} estimated slopes, sampled rel-L2 {err:.3e}")
+    assert err <= tol
+
+
 def test_fp32_vs_fp64_full_field(ctx):
     hier, fn = synth.config2()
     sig, dx, dy = synth.sample_fields(hier, fn, "central")
