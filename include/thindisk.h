@@ -37,7 +37,8 @@
  *     written as 0.
  *   - Every field is row-major [j][i] (x fastest), n * n elements per patch
  *     of the plan's dtype (float for TD_F32, double for TD_F64).
- *   - Forces have the units of sigma (G = 1): F = -grad Phi, attractive.
+ *   - Forces have the units of sigma (G = 1): F = -grad Phi, attractive;
+ *     the potential has the units of sigma times length.
  *
  * Ownership and errors
  *   - Field pointers are DEVICE pointers owned by the caller; the library
@@ -75,7 +76,8 @@ typedef enum {
 
 typedef enum { TD_F32 = 0, TD_F64 = 1 } td_dtype;
 
-/* One square patch of the hierarchy (a grid Omega^l_k of Section 2.1). */
+/* One patch of n x n cells of the hierarchy (a grid Omega^l_k of Section
+ * 2.1; physically square when the hierarchy's aspect is 1). */
 typedef struct {
     int32_t level; /* refinement level, 0 = base                          */
     int32_t n;     /* cells per side                                      */
@@ -149,10 +151,11 @@ td_status td_context_usage(const td_context* ctx, size_t* bytes_in_use, size_t* 
 
 /* ---------------------------------------------------------------- geometry */
 
-/* Validate a hierarchy (ratio, sizes, alignment, nesting, overlap).  TD_OK
- * if it can be planned.  Levels may differ in resolution by at most 16x
- * (ratio^(levels-1) <= 16), and each level's patches must span at most
- * TD_MAX_N cells (TD_EUNSUPPORTED otherwise). */
+/* Validate a hierarchy (ratio, sizes, alignment, nesting, overlap, aspect).
+ * TD_OK if it can be planned.  Levels may differ in resolution by at most
+ * 16x (ratio^(levels-1) <= 16), and each level's patches must span at most
+ * TD_MAX_N cells (TD_EUNSUPPORTED otherwise); an aspect outside 0 or
+ * [1/64, 64] is TD_EINVAL. */
 td_status td_hierarchy_check(const td_hierarchy* h);
 
 /* For a hierarchy of one patch per level (patches[l] on level l, sizes
@@ -213,7 +216,9 @@ td_status td_batch_create(td_context* ctx, int32_t count, td_plan* const* plans,
                           td_batch** out);
 /* Enqueue the solves (reqs[k].plan must be the k-th plan given at creation).
  * With use_graph != 0, the launches are captured once into a HIP graph and
- * replayed; pointer tables are refreshed by a copy node each replay. */
+ * replayed; before each replay the current field pointers are copied to the
+ * batch's device pointer table on the stream, outside the graph, so a
+ * replay always reads the request's pointers. */
 td_status td_batch_solve(td_batch* batch, const td_request* reqs, int use_graph,
                          void* hip_stream);
 td_status td_batch_footprint(const td_batch* batch, size_t* workspace_bytes);
