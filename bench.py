@@ -418,8 +418,16 @@ def main():
         tp0 = time.perf_counter()
         ox, oy = oracle.forces(hier, sig, dx, dy, tg, nthreads=nthreads)
         cpu_s = time.perf_counter() - tp0
+        model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                             None)
+        except OSError:
+            pass
         cpu = {"value": round(len(tg[0]) / cpu_s, 2), "unit": "cells/s", "cores": nthreads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": model,
+               "full_solve_s_extrapolated": round(cells * cpu_s / len(tg[0]), 1),
                "sample": f"{len(tg[0])} sampled target cells of the workload (25% within 2 "
                          f"cells of a level interface), each summed over every active source "
                          f"cell; {cpu_s:.1f} s"}
