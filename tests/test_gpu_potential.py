@@ -174,3 +174,22 @@ def test_potential_converges_to_the_appendix_pair(ctx):
     print("\npotential E1 vs analytic:", " ".join(f"{e:.4e}" for e in errs),
           " orders", " ".join(f"{o:.3f}" for o in orders))
     assert all(1.9 < o < 2.1 for o in orders)
+
+
+@pytest.mark.parametrize("workload,count,dtype,tol", [
+    ("two-level-256", 128, "f64", 1e-12), ("two-level-256", 128, "f32", 1e-5),
+    ("four-level-512", 32, "f64", 1e-12), ("four-level-512", 32, "f32", 1e-5)])
+def test_potential_full_size_sampled(ctx, workload, count, dtype, tol):
+    """Potential plans at the benched sizes (sigma in, slopes estimated),
+    sampled targets.  The potential weighs far cells more than the force
+    (1/r against 1/r^2), where the tables' corner differences cancel most."""
+    import bench
+    hier, fn = bench.workload(workload)
+    sig, _, _ = synth.sample_fields(hier, fn, "none")
+    phi = gpu_potential(ctx, hier, sig, None, None, dtype, slopes="estimate")
+    tg = synth.sample_targets(hier, count, seed=19)
+    want = oracle.potential(hier, sig, *oracle.slopes(hier, sig), tg)
+    got = np.array([phi[p][j, i] for p, i, j in zip(*tg)])
+    err = math.sqrt(((got - want) ** 2).sum() / (want ** 2).sum())
+    print(f"{workload} {dtype} potential sampled rel-L2 {err:.3e}")
+    assert err <= tol
