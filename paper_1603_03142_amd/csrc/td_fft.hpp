@@ -22,18 +22,30 @@
 // returns with the sequence ordered for its own wavefront(s) only: a caller
 // that then reads another wavefront's sequence must __syncthreads() first.
 //
-// LDS layout: element i of a sequence is stored at lds_pos(i) = i + i/8 and
-// sequences are lds_stride(M) = M + M/8 elements apart.  The extra element
-// per eight spreads the strided Stockham stores (spans 1 and 8) over the
-// LDS banks: at most two lanes of a wavefront share a bank.
+// LDS layout: element i of a sequence is stored at lds_pos(i) = i + i/P,
+// with one padding element per P = 16 (FP32) or 8 (FP64) elements;
+// sequences are lds_stride(M) = M + M/8 elements apart.  The LDS serves an
+// 8-byte access to 16 lanes per cycle (a 16-byte one to 8), so the lanes of
+// a cycle are conflict-free when their elements differ modulo 16 (modulo 8).
+// FP32 with P = 16 makes every read, and the stores of spans 1 and >= 16,
+// conflict-free, but not the stores of spans 2-8: those passes store with
+// P = 8 (and the next pass reads that layout), which needs the M/8 padding
+// of the stride.  (Measured: P = 8 throughout cost FP32 about 3.6
+// bank-conflict cycles per LDS instruction.)  FP64 uses P = 8 throughout.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace td {
 
+template <typename T>
+__host__ __device__ constexpr int lds_pad() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T>
 __host__ __device__ constexpr int lds_stride(int M) { return M + M / 8; }
-__device__ __forceinline__ int lds_pos(int i) { return i + (i >> 3); }
+template <int P>
+__device__ __forceinline__ int lds_pos_p(int i) { return i + i / P; }  // i >= 0
+template <typename T>
+__device__ __forceinline__ int lds_pos(int i) { return lds_pos_p<lds_pad<T>()>(i); }
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cpx {
@@ -143,33 +155,36 @@ __device__ __forceinline__ void seq_sync()
 }
 
 // One Stockham pass of radix R at span NS on sequence x (length M), for the
-// calling thread's `lane` in [0, M/8).
-template <typename T, int M, int R, int NS, bool INV>
+// calling thread's `lane` in [0, M/8); it reads the layout of padding PR and
+// writes that of padding PW.
+template <typename T, int M, int R, int NS, bool INV, int PR, int PW>
 __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
 {
     constexpr int B = 8 / R;          // butterflies per thread
     constexpr int STRIDE = M / R;     // distance between butterfly inputs
     // For M >= 64 every read of a thread sits at a compile-time offset from
-    // lds_pos(lane) (the offsets are multiples of 8), and every write of a
-    // butterfly at offset r NS + (r NS)/8 from lds_pos(base): one address
-    // per thread and butterfly, the rest immediate offsets.
+    // its first position, and every write of a butterfly at offset
+    // r NS + (r NS)/PW from lds_pos(base): one address per thread and
+    // butterfly, the rest immediate offsets.  (The offsets c are multiples of
+    // PR, or of 8 with lane < 8 when M = 64, and base % PW + (r NS) % PW < PW
+    // in every pass, so the padding splits over the sum.)
     constexpr bool LIN = M >= 64;
     cpx<T> v[B][R];
     if constexpr (LIN) {
-        const cpx<T>* rp = x + lds_pos(lane);
+        const cpx<T>* rp = x + lds_pos_p<PR>(lane);
 #pragma unroll
         for (int q = 0; q < B; ++q)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int c = q * (M / 8) + r * STRIDE;
-                v[q][r] = rp[c + c / 8];
+                v[q][r] = rp[c + c / PR];
             }
     } else {
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             const int j = lane + q * (M / 8);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos(j + r * STRIDE)];
+            for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos_p<PR>(j + r * STRIDE)];
         }
     }
     seq_sync<M>();
@@ -189,23 +204,32 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
         dftR<T, R, INV>(v[q]);
         const int base = (j / NS) * NS * R + k;
         if constexpr (LIN) {
-            cpx<T>* wp = x + lds_pos(base);
+            cpx<T>* wp = x + lds_pos_p<PW>(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) wp[r * NS + (r * NS) / 8] = v[q][r];
+            for (int r = 0; r < R; ++r) wp[r * NS + (r * NS) / PW] = v[q][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[lds_pos(base + r * NS)] = v[q][r];
+            for (int r = 0; r < R; ++r) x[lds_pos_p<PW>(base + r * NS)] = v[q][r];
         }
     }
     seq_sync<M>();
 }
 
-template <typename T, int M, int NS, bool INV>
+// Padding of the layout a pass of span NS writes: FP32 stores of spans 2-8
+// that another pass reads use 8, every other store the type's padding.
+template <typename T, int M, int NS>
+__host__ __device__ constexpr int pass_pad()
+{
+    return (sizeof(T) == 4 && NS >= 2 && NS <= 8 && NS * 8 < M) ? 8 : lds_pad<T>();
+}
+
+template <typename T, int M, int NS, bool INV, int PR>
 __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
 {
     if constexpr (NS < M) {
-        stockham_pass<T, M, 8, NS, INV>(x, tw, lane);
-        radix8_passes<T, M, NS * 8, INV>(x, tw, lane);
+        constexpr int PW = pass_pad<T, M, NS>();
+        stockham_pass<T, M, 8, NS, INV, PR, PW>(x, tw, lane);
+        radix8_passes<T, M, NS * 8, INV, PW>(x, tw, lane);
     }
 }
 
@@ -225,16 +249,17 @@ __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ 
     asm volatile("" : "+v"(tid));
     const int f = tid / (M / 8);
     const int lane = tid % (M / 8);
-    cpx<T>* x = buf + (size_t)f * lds_stride(M);
+    cpx<T>* x = buf + (size_t)f * lds_stride<T>(M);
     constexpr int REM = ilog2(M) % 3;
+    constexpr int P = lds_pad<T>();  // the layout in and out
     if constexpr (REM == 1) {
-        stockham_pass<T, M, 2, 1, INV>(x, tw, lane);
-        radix8_passes<T, M, 2, INV>(x, tw, lane);
+        stockham_pass<T, M, 2, 1, INV, P, P>(x, tw, lane);
+        radix8_passes<T, M, 2, INV, P>(x, tw, lane);
     } else if constexpr (REM == 2) {
-        stockham_pass<T, M, 4, 1, INV>(x, tw, lane);
-        radix8_passes<T, M, 4, INV>(x, tw, lane);
+        stockham_pass<T, M, 4, 1, INV, P, P>(x, tw, lane);
+        radix8_passes<T, M, 4, INV, P>(x, tw, lane);
     } else {
-        radix8_passes<T, M, 1, INV>(x, tw, lane);
+        radix8_passes<T, M, 1, INV, P>(x, tw, lane);
     }
 }
 

@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     char* ws;
     const RowFwdJob J = segs.find(blockIdx.x, &slot_base, &aux, &ws);
     const int C = blockDim.x / (M / 8);
-    constexpr int SP = lds_stride(M);
+    constexpr int SP = lds_stride<T>(M);
     cpx<T>* tw = buf + C * SP;
     stage_twiddles<T, M>(tw, tw_g);
     // source cells: window cell (m lc + col_off, m lr + row_off) of level
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
                 b = est ? (T)(J.est_scale * cell_slope(src, n, i, j1, J.f))
                         : (T)(J.scale * (double)src[(size_t)j1 * n + i]);
         }
-        buf[p * SP + lds_pos(lc)] = cpx<T>{a, b};
+        buf[p * SP + lds_pos<T>(lc)] = cpx<T>{a, b};
     }
     __syncthreads();
     fft_lds<T, M, false>(buf, tw);
@@ -267,8 +267,8 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
         const int r = idx % R, kx = idx / R;
         if (r >= J.nrow) continue;
         const int p = r >> 1;
-        const cpx<T> z = buf[p * SP + lds_pos(kx)];
-        const cpx<T> zc = conj(buf[p * SP + lds_pos((M - kx) & (M - 1))]);
+        const cpx<T> z = buf[p * SP + lds_pos<T>(kx)];
+        const cpx<T> zc = conj(buf[p * SP + lds_pos<T>((M - kx) & (M - 1))]);
         cpx<T> X;
         if ((r & 1) == 0) {
             X = cpx<T>{(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
@@ -399,7 +399,7 @@ __device__ __forceinline__ void load_column(cpx<T>* a, const char* ws, const Col
     for (int q = 0; q < 8; ++q) {
         const int sr = lane + q * TPS - I.lr_first;
         const cpx<T> v = ldg<T>(src, min(max(sr, 0), last));
-        a[lds_pos(lane + q * TPS)] = (ok && sr >= 0 && sr <= last) ? v : cpx<T>{0, 0};
+        a[lds_pos<T>(lane + q * TPS)] = (ok && sr >= 0 && sr <= last) ? v : cpx<T>{0, 0};
     }
 }
 
@@ -410,7 +410,7 @@ __device__ __forceinline__ void store_column(const cpx<T>* a, char* ws, const Co
 {
     constexpr int TPS = M / 8;
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + O.out) + (size_t)kx * O.out_ld;
-    for (int sr = lane; sr < O.out_ld; sr += TPS) dst[sr] = a[lds_pos(O.out_lr_first + sr)];
+    for (int sr = lane; sr < O.out_ld; sr += TPS) dst[sr] = a[lds_pos<T>(O.out_lr_first + sr)];
 }
 
 template <typename T, int M>
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TPS = M / 8;
-    constexpr int SP = lds_stride(M);
+    constexpr int SP = lds_stride<T>(M);
     const int S = blockDim.x / TPS;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* tw = A + S * SP;
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             if (ok) {
                 cpx<T> v[8], kv[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = a[lds_pos(lane + q * TPS)];
+                for (int q = 0; q < 8; ++q) v[q] = a[lds_pos<T>(lane + q * TPS)];
                 kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) ax[q] = ax[q] + cmul(kv[q], v[q]);
@@ -472,12 +472,12 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         const int gy = G > 1 ? 1 : 0;
         cpx<T> sx[8], sy[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = ax[q];
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ax[q];
         __syncthreads();
         if (g == 0) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int p = lds_pos(lane + q * TPS);
+                const int p = lds_pos<T>(lane + q * TPS);
                 cpx<T> sum = col0[p];
                 for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
                 sx[q] = sum;
@@ -485,12 +485,12 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = ay[q];
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ay[q];
         __syncthreads();
         if (g == gy) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int p = lds_pos(lane + q * TPS);
+                const int p = lds_pos<T>(lane + q * TPS);
                 cpx<T> sum = col0[p];
                 for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
                 sy[q] = sum;
@@ -499,10 +499,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         __syncthreads();
         if (g == 0) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = sx[q];
+            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sx[q];
         } else if (g == gy) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = sy[q];
+            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sy[q];
         }
         __syncthreads();
         fft_lds<T, M, true>(A, tw);
@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         if (G == 1) {
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = sy[q];
+            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sy[q];
             __syncthreads();
             fft_lds<T, M, true>(A, tw);
             if (col_ok) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         for (int f = 0; f < 3; ++f) {
             if (f >= r0 && f < r0 + G) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos(lane + q * TPS)];
+                for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos<T>(lane + q * TPS)];
             }
         }
         __syncthreads();
@@ -560,7 +560,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             }
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos(lane + q * TPS)] = acc[q];
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = acc[q];
         seq_sync<M>();
         fft_lds<T, M, true>(A, tw);
         if (ok) store_column<T, M>(a, ws, O, kx, lane);
@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TPS = M / 8;
     constexpr int H = M / 2 + 1;
-    constexpr int SP = lds_stride(M);
+    constexpr int SP = lds_stride<T>(M);
     const int S = blockDim.x / TPS;
     const int C = S / G;  // rows of this workgroup
     const int GT = G * TPS;
@@ -673,8 +673,8 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
                 zr = cpx<T>{X.re + Y.im, Y.re - X.im};
             }
             cpx<T>* row = A + (cc * G + gg) * SP;
-            row[lds_pos(kx)] = z;
-            if (kx > 0 && kx < M / 2) row[lds_pos(M - kx)] = zr;
+            row[lds_pos<T>(kx)] = z;
+            if (kx > 0 && kx < M / 2) row[lds_pos<T>(M - kx)] = zr;
         }
         __syncthreads();
         fft_lds<T, M, true>(A, tw);
@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
                 const int gx = J.ox_t + J.x0 + ii;  // >= 0
                 const int Ic = ratio_div(gx, mm, sh >= 0 ? sh : -1);
                 if (gx - Ic * mm != kxp) continue;
-                const cpx<T> v = rowv[lds_pos(Ic - oxs)];
+                const cpx<T> v = rowv[lds_pos<T>(Ic - oxs)];
                 accx[q] += v.re;
                 accy[q] += v.im;
             }
@@ -745,7 +745,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<double>* buf = reinterpret_cast<cpx<double>*>(smem_raw);
     const int C = blockDim.x / (M / 8);
-    constexpr int SP = lds_stride(M);
+    constexpr int SP = lds_stride<double>(M);
     cpx<double>* tw = buf + C * SP;
     stage_twiddles<double, M>(tw, tw_g);
     constexpr int NCOL = M / 2 + 1;
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
         const int c = i / M, ky = i % M;
         cpx<double> v{0, 0};
         if (kx0 + c < NCOL) v = rows[((size_t)X * NCOL + kx0 + c) * M + ky];
-        buf[c * SP + lds_pos(ky)] = v;
+        buf[c * SP + lds_pos<double>(ky)] = v;
     }
     __syncthreads();
     fft_lds<double, M, false>(buf, tw);
@@ -765,7 +765,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
     for (int i = threadIdx.x; i < C * M; i += blockDim.x) {
         const int c = i / M, ky = i % M;
         if (kx0 + c >= NCOL) continue;
-        const cpx<double> v = buf[c * SP + lds_pos(ky)];
+        const cpx<double> v = buf[c * SP + lds_pos<double>(ky)];
         if (!(quarter & 1)) {
             out[((size_t)X * NCOL + kx0 + c) * M + ky] = cpx<TO>{(TO)(v.re * sc), (TO)(v.im * sc)};
         } else if (ky <= M / 2) {
@@ -859,7 +859,7 @@ hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void
     const int threads = C * (M / 8);
     const int per_x = (M / 2 + 1 + C - 1) / C;
     const int blocks = 6 * per_x;
-    const size_t smem = ((size_t)C * lds_stride(M) + M) * sizeof(cpx<double>);
+    const size_t smem = ((size_t)C * lds_stride<double>(M) + M) * sizeof(cpx<double>);
     const cpx<double>* r = reinterpret_cast<const cpx<double>*>(rows);
     void* o = out;
     const cpx<double>* t = reinterpret_cast<const cpx<double>*>(tw64);
