@@ -42,9 +42,9 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # slopes mode, pass) and tied to the SHA-256 of the kernel source they were taken on: a
 # changed kernel reports null until it is profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "estimate", "col"): (29400249, "4d58d2b3f253b208"),
-    ("two-level-256", "f32", "estimate", "row_inv"): (7622007, "4d58d2b3f253b208"),
-    ("two-level-256", "f32", "estimate", "row_fwd"): (9350743, "4d58d2b3f253b208"),
+    ("two-level-256", "f32", "estimate", "col"): (29377294, "a5e28c020db2b791"),
+    ("two-level-256", "f32", "estimate", "row_inv"): (7616895, "a5e28c020db2b791"),
+    ("two-level-256", "f32", "estimate", "row_fwd"): (9354259, "a5e28c020db2b791"),
 }
 
 
