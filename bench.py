@@ -15,7 +15,8 @@ resident (plan built beforehand).  Prints one JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
                   [--workload two-level-256|single-64|four-level-512|example3-512|
                               example1-1024|batch-64|serve]
-                  [--mode eager|graph] [--slopes estimate|given] [--no-cpu] [--tune DB]
+                  [--mode eager|graph] [--slopes estimate|given]
+                  [--quantity force|potential] [--no-cpu] [--tune DB]
 
 Other workloads: batch-64 = 64 independent disks (base N in {64..512}, 1-3
 nested levels, random aligned refinement, generalized Maclaurin sigma) solved
@@ -255,6 +256,8 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="two-level-256")
     ap.add_argument("--mode", default="eager", choices=["eager", "graph"])
+    ap.add_argument("--quantity", default="force", choices=["force", "potential"],
+                    help="force (the metric) or the potential (a TD_POTENTIAL plan)")
     ap.add_argument("--slopes", default="estimate", choices=["estimate", "given"],
                     help="estimate: sigma in, slopes from it inside the solve; given: "
                          "central differences of the analytic sigma passed in")
@@ -306,9 +309,9 @@ def main():
         ctx.autotune(args.dtype, max(p.n for p in hier.patches) * 2, args.tune)
         tune_s = round(time.perf_counter() - t0, 2)
     t0 = time.perf_counter()
-    plan = ctx.plan(hier, args.dtype)
+    plan = ctx.plan(hier, args.dtype, quantity=args.quantity)
     plan_s = time.perf_counter() - t0
-    FX, FY = plan.outputs()
+    FX, FY = plan.outputs()  # FY is None for a potential plan (Phi in FX)
     cells = plan.cells
     stream = torch.cuda.current_stream()
 
@@ -369,7 +372,8 @@ def main():
         achieved = bytes_per_launch / per_launch_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, args.dtype, args.slopes, dom),
+                "traffic": (measured_traffic(args.workload, args.dtype, args.slopes, dom)
+                            if args.quantity == "force" else None),
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
                 "alg_bytes_per_launch": int(bytes_per_launch),
                 "passes_us_per_solve_warmup": {p: round(1000.0 * warm[p][0] / args.warmup, 2)
@@ -381,7 +385,7 @@ def main():
     if not args.no_fp64_leg and not (args.dtype == "f64" and args.mode == "eager"):
         S64, DX64, DY64, _ = dev_fields(torch, torch.float64, (sig, dx, dy), args.slopes)
         ctx64 = td.Context(0)
-        plan64 = ctx64.plan(hier, "f64")
+        plan64 = ctx64.plan(hier, "f64", quantity=args.quantity)
         FX64, FY64 = plan64.outputs()
         k64 = max(3, args.steps // 4)
         for _ in range(3):
@@ -409,14 +413,17 @@ def main():
         nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         # a probe of 64 targets (a smaller one overestimates the per-target
         # time: the thread pool starts up inside it)
+        pot = args.quantity == "potential"
+        direct = oracle.potential if pot else oracle.forces
         probe = synth.sample_targets(hier, 64, seed=1)
         tp0 = time.perf_counter()
-        oracle.forces(hier, sig, dx, dy, probe, nthreads=nthreads)
+        direct(hier, sig, dx, dy, probe, nthreads=nthreads)
         per_target = (time.perf_counter() - tp0) / len(probe[0])
         count = max(8, min(4096, int(args.cpu_seconds / max(per_target, 1e-9))))
         tg = synth.sample_targets(hier, count, seed=2)
         tp0 = time.perf_counter()
-        ox, oy = oracle.forces(hier, sig, dx, dy, tg, nthreads=nthreads)
+        ref = direct(hier, sig, dx, dy, tg, nthreads=nthreads)
+        ox, oy = (ref, np.zeros_like(ref)) if pot else ref
         cpu_s = time.perf_counter() - tp0
         model = None
         try:
@@ -432,9 +439,12 @@ def main():
                          f"cells of a level interface), each summed over every active source "
                          f"cell; {cpu_s:.1f} s"}
         fxc = [f.double().cpu().numpy() for f in FX]
-        fyc = [f.double().cpu().numpy() for f in FY]
         gx = np.array([fxc[p][j, i] for p, i, j in zip(*tg)])
-        gy = np.array([fyc[p][j, i] for p, i, j in zip(*tg)])
+        if pot:
+            gy = np.zeros_like(gx)
+        else:
+            fyc = [f.double().cpu().numpy() for f in FY]
+            gy = np.array([fyc[p][j, i] for p, i, j in zip(*tg)])
         acc = math.sqrt((((gx - ox) ** 2).sum() + ((gy - oy) ** 2).sum()) /
                         ((ox ** 2).sum() + (oy ** 2).sum()))
 
@@ -454,6 +464,7 @@ def main():
         "config": {"workload": args.workload, "levels": hier.nlevels,
                    "patches": [[p.level, p.n] for p in hier.patches], "ratio": hier.ratio,
                    "cells_per_solve": cells, "mode": args.mode, "slopes": args.slopes,
+                   "quantity": args.quantity,
                    "plan_build_s": round(plan_s, 3), "autotune_s": tune_s},
         "latency": latency,
         "roofline": roof,
