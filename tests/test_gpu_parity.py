@@ -127,6 +127,8 @@ HIERS = {
     # odd ratio (m = 3, 9)
     "ratio3_2lev": H([(18, 0, 0), (15, 12, 21)], ratio=3),
     "ratio3_3lev": H([(12, 0, 0), (18, 9, 6), (27, 36, 30)], ratio=3),
+    # five levels (m up to 16 through ratio 2: 256 Case-2 phases of one row)
+    "5lev": H([(16, 0, 0), (16, 8, 8), (16, 24, 24), (16, 56, 56), (16, 120, 120)]),
     # rectangular cells (height = aspect x width)
     "aspect_0p5_3lev": H([(20, 0, 0), (16, 10, 8), (12, 26, 22)], aspect=0.5, y0=-0.5),
     "aspect_2p5_ratio3": H([(12, 0, 0), (18, 9, 6)], ratio=3, aspect=2.5, y0=-2.5),
