@@ -347,7 +347,7 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int fami
         if (he == hipSuccess)
             he = launch_row_fwd<double>(M, C, (int)jobs.size(),
                                         single_seg<RowFwdJob>(djobs, (int)jobs.size(), 0, dlp, (char*)rows),
-                                        (const void* const*)dptr, FieldPtrs{}, tw64, ctx->stream);
+                                        (const void* const*)dptr, FieldPtrs{}, tw64, false, ctx->stream);
         const int Cs = std::max(1, std::min(shape_C(default_shape(P_ROWINV, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
         void* dst = (char*)e.ptr + (size_t)p * per_phase * elem_size(dt);
         if (he == hipSuccess)
@@ -947,10 +947,20 @@ td_status validate_jobs(td_plan* P)
                 lds_bytes(M, C, es, Gs) > TD_MAX_DYN_LDS)
                 return bad("launch shape");
         }
-        // pass 1: rows written per row-pass plane
+        // pass 1: rows written per row-pass plane, and the lattice row of
+        // each plane's stored row 0
         std::map<int64_t, std::vector<char>> rows_written;
+        std::map<int64_t, int> plane_lr;
         for (auto& j : g.rowfwd) {
             if (j.lvl < 0 || j.lvl >= P->nlevels || j.f < 0 || j.f > 2) return bad("row source");
+            // lattice columns and rows >= M/2 map past the source level's
+            // window (so hold zeros): the row transforms gather only columns
+            // < M/2 and the column transforms read only rows < M/2
+            if ((int64_t)j.m * (M / 2) + j.col_off < P->lv[j.lvl].nx ||
+                (int64_t)j.m * (M / 2) + j.row_off < P->lv[j.lvl].ny)
+                return bad("row source reaches the upper half of the lattice");
+            if (plane_lr.emplace(j.out, j.lr_first).first->second != j.lr_first)
+                return bad("row plane origin");
             // slope fields are scaled by their level's cell side, which the
             // row kernel's in-place slope estimate (per-cell differences)
             // takes for granted
@@ -972,6 +982,10 @@ td_status validate_jobs(td_plan* P)
         for (size_t i = 0; i < g.colins.size(); ++i) {
             const ColIn& I = g.colins[i];
             if (I.ld < 1 || I.lr_first < 0 || I.lr_first + I.ld > M) return bad("col input rows");
+            {
+                auto pl = plane_lr.find(I.in);
+                if (pl == plane_lr.end() || pl->second != I.lr_first) return bad("col input origin");
+            }
             if (I.f < 0 || I.f > 2 || (I.flip & ~8) < 0 || (I.flip & ~8) > 4 ||
                 ((I.flip >> 3) & 1) != (P->quantity == TD_POTENTIAL ? 1 : 0))
                 return bad("col input kernel");
@@ -983,7 +997,8 @@ td_status validate_jobs(td_plan* P)
             in_ok[i] = 1;
         }
         for (auto& O : g.colouts) {
-            if (O.out_ld < 1 || O.out_lr_first < 0 || O.out_lr_first + O.out_ld > M) return bad("col output rows");
+            if (O.out_ld < 1 || O.out_lr_first < 0 || O.out_lr_first + O.out_ld > M / 2)
+                return bad("col output rows");
             if (!in_ws(O.out, (int64_t)H * O.out_ld)) return bad("col output plane");
             if (O.comp < 0 || O.comp > 1 || (O.flip & ~8) < 0 || (O.flip & ~8) > 3 ||
                 (O.kern && ((O.flip >> 3) & 1) != (P->quantity == TD_POTENTIAL ? 1 : 0)))
@@ -1036,7 +1051,7 @@ td_status validate_jobs(td_plan* P)
                     }
                     for (int ii : {j.x0, j.x0 + j.nx - 1}) {
                         const int lc = floor_div(j.ox_t + ii, c.m) - c.ox_s;
-                        if (lc < 0 || lc >= M) return bad("rinv source col");
+                        if (lc < 0 || lc >= M / 2) return bad("rinv source col");
                     }
                     const int64_t last = c.base + ((int64_t)(c.m * c.m - 1) * c.phase_stride +
                                                    c.comp_stride + (int64_t)H * c.ld) * (int64_t)es;
@@ -1273,8 +1288,8 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                         push_seg(t, n, gs.first->d_rowfwd, (int)gs.first->rowfwd.size(), gs.second->slot_base,
                                  (const void*)gs.second->plan->d_lp, gs.second->ws);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, st)
-                                : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, st);
+                        e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, true, st)
+                                : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, true, st);
                 } else if (pass == P_COL) {
                     std::vector<SegTable<ColJob>> t;
                     std::vector<int> n;
@@ -2178,13 +2193,14 @@ extern "C" td_status td_plan_traffic(const td_plan* P, int32_t slopes, double* b
             const bool reads = j.f == 0 || slopes == TD_SLOPES_GIVEN;
             bytes[P_ROWFWD] += (reads ? (double)rows * cols * rs : 0.0) + (double)H * j.nrow * cs;
         }
-        // col: every input plane, every stored kernel plane it multiplies
-        // (real quarter planes for same-level kernels) and every output
-        // plane, once per solve
+        // col: every input plane (its rows below lattice row M/2), every
+        // stored kernel plane it multiplies (real quarter planes for
+        // same-level kernels) and every output plane, once per solve
         std::set<int64_t> ins;
         std::set<std::pair<const void*, int>> kerns;
         for (auto& I : g.colins) {
-            if (ins.insert(I.in).second) bytes[P_COL] += (double)H * I.ld * cs;
+            if (ins.insert(I.in).second)
+                bytes[P_COL] += (double)H * std::max(0, std::min(I.ld, M / 2 - I.lr_first)) * cs;
             for (int comp = 0; comp < 2; ++comp)
                 if (kerns.insert({I.kern, kKernOfHost[comp][I.f]}).second)
                     bytes[P_COL] += (I.flip & 4) ? (double)H * H * rs : (double)H * M * cs;

@@ -1,12 +1,14 @@
 // Batched LDS-resident Stockham FFTs for gfx950.
 //
 // A workgroup transforms C independent sequences of length M (a power of two,
-// 16 <= M <= 4096) that sit contiguously in LDS (sequence f at buf + f*M).
-// The workgroup has exactly C*(M/8) threads; in every pass each thread holds
+// 16 <= M <= 4096) that sit in LDS lds_stride(M) elements apart.  The
+// workgroup has exactly C*(M/8) threads; in every pass each thread holds
 // eight complex values in registers: one radix-8 butterfly, two radix-4
-// butterflies or four radix-2 butterflies.  Every pass reads all operands,
+// butterflies or four radix-2 butterflies.  Every pass reads its operands,
 // synchronises, and writes them back permuted (Stockham autosort), so a
 // single LDS buffer per sequence suffices and the result is in natural order.
+// Zero-padded inputs (upper half zero) skip that half in the first pass, and
+// transforms of which only the lower half is wanted skip it in the last.
 //
 // Forward: X[k] = sum_n x[n] exp(-2 pi i k n / M); inverse uses +i and is
 // unnormalised.  Twiddles come from a table computed on the host in long
@@ -78,32 +80,50 @@ __device__ __forceinline__ cpx<T> rot_i(cpx<T> a)
     return INV ? cpx<T>{-a.im, a.re} : cpx<T>{a.im, -a.re};
 }
 
-template <typename T, bool INV>
+// Butterflies.  ZIN: the upper half of the inputs, v[R/2 .. R-1], is zero
+// (not read); ZOUT: only the lower half of the outputs, v[0 .. R/2-1], is
+// wanted (the rest is left undefined).
+template <typename T, bool INV, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void dft2(cpx<T>* v)
 {
-    cpx<T> a = v[0], b = v[1];
-    v[0] = a + b;
-    v[1] = a - b;
+    if constexpr (ZIN) {
+        v[1] = v[0];
+    } else {
+        cpx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        if constexpr (!ZOUT) v[1] = a - b;
+    }
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void dft4(cpx<T>* v)
 {
-    cpx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
-    cpx<T> s13 = v[1] + v[3], d13 = rot_i<T, INV>(v[1] - v[3]);
+    cpx<T> s02, d02, s13, d13;
+    if constexpr (ZIN) {
+        s02 = d02 = v[0];
+        s13 = v[1];
+        d13 = rot_i<T, INV>(v[1]);
+    } else {
+        s02 = v[0] + v[2];
+        d02 = v[0] - v[2];
+        s13 = v[1] + v[3];
+        d13 = rot_i<T, INV>(v[1] - v[3]);
+    }
     v[0] = s02 + s13;
-    v[2] = s02 - s13;
     v[1] = d02 + d13;
-    v[3] = d02 - d13;
+    if constexpr (!ZOUT) {
+        v[2] = s02 - s13;
+        v[3] = d02 - d13;
+    }
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void dft8(cpx<T>* v)
 {
     cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
     cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
-    dft4<T, INV>(e);
-    dft4<T, INV>(o);
+    dft4<T, INV, ZIN>(e);
+    dft4<T, INV, ZIN>(o);
     const T h = (T)0.70710678118654752440084436210484903928;
     // o[k] *= w8^k,  w8 = exp(-+ i pi/4)
     o[1] = INV ? cpx<T>{h * (o[1].re - o[1].im), h * (o[1].re + o[1].im)}
@@ -114,16 +134,16 @@ __device__ __forceinline__ void dft8(cpx<T>* v)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         v[k] = e[k] + o[k];
-        v[k + 4] = e[k] - o[k];
+        if constexpr (!ZOUT) v[k + 4] = e[k] - o[k];
     }
 }
 
-template <typename T, int R, bool INV>
+template <typename T, int R, bool INV, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void dftR(cpx<T>* v)
 {
-    if constexpr (R == 2) dft2<T, INV>(v);
-    else if constexpr (R == 4) dft4<T, INV>(v);
-    else dft8<T, INV>(v);
+    if constexpr (R == 2) dft2<T, INV, ZIN, ZOUT>(v);
+    else if constexpr (R == 4) dft4<T, INV, ZIN, ZOUT>(v);
+    else dft8<T, INV, ZIN, ZOUT>(v);
 }
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
@@ -156,12 +176,19 @@ __device__ __forceinline__ void seq_sync()
 
 // One Stockham pass of radix R at span NS on sequence x (length M), for the
 // calling thread's `lane` in [0, M/8); it reads the layout of padding PR and
-// writes that of padding PW.
-template <typename T, int M, int R, int NS, bool INV, int PR, int PW>
+// writes that of padding PW.  In the first pass (NS == 1) a butterfly's
+// inputs r >= R/2 are the elements >= M/2, so ZIN (those elements are zero)
+// skips them; in the last (NS R == M) its outputs r >= R/2 land at >= M/2,
+// so ZOUT (only elements < M/2 are wanted) does not form or store them.
+template <typename T, int M, int R, int NS, bool INV, int PR, int PW, bool ZIN = false,
+          bool ZOUT = false>
 __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
 {
+    static_assert(!ZIN || NS == 1, "ZIN applies to the first pass");
+    static_assert(!ZOUT || NS * R == M, "ZOUT applies to the last pass");
     constexpr int B = 8 / R;          // butterflies per thread
     constexpr int STRIDE = M / R;     // distance between butterfly inputs
+    constexpr int RIN = ZIN ? R / 2 : R, ROUT = ZOUT ? R / 2 : R;
     // For M >= 64 every read of a thread sits at a compile-time offset from
     // its first position, and every write of a butterfly at offset
     // r NS + (r NS)/PW from lds_pos(base): one address per thread and
@@ -177,14 +204,15 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int c = q * (M / 8) + r * STRIDE;
-                v[q][r] = rp[c + c / PR];
+                v[q][r] = r < RIN ? rp[c + c / PR] : cpx<T>{0, 0};
             }
     } else {
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             const int j = lane + q * (M / 8);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = x[lds_pos_p<PR>(j + r * STRIDE)];
+            for (int r = 0; r < R; ++r)
+                v[q][r] = r < RIN ? x[lds_pos_p<PR>(j + r * STRIDE)] : cpx<T>{0, 0};
         }
     }
     seq_sync<M>();
@@ -201,15 +229,15 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
                 v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
             }
         }
-        dftR<T, R, INV>(v[q]);
+        dftR<T, R, INV, ZIN, ZOUT>(v[q]);
         const int base = (j / NS) * NS * R + k;
         if constexpr (LIN) {
             cpx<T>* wp = x + lds_pos_p<PW>(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) wp[r * NS + (r * NS) / PW] = v[q][r];
+            for (int r = 0; r < ROUT; ++r) wp[r * NS + (r * NS) / PW] = v[q][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[lds_pos_p<PW>(base + r * NS)] = v[q][r];
+            for (int r = 0; r < ROUT; ++r) x[lds_pos_p<PW>(base + r * NS)] = v[q][r];
         }
     }
     seq_sync<M>();
@@ -223,25 +251,27 @@ __host__ __device__ constexpr int pass_pad()
     return (sizeof(T) == 4 && NS >= 2 && NS <= 8 && NS * 8 < M) ? 8 : lds_pad<T>();
 }
 
-template <typename T, int M, int NS, bool INV, int PR>
+template <typename T, int M, int NS, bool INV, int PR, bool ZIN, bool ZOUT>
 __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
 {
     if constexpr (NS < M) {
         constexpr int PW = pass_pad<T, M, NS>();
-        stockham_pass<T, M, 8, NS, INV, PR, PW>(x, tw, lane);
-        radix8_passes<T, M, NS * 8, INV, PW>(x, tw, lane);
+        stockham_pass<T, M, 8, NS, INV, PR, PW, ZIN && NS == 1, ZOUT && NS * 8 == M>(x, tw, lane);
+        radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT>(x, tw, lane);
     }
 }
 
 // Transform sequence `f = threadIdx.x / (M/8)` of the C sequences at buf
-// (padded layout).
+// (padded layout).  ZIN: elements M/2 .. M-1 of the input are zero and are
+// not read (a zero-padded sequence); ZOUT: only elements 0 .. M/2-1 of the
+// result are wanted, the others are left stale.
 // Must be called by every thread of the workgroup (it synchronises).
 //
 // The thread index goes through an empty asm barrier: in a kernel that
 // calls fft_lds inside a loop, every LDS address and twiddle of every pass
 // is loop-invariant, and hoisting them all out of the loop would hold them
 // in registers for its whole length (tens of VGPRs, halving occupancy).
-template <typename T, int M, bool INV>
+template <typename T, int M, bool INV, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ tw)
 {
     static_assert(M >= 16 && (M & (M - 1)) == 0, "M must be a power of two >= 16");
@@ -253,13 +283,13 @@ __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ 
     constexpr int REM = ilog2(M) % 3;
     constexpr int P = lds_pad<T>();  // the layout in and out
     if constexpr (REM == 1) {
-        stockham_pass<T, M, 2, 1, INV, P, P>(x, tw, lane);
-        radix8_passes<T, M, 2, INV, P>(x, tw, lane);
+        stockham_pass<T, M, 2, 1, INV, P, P, ZIN>(x, tw, lane);
+        radix8_passes<T, M, 2, INV, P, false, ZOUT>(x, tw, lane);
     } else if constexpr (REM == 2) {
-        stockham_pass<T, M, 4, 1, INV, P, P>(x, tw, lane);
-        radix8_passes<T, M, 4, INV, P>(x, tw, lane);
+        stockham_pass<T, M, 4, 1, INV, P, P, ZIN>(x, tw, lane);
+        radix8_passes<T, M, 4, INV, P, false, ZOUT>(x, tw, lane);
     } else {
-        radix8_passes<T, M, 1, INV, P>(x, tw, lane);
+        radix8_passes<T, M, 1, INV, P, ZIN, ZOUT>(x, tw, lane);
     }
 }
 

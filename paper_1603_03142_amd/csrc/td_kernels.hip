@@ -211,7 +211,11 @@ __device__ __forceinline__ double cell_slope(const T* __restrict__ s, int n, int
     return 0.5 * ((double)p[st] - (double)p[-st]);
 }
 
-template <typename T, int M>
+// ZP: zero-padded rows (the solve's inputs): lattice columns >= M/2 lie
+// past the level's window (M >= 2 nx and the nesting, checked on the host),
+// so only the lower half of each sequence is gathered and the first FFT
+// pass skips the rest.  The kernel-table rows are full length (!ZP).
+template <typename T, int M, bool ZP>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> segs,
                                                   const void* const* __restrict__ ptrs,
                                                   const FieldPtrs fp,
@@ -233,8 +237,9 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     gpatches L = (gpatches)aux + J.lvl;
     const int np = L->np;
     const int rend = J.row0 + J.nrow;
-    for (int idx = threadIdx.x; idx < C * M; idx += blockDim.x) {
-        const int p = idx / M, lc = idx % M;
+    constexpr int NG = ZP ? M / 2 : M;  // columns gathered
+    for (int idx = threadIdx.x; idx < C * NG; idx += blockDim.x) {
+        const int p = idx / NG, lc = idx % NG;
         const int s0 = J.row0 + 2 * p;
         const int scol = J.m * lc + J.col_off;
         const int sr0 = J.m * (J.lr_first + s0) + J.row_off, sr1 = sr0 + J.m;
@@ -259,7 +264,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
         buf[p * SP + lds_pos<T>(lc)] = cpx<T>{a, b};
     }
     __syncthreads();
-    fft_lds<T, M, false>(buf, tw);
+    fft_lds<T, M, false, ZP>(buf, tw);
     __syncthreads();  // the transposed write reads every sequence
     cpx<T>* out = reinterpret_cast<cpx<T>*>(ws + J.out);
     const int R = 2 * C;
@@ -385,7 +390,10 @@ struct ColTables {
     const ColOut* outs;
 };
 
-// Stored rows of input plane I, column kx, into sequence a (zero elsewhere).
+// Stored rows of input plane I, column kx, into the lower half of sequence
+// a (zero elsewhere in that half).  Lattice rows >= M/2 hold no source cell
+// (M >= 2 ny and the nesting, checked on the host): that half is zero, is
+// not written here and is skipped by the forward transform (ZIN).
 // (Unconditional loads from a clamped row -- row 0 of the workspace for a
 // slot without an input -- then a select.)
 template <typename T, int M>
@@ -396,14 +404,16 @@ __device__ __forceinline__ void load_column(cpx<T>* a, const char* ws, const Col
     gptr<cpx<T>> src = (gptr<cpx<T>>)(ws + (ok ? I.in + (int64_t)kx * I.ld * (int64_t)sizeof(cpx<T>) : 0));
     const int last = ok ? I.ld - 1 : 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
         const int sr = lane + q * TPS - I.lr_first;
         const cpx<T> v = ldg<T>(src, min(max(sr, 0), last));
         a[lds_pos<T>(lane + q * TPS)] = (ok && sr >= 0 && sr <= last) ? v : cpx<T>{0, 0};
     }
 }
 
-// Rows [out_lr_first, out_lr_first + out_ld) of the transformed sequence a.
+// Rows [out_lr_first, out_lr_first + out_ld) of the transformed sequence a
+// (all below M/2, checked on the host: the inverse transforms form only
+// that half, ZOUT).
 template <typename T, int M>
 __device__ __forceinline__ void store_column(const cpx<T>* a, char* ws, const ColOut& O, int kx,
                                              int lane)
@@ -453,7 +463,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             if (ok) I = tabs.ins[J.in0 + i];
             load_column<T, M>(a, ws, I, kx, ok, lane);
             seq_sync<M>();
-            fft_lds<T, M, false>(A, tw);
+            fft_lds<T, M, false, true>(A, tw);
             if (ok) {
                 cpx<T> v[8], kv[8];
 #pragma unroll
@@ -505,7 +515,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sy[q];
         }
         __syncthreads();
-        fft_lds<T, M, true>(A, tw);
+        fft_lds<T, M, true, false, true>(A, tw);
         if (col_ok && g == 0) store_column<T, M>(a, ws, tabs.outs[J.out0], kx, lane);
         if (col_ok && G > 1 && g == 1) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
         if (G == 1) {
@@ -513,7 +523,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
 #pragma unroll
             for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sy[q];
             __syncthreads();
-            fft_lds<T, M, true>(A, tw);
+            fft_lds<T, M, true, false, true>(A, tw);
             if (col_ok) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
         }
         return;
@@ -529,7 +539,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         if (ok) I = tabs.ins[J.in0 + i];
         load_column<T, M>(a, ws, I, kx, ok, lane);
         seq_sync<M>();
-        fft_lds<T, M, false>(A, tw);
+        fft_lds<T, M, false, true>(A, tw);
         __syncthreads();  // every slot reads the three transformed inputs
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -562,7 +572,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
 #pragma unroll
         for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = acc[q];
         seq_sync<M>();
-        fft_lds<T, M, true>(A, tw);
+        fft_lds<T, M, true, false, true>(A, tw);
         if (ok) store_column<T, M>(a, ws, O, kx, lane);
         seq_sync<M>();
     }
@@ -677,7 +687,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
             if (kx > 0 && kx < M / 2) row[lds_pos<T>(M - kx)] = zr;
         }
         __syncthreads();
-        fft_lds<T, M, true>(A, tw);
+        fft_lds<T, M, true, false, true>(A, tw);
         __syncthreads();  // outputs gather from every slot of their row
         for (int gg = 0; gg < G; ++gg) {
             if (it_c[gg] < 0) break;
@@ -794,7 +804,7 @@ static hipError_t launch_common(KF kf, int blocks, int threads, size_t smem, hip
 template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
                           const void* const* ptrs, const FieldPtrs& fp, const void* tw,
-                          hipStream_t st)
+                          bool padded, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * (M / 8);
@@ -805,7 +815,12 @@ hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& s
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
     void* args[] = {&s, &p, &f, &t};
     switch (M) {
-#define X(MM) case MM: return launch_common(k_row_fwd<T, MM>, blocks, threads, smem, st, args);
+#define X(MM)                                                                            \
+    case MM:                                                                             \
+        if (padded) return launch_common(k_row_fwd<T, MM, true>, blocks, threads, smem, st, args); \
+        if constexpr (sizeof(T) == 8)                                                    \
+            return launch_common(k_row_fwd<T, MM, false>, blocks, threads, smem, st, args); \
+        return hipErrorInvalidValue;
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -883,10 +898,10 @@ hipError_t launch_table(const TableJob& job, hipStream_t st)
 }
 
 template hipError_t launch_row_fwd<float>(int, int, int, const SegTable<RowFwdJob>&,
-                                          const void* const*, const FieldPtrs&, const void*,
+                                          const void* const*, const FieldPtrs&, const void*, bool,
                                           hipStream_t);
 template hipError_t launch_row_fwd<double>(int, int, int, const SegTable<RowFwdJob>&,
-                                           const void* const*, const FieldPtrs&, const void*,
+                                           const void* const*, const FieldPtrs&, const void*, bool,
                                            hipStream_t);
 template hipError_t launch_col<float>(int, int, int, int, const SegTable<ColJob>&, const void*,
                                       hipStream_t);
@@ -908,7 +923,8 @@ hipError_t prepare_kernels()
     const int lim = (int)TD_MAX_DYN_LDS;
     hipError_t e = hipSuccess;
 #define SETA(k) if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-#define X(MM) SETA((k_row_fwd<float, MM>)) SETA((k_row_fwd<double, MM>)) \
+#define X(MM) SETA((k_row_fwd<float, MM, true>)) SETA((k_row_fwd<double, MM, true>)) \
+    SETA((k_row_fwd<double, MM, false>)) \
     SETA((k_col<float, MM>)) SETA((k_col<double, MM>)) \
     SETA((k_row_inv<float, MM>)) SETA((k_row_inv<double, MM>)) \
     SETA((k_spec_col<float, MM>)) SETA((k_spec_col<double, MM>))

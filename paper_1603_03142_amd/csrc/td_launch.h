@@ -50,10 +50,12 @@ struct FieldPtrs {
     void* p[TD_KARG_PTRS];
 };
 
+// padded: the solve's zero-padded rows (only lattice columns < M/2 can be
+// non-zero); false: full-length rows (the kernel tables, FP64 only).
 template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
                           const void* const* ptrs, const FieldPtrs& fp, const void* tw,
-                          hipStream_t st);
+                          bool padded, hipStream_t st);
 template <typename T>
 hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& segs,
                       const void* tw, hipStream_t st);

@@ -139,6 +139,47 @@ def test_server_alone_equals_in_mix(ctx):
     srv.close()
 
 
+def test_server_mixed_quantities_and_slopes(ctx):
+    """Force and potential plans, given and estimated slopes, interleaved in
+    one server: every request's output equals its own single solve bit for
+    bit (a flight runs the batch launches, which compute each member exactly
+    as a single solve does)."""
+    import torch
+    import paper_1603_03142_amd as td
+    hiers = _mix(seed=11, count=8)
+    cases = []
+    for k, h in enumerate(hiers):
+        quantity = "potential" if k % 3 == 1 else "force"
+        slopes = "estimate" if k % 2 else "given"
+        plan = ctx.plan(h, "f32", quantity=quantity)
+        f = _dev_fields(h, 500 + k, "f32")[0]
+        f = f if slopes == "given" else (f[0], None, None)
+        cases.append((plan, f, slopes))
+    single = []
+    for plan, f, slopes in cases:
+        single.append(plan.solve(*f, slopes=slopes))
+    torch.cuda.synchronize()
+    srv = td.Server(ctx, max_inflight=2, max_batch=5)
+    tickets = []
+    for rep in range(2):
+        for k, (plan, f, slopes) in enumerate(cases):
+            tickets.append((k, *srv.submit(plan, *f, slopes=slopes)))
+    srv.drain()
+    for k, tk, fx, fy in tickets:
+        done, _ = srv.poll(tk)
+        assert done
+        want_x, want_y = single[k]
+        for a, b in zip(fx, want_x):
+            assert torch.equal(a, b), k
+        if cases[k][0].quantity == "potential":
+            assert fy is None
+        else:
+            for a, b in zip(fy, want_y):
+                assert torch.equal(a, b), k
+    assert srv.stats()["completed"] == 2 * len(cases)
+    srv.close()
+
+
 def test_server_cancel_and_budget(ctx):
     import paper_1603_03142_amd as td
     hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / 128, 2, [(128, 0, 0), (128, 64, 64)])
