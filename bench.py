@@ -25,6 +25,8 @@ by one batched launch set per step; serve = Poisson arrivals (mean rate
 serving loop, reporting p50/p99 latency beside throughput.
 """
 import argparse
+import contextlib
+import gc
 import json
 import math
 import os
@@ -47,6 +49,21 @@ TRAFFIC = {
     ("two-level-256", "f32", "estimate", "row_inv"): (7607654, "ba2d092b9ce6ac11"),
     ("two-level-256", "f32", "estimate", "row_fwd"): (9354217, "ba2d092b9ce6ac11"),
 }
+
+
+@contextlib.contextmanager
+def gc_paused():
+    """Python's cyclic garbage collector paused for a timed loop, as timeit
+    does: a full collection stalls the submitting thread for milliseconds
+    while only a few solves are queued on the device, and the GPU idles
+    (2000 eager two-level solves: 67-69 us each with it, 52.5 us without)."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
 
 
 def kernel_source_hash():
@@ -130,11 +147,12 @@ def run_batch(args, td, torch, synth):
     for _ in range(args.warmup):
         batch.solve(fields, outs, use_graph=use_graph, stream=stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.solve(fields, outs, use_graph=use_graph, stream=stream)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.solve(fields, outs, use_graph=use_graph, stream=stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     cells = sum(p.cells for p in plans)
     return {
         "metric": METRIC,
@@ -144,7 +162,7 @@ def run_batch(args, td, torch, synth):
         "data": "synthetic",
         "config": {"workload": "batch-64", "hierarchies": len(plans), "cells_per_step": cells,
                    "mode": args.mode, "slopes": args.slopes,
-                   "workspace_bytes": batch.footprint()},
+                   "workspace_bytes": batch.footprint(), "python_gc": "paused in timed loops"},
         "roofline": None, "cpu_baseline": None,
     }
 
@@ -343,11 +361,12 @@ def main():
         ctx.timing(True, passes=[dom])
         ctx.timing_read()  # clear
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with gc_paused():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     elapsed = t1 - t0
     passes = ctx.timing_read() if dom else None
     ctx.timing(False)
@@ -357,11 +376,12 @@ def main():
     # latency of one solve on an idle device: enqueue to completion, each
     # solve synchronised (after the timed region, so it does not change it)
     lat = []
-    for _ in range(max(50, min(400, args.steps))):
-        t0 = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
+    with gc_paused():
+        for _ in range(max(50, min(400, args.steps))):
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
     lat = np.array(lat) * 1e3
     latency = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "samples": len(lat),
@@ -397,11 +417,12 @@ def main():
         for _ in range(3):
             plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream, slopes=SL)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(k64):
-            plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream, slopes=SL)
-        torch.cuda.synchronize()
-        el64 = time.perf_counter() - t0
+        with gc_paused():
+            t0 = time.perf_counter()
+            for _ in range(k64):
+                plan64.solve(S64, DX64, DY64, FX64, FY64, stream=stream, slopes=SL)
+            torch.cuda.synchronize()
+            el64 = time.perf_counter() - t0
         v64 = cells * k64 / el64
         fp64 = {"value": v64, "unit": "cells/s", "steps": k64,
                 "ms_per_step": 1000.0 * el64 / k64, "speedup": value / v64}
@@ -471,7 +492,8 @@ def main():
                    "patches": [[p.level, p.n] for p in hier.patches], "ratio": hier.ratio,
                    "cells_per_solve": cells, "mode": args.mode, "slopes": args.slopes,
                    "quantity": args.quantity,
-                   "plan_build_s": round(plan_s, 3), "autotune_s": tune_s},
+                   "plan_build_s": round(plan_s, 3), "autotune_s": tune_s,
+                   "python_gc": "paused in timed loops"},
         "latency": latency,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -144,13 +144,32 @@ struct td_context {
     bool timing = false;
     int timing_mask = 0;  // launch kinds timed (bit per kind)
     struct Timed { int pass; hipEvent_t a, b; };
-    std::vector<Timed> timed;
+    std::deque<Timed> timed;
     std::vector<hipEvent_t> ev_pool;
     double t_ms[NTIMED] = {0, 0, 0, 0};
     int64_t t_n[NTIMED] = {0, 0, 0, 0};
+    // Fold the timed launches that have completed into the totals and
+    // return their events to the pool (oldest first, stopping at the first
+    // still in flight), so that a long timed run reuses a few events
+    // instead of creating two per launch.
+    void harvest_timed()
+    {
+        while (!timed.empty() && hipEventQuery(timed.front().b) == hipSuccess) {
+            const Timed t = timed.front();
+            timed.pop_front();
+            float e = 0;
+            if (hipEventElapsedTime(&e, t.a, t.b) == hipSuccess) {
+                t_ms[t.pass] += e;
+                t_n[t.pass] += 1;
+            }
+            ev_pool.push_back(t.a);
+            ev_pool.push_back(t.b);
+        }
+    }
     hipEvent_t get_event()
     {
         hipEvent_t e = nullptr;
+        if (ev_pool.empty()) harvest_timed();
         if (!ev_pool.empty()) {
             e = ev_pool.back();
             ev_pool.pop_back();
