@@ -180,12 +180,23 @@ __device__ __forceinline__ void seq_sync()
 // inputs r >= R/2 are the elements >= M/2, so ZIN (those elements are zero)
 // skips them; in the last (NS R == M) its outputs r >= R/2 land at >= M/2,
 // so ZOUT (only elements < M/2 are wanted) does not form or store them.
+//
+// Register ends: the inputs of a thread's butterflies in the first pass,
+// elements j + r M/R with j = lane + q M/8, are the elements lane + k M/8
+// (k = q + r 8/R), and the outputs of its one radix-8 butterfly in the last
+// pass are again lane + r M/8.  FROMR takes the first pass's inputs from
+// vr[k] instead of LDS; TOR leaves the last pass's outputs in vr[r] instead
+// of storing them (and ends without the closing ordering point: the one
+// after its reads already orders them before any later write).
 template <typename T, int M, int R, int NS, bool INV, int PR, int PW, bool ZIN = false,
-          bool ZOUT = false>
-__device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
+          bool ZOUT = false, bool FROMR = false, bool TOR = false>
+__device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane,
+                                              cpx<T>* vr = nullptr)
 {
     static_assert(!ZIN || NS == 1, "ZIN applies to the first pass");
     static_assert(!ZOUT || NS * R == M, "ZOUT applies to the last pass");
+    static_assert(!FROMR || NS == 1, "FROMR applies to the first pass");
+    static_assert(!TOR || (NS * R == M && R == 8), "TOR applies to the last (radix-8) pass");
     constexpr int B = 8 / R;          // butterflies per thread
     constexpr int STRIDE = M / R;     // distance between butterfly inputs
     constexpr int RIN = ZIN ? R / 2 : R, ROUT = ZOUT ? R / 2 : R;
@@ -197,7 +208,12 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
     // in every pass, so the padding splits over the sum.)
     constexpr bool LIN = M >= 64;
     cpx<T> v[B][R];
-    if constexpr (LIN) {
+    if constexpr (FROMR) {
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = r < RIN ? vr[q + r * B] : cpx<T>{0, 0};
+    } else if constexpr (LIN) {
         const cpx<T>* rp = x + lds_pos_p<PR>(lane);
 #pragma unroll
         for (int q = 0; q < B; ++q)
@@ -231,7 +247,10 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
         }
         dftR<T, R, INV, ZIN, ZOUT>(v[q]);
         const int base = (j / NS) * NS * R + k;
-        if constexpr (LIN) {
+        if constexpr (TOR) {
+#pragma unroll
+            for (int r = 0; r < ROUT; ++r) vr[r] = v[q][r];
+        } else if constexpr (LIN) {
             cpx<T>* wp = x + lds_pos_p<PW>(base);
 #pragma unroll
             for (int r = 0; r < ROUT; ++r) wp[r * NS + (r * NS) / PW] = v[q][r];
@@ -240,7 +259,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
             for (int r = 0; r < ROUT; ++r) x[lds_pos_p<PW>(base + r * NS)] = v[q][r];
         }
     }
-    seq_sync<M>();
+    if constexpr (!TOR) seq_sync<M>();
 }
 
 // Padding of the layout a pass of span NS writes: FP32 stores of spans 2-8
@@ -251,13 +270,16 @@ __host__ __device__ constexpr int pass_pad()
     return (sizeof(T) == 4 && NS >= 2 && NS <= 8 && NS * 8 < M) ? 8 : lds_pad<T>();
 }
 
-template <typename T, int M, int NS, bool INV, int PR, bool ZIN, bool ZOUT>
-__device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane)
+template <typename T, int M, int NS, bool INV, int PR, bool ZIN, bool ZOUT, bool FROMR = false,
+          bool TOR = false>
+__device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane,
+                                              cpx<T>* vr = nullptr)
 {
     if constexpr (NS < M) {
         constexpr int PW = pass_pad<T, M, NS>();
-        stockham_pass<T, M, 8, NS, INV, PR, PW, ZIN && NS == 1, ZOUT && NS * 8 == M>(x, tw, lane);
-        radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT>(x, tw, lane);
+        stockham_pass<T, M, 8, NS, INV, PR, PW, ZIN && NS == 1, ZOUT && NS * 8 == M,
+                      FROMR && NS == 1, TOR && NS * 8 == M>(x, tw, lane, vr);
+        radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, FROMR, TOR>(x, tw, lane, vr);
     }
 }
 
@@ -290,6 +312,34 @@ __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ 
         radix8_passes<T, M, 4, INV, P, false, ZOUT>(x, tw, lane);
     } else {
         radix8_passes<T, M, 1, INV, P, ZIN, ZOUT>(x, tw, lane);
+    }
+}
+
+// fft_lds with register ends: the calling thread's elements lane + k M/8
+// (k < 8) of its sequence (f = threadIdx.x / (M/8)) come in and go out in
+// v[k]; only the middle passes use the sequence's LDS.  With ZIN, v[4..7]
+// are not read; with ZOUT, only v[0..3] are formed.  Must be called by every
+// thread of the workgroup; on return the sequence's LDS may be written
+// again by any of its threads.
+template <typename T, int M, bool INV, bool ZIN = false, bool ZOUT = false>
+__device__ __forceinline__ void fft_regs(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw)
+{
+    static_assert(M >= 16 && (M & (M - 1)) == 0, "M must be a power of two >= 16");
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int f = tid / (M / 8);
+    const int lane = tid % (M / 8);
+    cpx<T>* x = buf + (size_t)f * lds_stride<T>(M);
+    constexpr int REM = ilog2(M) % 3;
+    constexpr int P = lds_pad<T>();
+    if constexpr (REM == 1) {
+        stockham_pass<T, M, 2, 1, INV, P, P, ZIN, false, true, false>(x, tw, lane, v);
+        radix8_passes<T, M, 2, INV, P, false, ZOUT, false, true>(x, tw, lane, v);
+    } else if constexpr (REM == 2) {
+        stockham_pass<T, M, 4, 1, INV, P, P, ZIN, false, true, false>(x, tw, lane, v);
+        radix8_passes<T, M, 4, INV, P, false, ZOUT, false, true>(x, tw, lane, v);
+    } else {
+        radix8_passes<T, M, 1, INV, P, ZIN, ZOUT, true, true>(x, tw, lane, v);
     }
 }
 

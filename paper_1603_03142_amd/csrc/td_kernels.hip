@@ -390,14 +390,14 @@ struct ColTables {
     const ColOut* outs;
 };
 
-// Stored rows of input plane I, column kx, into the lower half of sequence
-// a (zero elsewhere in that half).  Lattice rows >= M/2 hold no source cell
-// (M >= 2 ny and the nesting, checked on the host): that half is zero, is
-// not written here and is skipped by the forward transform (ZIN).
-// (Unconditional loads from a clamped row -- row 0 of the workspace for a
-// slot without an input -- then a select.)
+// Stored rows of input plane I, column kx, at the calling thread's
+// elements lane + q M/8 of the column (q < 4; zero where no row is stored).
+// Lattice rows >= M/2 hold no source cell (M >= 2 ny and the nesting,
+// checked on the host): v[4..7] are not set, the forward transform skips
+// them (ZIN).  (Unconditional loads from a clamped row -- row 0 of the
+// workspace for a slot without an input -- then a select.)
 template <typename T, int M>
-__device__ __forceinline__ void load_column(cpx<T>* a, const char* ws, const ColIn& I, int kx,
+__device__ __forceinline__ void load_column(cpx<T> (&v)[8], const char* ws, const ColIn& I, int kx,
                                             bool ok, int lane)
 {
     constexpr int TPS = M / 8;
@@ -406,21 +406,26 @@ __device__ __forceinline__ void load_column(cpx<T>* a, const char* ws, const Col
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int sr = lane + q * TPS - I.lr_first;
-        const cpx<T> v = ldg<T>(src, min(max(sr, 0), last));
-        a[lds_pos<T>(lane + q * TPS)] = (ok && sr >= 0 && sr <= last) ? v : cpx<T>{0, 0};
+        const cpx<T> x = ldg<T>(src, min(max(sr, 0), last));
+        v[q] = (ok && sr >= 0 && sr <= last) ? x : cpx<T>{0, 0};
     }
 }
 
-// Rows [out_lr_first, out_lr_first + out_ld) of the transformed sequence a
-// (all below M/2, checked on the host: the inverse transforms form only
-// that half, ZOUT).
+// Rows [out_lr_first, out_lr_first + out_ld) of a transformed column from
+// the calling thread's elements lane + r M/8; every stored row is below M/2
+// (checked on the host), so r < 4, the half the inverse transforms form
+// (ZOUT).
 template <typename T, int M>
-__device__ __forceinline__ void store_column(const cpx<T>* a, char* ws, const ColOut& O, int kx,
+__device__ __forceinline__ void store_column(const cpx<T> (&w)[8], char* ws, const ColOut& O, int kx,
                                              int lane)
 {
     constexpr int TPS = M / 8;
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(ws + O.out) + (size_t)kx * O.out_ld;
-    for (int sr = lane; sr < O.out_ld; sr += TPS) dst[sr] = a[lds_pos<T>(O.out_lr_first + sr)];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int sr = lane + r * TPS - O.out_lr_first;
+        if (sr >= 0 && sr < O.out_ld) dst[sr] = w[r];
+    }
 }
 
 template <typename T, int M>
@@ -461,13 +466,11 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             const bool ok = col_ok && i < J.nin;
             ColIn I{0, nullptr, 0, 0, 0, 0};
             if (ok) I = tabs.ins[J.in0 + i];
-            load_column<T, M>(a, ws, I, kx, ok, lane);
-            seq_sync<M>();
-            fft_lds<T, M, false, true>(A, tw);
+            cpx<T> v[8];
+            load_column<T, M>(v, ws, I, kx, ok, lane);
+            fft_regs<T, M, false, true>(v, A, tw);
             if (ok) {
-                cpx<T> v[8], kv[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = a[lds_pos<T>(lane + q * TPS)];
+                cpx<T> kv[8];
                 kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) ax[q] = ax[q] + cmul(kv[q], v[q]);
@@ -475,12 +478,13 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
 #pragma unroll
                 for (int q = 0; q < 8; ++q) ay[q] = ay[q] + cmul(kv[q], v[q]);
             }
-            // the next load writes only this thread's own positions
         }
         // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
         // (slot 0 as well when G == 1)
         const int gy = G > 1 ? 1 : 0;
         cpx<T> sx[8], sy[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sx[q] = sy[q] = cpx<T>{0, 0};
 #pragma unroll
         for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ax[q];
         __syncthreads();
@@ -506,25 +510,20 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                 sy[q] = sum;
             }
         }
-        __syncthreads();
-        if (g == 0) {
+        __syncthreads();  // the sums are read: the slots' LDS is free again
+        // inverse column transforms in registers (every slot transforms:
+        // slot 0 Fx, slot gy Fy, the others zeros)
+        cpx<T> w[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sx[q];
-        } else if (g == gy) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sy[q];
-        }
-        __syncthreads();
-        fft_lds<T, M, true, false, true>(A, tw);
-        if (col_ok && g == 0) store_column<T, M>(a, ws, tabs.outs[J.out0], kx, lane);
-        if (col_ok && G > 1 && g == 1) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
+        for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
+        fft_regs<T, M, true, false, true>(w, A, tw);
+        if (col_ok && g == 0) store_column<T, M>(w, ws, tabs.outs[J.out0], kx, lane);
+        if (col_ok && G > 1 && g == 1) store_column<T, M>(w, ws, tabs.outs[J.out0 + 1], kx, lane);
         if (G == 1) {
-            __syncthreads();
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = sy[q];
-            __syncthreads();
-            fft_lds<T, M, true, false, true>(A, tw);
-            if (col_ok) store_column<T, M>(a, ws, tabs.outs[J.out0 + 1], kx, lane);
+            for (int q = 0; q < 8; ++q) w[q] = sy[q];
+            fft_regs<T, M, true, false, true>(w, A, tw);
+            if (col_ok) store_column<T, M>(w, ws, tabs.outs[J.out0 + 1], kx, lane);
         }
         return;
     }
@@ -537,9 +536,11 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         const bool ok = col_ok && i < 3;
         ColIn I{0, nullptr, 0, 0, 0, 0};
         if (ok) I = tabs.ins[J.in0 + i];
-        load_column<T, M>(a, ws, I, kx, ok, lane);
-        seq_sync<M>();
-        fft_lds<T, M, false, true>(A, tw);
+        cpx<T> v[8];
+        load_column<T, M>(v, ws, I, kx, ok, lane);
+        fft_regs<T, M, false, true>(v, A, tw);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = v[q];
         __syncthreads();  // every slot reads the three transformed inputs
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -569,12 +570,8 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                 for (int q = 0; q < 8; ++q) acc[q] = acc[q] + cmul(kv[q], vin[f][q]);
             }
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = acc[q];
-        seq_sync<M>();
-        fft_lds<T, M, true, false, true>(A, tw);
-        if (ok) store_column<T, M>(a, ws, O, kx, lane);
-        seq_sync<M>();
+        fft_regs<T, M, true, false, true>(acc, A, tw);
+        if (ok) store_column<T, M>(acc, ws, O, kx, lane);
     }
 }
 
