@@ -468,7 +468,9 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             if (ok) I = tabs.ins[J.in0 + i];
             cpx<T> v[8];
             load_column<T, M>(v, ws, I, kx, ok, lane);
-            fft_regs<T, M, false, true>(v, A, tw);
+            // a slot without an input skips its transform when sequences
+            // are ordered within their wavefront only (M/8 <= 64)
+            if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
             if (ok) {
                 cpx<T> kv[8];
                 kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
@@ -516,7 +518,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         cpx<T> w[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
-        fft_regs<T, M, true, false, true>(w, A, tw);
+        if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
         if (col_ok && g == 0) store_column<T, M>(w, ws, tabs.outs[J.out0], kx, lane);
         if (col_ok && G > 1 && g == 1) store_column<T, M>(w, ws, tabs.outs[J.out0 + 1], kx, lane);
         if (G == 1) {
@@ -570,7 +572,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                 for (int q = 0; q < 8; ++q) acc[q] = acc[q] + cmul(kv[q], vin[f][q]);
             }
         }
-        fft_regs<T, M, true, false, true>(acc, A, tw);
+        if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);
         if (ok) store_column<T, M>(acc, ws, O, kx, lane);
     }
 }
@@ -684,7 +686,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
             if (kx > 0 && kx < M / 2) row[lds_pos<T>(M - kx)] = zr;
         }
         __syncthreads();
-        fft_lds<T, M, true, false, true>(A, tw);
+        // a slot without an item need not transform (its zeros are never
+        // read); with M/8 <= 64 a sequence is ordered within its wavefront
+        // only, so skipping it cannot unbalance a workgroup barrier
+        if (M / 8 > 64 || it_c[(threadIdx.x / TPS) % G] >= 0) fft_lds<T, M, true, false, true>(A, tw);
         __syncthreads();  // outputs gather from every slot of their row
         for (int gg = 0; gg < G; ++gg) {
             if (it_c[gg] < 0) break;
