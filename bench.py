@@ -45,9 +45,9 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # slopes mode, pass) and tied to the SHA-256 of the kernel source they were taken on: a
 # changed kernel reports null until it is profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "estimate", "col"): (29276502, "9809038ff08fa2f1"),
-    ("two-level-256", "f32", "estimate", "row_inv"): (7607662, "9809038ff08fa2f1"),
-    ("two-level-256", "f32", "estimate", "row_fwd"): (9354518, "9809038ff08fa2f1"),
+    ("two-level-256", "f32", "estimate", "col"): (29289505, "3acb4b0d759eaf5b"),
+    ("two-level-256", "f32", "estimate", "row_inv"): (7626106, "3acb4b0d759eaf5b"),
+    ("two-level-256", "f32", "estimate", "row_fwd"): (9353900, "3acb4b0d759eaf5b"),
 }
 
 
