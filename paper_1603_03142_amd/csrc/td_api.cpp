@@ -2008,14 +2008,23 @@ void db_load(td_context* ctx, const char* path, const std::string& arch)
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
+        // position of the value of "key" (after its colon and any blanks)
+        auto value_at = [&](const char* key) -> size_t {
+            size_t p = line.find(std::string("\"") + key + "\"");
+            if (p == std::string::npos) return std::string::npos;
+            p = line.find(':', p + strlen(key) + 2);
+            if (p == std::string::npos) return std::string::npos;
+            return line.find_first_not_of(" \t", p + 1);
+        };
         auto num = [&](const char* key, double* v) {
-            size_t p = line.find(std::string("\"") + key + "\":");
+            const size_t p = value_at(key);
             if (p == std::string::npos) return false;
-            *v = atof(line.c_str() + p + strlen(key) + 3);
+            *v = atof(line.c_str() + p);
             return true;
         };
+        const size_t pa = value_at("arch");
+        if (pa == std::string::npos || line.compare(pa, arch.size() + 2, "\"" + arch + "\"") != 0) continue;
         double dt, pass, M, C, G = 1;
-        if (line.find("\"arch\":\"" + arch + "\"") == std::string::npos) continue;
         num("G", &G);
         if (num("dtype", &dt) && num("pass", &pass) && num("M", &M) && num("C", &C))
             ctx->tune[std::make_tuple((int)pass, (int)M, (int)dt)] = pack_shape((int)C, (int)G);
