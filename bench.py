@@ -42,12 +42,14 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # HBM bytes per launch of a pass, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs
 # of this script, each scaled by the ratio of a plain copy kernel's known
 # bytes to what the same counter read for it.  Keyed by (workload, dtype,
-# slopes mode, pass) and tied to the SHA-256 of the kernel source they were taken on: a
-# changed kernel reports null until it is profiled again.
+# slopes mode, pass) and tied to the SHA-256 of the sources they were taken
+# on -- the kernels and the plan builder, whose jobs and launch shapes
+# decide the traffic too: a changed source reports null until it is
+# profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "estimate", "col"): (29289505, "3acb4b0d759eaf5b"),
-    ("two-level-256", "f32", "estimate", "row_inv"): (7626106, "3acb4b0d759eaf5b"),
-    ("two-level-256", "f32", "estimate", "row_fwd"): (9353900, "3acb4b0d759eaf5b"),
+    ("two-level-256", "f32", "estimate", "col"): (29281284, "2ff9d86c32016cda"),
+    ("two-level-256", "f32", "estimate", "row_inv"): (5496380, "2ff9d86c32016cda"),
+    ("two-level-256", "f32", "estimate", "row_fwd"): (9354505, "2ff9d86c32016cda"),
 }
 
 
@@ -69,7 +71,7 @@ def gc_paused():
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("td_kernels.hip", "td_fft.hpp", "td_jobs.h", "td_launch.h"):
+    for f in ("td_kernels.hip", "td_fft.hpp", "td_jobs.h", "td_launch.h", "td_api.cpp"):
         with open(os.path.join(ROOT, "paper_1603_03142_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

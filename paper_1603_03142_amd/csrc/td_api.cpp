@@ -92,7 +92,8 @@ int pack_shape(int C, int G) { return C | (G << 16); }
 
 // Default launch shapes (from autotuning on gfx950): row FFTs 256 threads;
 // the column pass and the row inverse one column / row per workgroup with
-// up to 16 slots, 512 threads up to M = 256 and 256 threads beyond; LDS
+// up to 16 slots, 512 threads up to M = 256 and 256 threads beyond, except
+// the row inverse at M = 512: two rows of 4 slots (512 threads); LDS
 // <= 64 KiB.
 int default_shape(int pass, int M, td_dtype dt)
 {
@@ -102,6 +103,7 @@ int default_shape(int pass, int M, td_dtype dt)
         while (S > 1 && lds_bytes(M, S, es) > 64 * 1024) S /= 2;
         return pack_shape(S, 1);
     }
+    if (pass == P_ROWINV && M == 512 && lds_bytes(M, 2, es, 4) <= 64 * 1024) return pack_shape(2, 4);
     int S = std::max(1, (M <= 256 ? 4096 : 2048) / M);
     int G = std::min(16, S);
     int C = std::max(1, S / G);
