@@ -47,9 +47,9 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # decide the traffic too: a changed source reports null until it is
 # profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "estimate", "col"): (29281284, "2ff9d86c32016cda"),
-    ("two-level-256", "f32", "estimate", "row_inv"): (5496380, "2ff9d86c32016cda"),
-    ("two-level-256", "f32", "estimate", "row_fwd"): (9354505, "2ff9d86c32016cda"),
+    ("two-level-256", "f32", "estimate", "col"): (29275163, "6c19ff0199bdee8c"),
+    ("two-level-256", "f32", "estimate", "row_inv"): (5478977, "6c19ff0199bdee8c"),
+    ("two-level-256", "f32", "estimate", "row_fwd"): (9354249, "6c19ff0199bdee8c"),
 }
 
 

@@ -411,6 +411,24 @@ __device__ __forceinline__ void load_column(cpx<T> (&v)[8], const char* ws, cons
     }
 }
 
+// load_column split in two so that the loads can be issued one iteration
+// ahead: the raw values (unconditional loads from a clamped row) and their
+// validity, applied where the values are used.
+template <typename T, int M>
+__device__ __forceinline__ void load_column_raw(cpx<T> (&x)[4], bool (&val)[4], const char* ws,
+                                                const ColIn& I, int kx, bool ok, int lane)
+{
+    constexpr int TPS = M / 8;
+    gptr<cpx<T>> src = (gptr<cpx<T>>)(ws + (ok ? I.in + (int64_t)kx * I.ld * (int64_t)sizeof(cpx<T>) : 0));
+    const int last = ok ? I.ld - 1 : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int sr = lane + q * TPS - I.lr_first;
+        x[q] = ldg<T>(src, min(max(sr, 0), last));
+        val[q] = ok && sr >= 0 && sr <= last;
+    }
+}
+
 // Rows [out_lr_first, out_lr_first + out_ld) of a transformed column from
 // the calling thread's elements lane + r M/8; every stored row is below M/2
 // (checked on the host), so r < 4, the half the inverse transforms form
@@ -459,15 +477,33 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         cpx<T> ax[8], ay[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
+        // each input's column is loaded one iteration ahead, while the
+        // previous input is transformed and multiplied
+        ColIn In{0, nullptr, 0, 0, 0, 0};
+        bool okn;
+        cpx<T> xn[4];
+        bool vn[4];
+        {
+            const int i = slot_uniform<M>(g);
+            okn = col_ok && i < J.nin;
+            if (okn) In = tabs.ins[J.in0 + i];
+            load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
+        }
         for (int r0 = 0; r0 < J.nin; r0 += G) {
             int lane = lane_c;
             asm volatile("" : "+v"(lane));
-            const int i = slot_uniform<M>(r0 + g);
-            const bool ok = col_ok && i < J.nin;
-            ColIn I{0, nullptr, 0, 0, 0, 0};
-            if (ok) I = tabs.ins[J.in0 + i];
+            const ColIn I = In;
+            const bool ok = okn;
             cpx<T> v[8];
-            load_column<T, M>(v, ws, I, kx, ok, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
+            {
+                const int i = slot_uniform<M>(r0 + G + g);
+                okn = col_ok && i < J.nin;
+                In = ColIn{0, nullptr, 0, 0, 0, 0};
+                if (okn) In = tabs.ins[J.in0 + i];
+                load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
+            }
             // a slot without an input skips its transform when sequences
             // are ordered within their wavefront only (M/8 <= 64)
             if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
