@@ -47,9 +47,9 @@ METRIC = "force-solve cells/s at rel-L2 <=1e-5 vs FP64 oracle; p50/p99 latency"
 # decide the traffic too: a changed source reports null until it is
 # profiled again.
 TRAFFIC = {
-    ("two-level-256", "f32", "estimate", "col"): (29275163, "6c19ff0199bdee8c"),
-    ("two-level-256", "f32", "estimate", "row_inv"): (5478977, "6c19ff0199bdee8c"),
-    ("two-level-256", "f32", "estimate", "row_fwd"): (9354249, "6c19ff0199bdee8c"),
+    ("two-level-256", "f32", "estimate", "col"): (35638059, "11647acb5d2dd52a"),
+    ("two-level-256", "f32", "estimate", "row_inv"): (5485122, "11647acb5d2dd52a"),
+    ("two-level-256", "f32", "estimate", "row_fwd"): (9355045, "11647acb5d2dd52a"),
 }
 
 

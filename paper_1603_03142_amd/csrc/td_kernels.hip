@@ -329,6 +329,57 @@ __device__ __forceinline__ cpx<T> ldg(gptr<cpx<T>> p, size_t i)
 //    its x- / y-mirror image: S'(kx, ky) = s_x conj S(kx, -ky),
 //    s_y S(kx, -ky), or s_x s_y conj S(kx, ky).
 // Branch-free apart from the layout test, which is uniform per slot.
+// kern_load issues the reads (the real layout fills only .re) and
+// kern_apply forms the values, so that the reads can be in flight across
+// other work in between; kern_column does both at once.
+template <typename T, int M>
+__device__ __forceinline__ void kern_load(cpx<T> (&z)[8], const void* Kv, int X, int kx, int flip,
+                                          int lane)
+{
+    constexpr int TPS = M / 8, H = M / 2 + 1;
+    if (flip & 4) {
+        gptr<T> R = (gptr<T>)Kv + ((size_t)X * H + kx) * H;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ky = lane + q * TPS;
+            z[q].re = R[q < 4 ? ky : M - ky];  // ky >= M/2 from its mirror M - ky
+        }
+    } else {
+        gptr<cpx<T>> K = (gptr<cpx<T>>)Kv + ((size_t)X * H + kx) * M;
+        const int mir = flip & 3;
+        const bool rev = mir == 1 || mir == 2;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ky = lane + q * TPS;
+            z[q] = ldg<T>(K, rev ? ((M - ky) & (M - 1)) : ky);
+        }
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void kern_apply(cpx<T> (&kv)[8], const cpx<T> (&z)[8], int X, int flip,
+                                           int lane)
+{
+    const int fam = (flip >> 3) & 1;
+    if (flip & 4) {
+        const T sy = (T)sign_y(X, fam);
+        const bool imag = sign_x(X, fam) * sign_y(X, fam) < 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            T v = z[q].re;
+            if (q > 4 || (q == 4 && lane > 0)) v *= sy;  // ky = M/2 is stored directly
+            kv[q] = imag ? cpx<T>{0, v} : cpx<T>{v, 0};
+        }
+    } else {
+        const int mir = flip & 3;
+        const T s = (T)(((mir & 1) ? sign_x(X, fam) : 1) * ((mir & 2) ? sign_y(X, fam) : 1));
+        const T si = (mir & 1) ? -s : s;  // x-mirrors conjugate
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kv[q] = cpx<T>{s * z[q].re, si * z[q].im};
+    }
+}
+
+// The same in one step (no reads left in flight).
 template <typename T, int M>
 __device__ __forceinline__ void kern_column(cpx<T>* kv, const void* Kv, int X, int kx, int flip,
                                             int lane)
@@ -504,15 +555,29 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                 if (okn) In = tabs.ins[J.in0 + i];
                 load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
             }
+            // FP32 with M >= 512: the input's kernel columns are read
+            // before its transform and formed after it, so that the reads
+            // are in flight meanwhile (32 more VGPRs, still 3 waves per
+            // SIMD there; smaller M and FP64 would lose occupancy or spill)
+            constexpr bool EARLY = sizeof(T) == 4 && M >= 512;
+            cpx<T> z0[8], z1[8];
+            if constexpr (EARLY) {
+                if (ok) {
+                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                }
+            }
             // a slot without an input skips its transform when sequences
             // are ordered within their wavefront only (M/8 <= 64)
             if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
             if (ok) {
                 cpx<T> kv[8];
-                kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                if constexpr (EARLY) kern_apply<T, M>(kv, z0, kern_of(0, I.f), I.flip, lane);
+                else kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) ax[q] = ax[q] + cmul(kv[q], v[q]);
-                kern_column<T, M>(kv, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                if constexpr (EARLY) kern_apply<T, M>(kv, z1, kern_of(1, I.f), I.flip, lane);
+                else kern_column<T, M>(kv, I.kern, kern_of(1, I.f), kx, I.flip, lane);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) ay[q] = ay[q] + cmul(kv[q], v[q]);
             }
