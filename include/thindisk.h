@@ -245,23 +245,49 @@ td_status td_server_create(td_context* ctx, int32_t max_inflight, int32_t max_ba
  * beyond it are refused (see td_server_submit). */
 td_status td_server_set_queue_limit(td_server* s, int32_t max_queued);
 /* Submit a solve.  The request's plan must stay alive until the ticket is
- * done.  If the server has no room (queue at its limit) and queue_if_full
- * is 0, returns TD_EBUSY (counted as refused).  Arrival time = time of the
- * call. */
+ * done.  Ordering: the call records an event on `hip_stream` (a hipStream_t
+ * of the caller, NULL = the null stream), and the solve starts only after
+ * the work enqueued there before the call -- the writes of sigma and the
+ * slopes, and any earlier use of the output buffers -- has completed.  The
+ * caller must not write the inputs or touch the outputs again until the
+ * ticket is done.  If the server has no room (queue at its limit) and
+ * queue_if_full is 0, returns TD_EBUSY (counted as refused).  Arrival time
+ * = time of the call. */
 td_status td_server_submit(td_server* s, const td_request* req, int32_t queue_if_full,
-                           uint64_t* ticket);
+                           void* hip_stream, uint64_t* ticket);
+/* Submit a solve of a hierarchy for which the caller holds no plan
+ * (req->plan must be NULL; the other fields of req as for td_solve, with
+ * npatches of `h`).  The server plans the hierarchy on a thread of its own
+ * -- spectra and job tables are built on the context's stream while
+ * flights keep running -- keeps the plan for later requests of the same
+ * hierarchy (until the server is destroyed), and then admits the request as
+ * td_server_submit does.  Validation errors are returned at once; planning
+ * failures (e.g. TD_ENOMEM) are reported by td_server_poll.  Ordering and
+ * refusal as td_server_submit. */
+td_status td_server_submit_hierarchy(td_server* s, const td_hierarchy* h, td_dtype dtype,
+                                     int32_t quantity, const td_request* req,
+                                     int32_t queue_if_full, void* hip_stream, uint64_t* ticket);
 /* done = 1 once the outputs of `ticket` are complete on the device.
- * latency_s = completion - submission (seconds), valid when done. */
+ * latency_s = completion - submission (seconds), valid when done.  A ticket
+ * reported done (or failed) is forgotten: polling it again is TD_EINVAL.  A
+ * request that failed returns its error status (e.g. TD_ENOMEM when its
+ * workspace can never fit in the budget) instead of TD_OK. */
 td_status td_server_poll(td_server* s, uint64_t ticket, int32_t* done, double* latency_s);
 /* Block until every submitted request is done. */
 td_status td_server_drain(td_server* s);
-/* Cancel a request that has not started; TD_EINVAL if unknown or started. */
+/* Cancel a request that has not started (queued or waiting for its plan);
+ * TD_EINVAL if unknown or started.  The ticket is forgotten. */
 td_status td_server_cancel(td_server* s, uint64_t ticket);
 /* Counters: completed, cancelled, refused, deferred (admission waited for
  * memory), batches launched, peak queue depth. */
 td_status td_server_stats(const td_server* s, uint64_t* completed, uint64_t* cancelled,
                           uint64_t* refused, uint64_t* deferred, uint64_t* batches,
                           uint64_t* peak_queue);
+/* Hierarchies planned by the server (td_server_submit_hierarchy) and
+ * requests that failed. */
+td_status td_server_stats2(const td_server* s, uint64_t* planned, uint64_t* failed);
+/* Stop accepting work, finish every submitted request, free the server's
+ * streams, workspace pool and the plans it made. */
 td_status td_server_destroy(td_server* s);
 
 /* ---------------------------------------------------------------- diagnostics */

@@ -288,18 +288,79 @@ class Server:
                 "td_server_set_queue_limit")
 
     def submit(self, plan: Plan, sigma, dsdx=None, dsdy=None, fx=None, fy=None,
-               queue_if_full: bool = True, slopes="given"):
+               queue_if_full: bool = True, slopes="given", stream=None):
+        """Submit a solve of `plan`.  The solve waits for the work enqueued on
+        `stream` (default: the current torch stream) before the call, so
+        inputs written there are visible; the tensors are held until the
+        ticket is reported done."""
         req, fx, fy = plan.request(sigma, dsdx, dsdy, fx, fy, slopes)
         t = ctypes.c_uint64()
         B.check(lib().td_server_submit(self.handle, ctypes.byref(req), 1 if queue_if_full else 0,
-                                       ctypes.byref(t)), "td_server_submit")
+                                       _stream_handle(stream), ctypes.byref(t)),
+                "td_server_submit")
+        self._live[t.value] = req
+        return t.value, fx, fy
+
+    def submit_hierarchy(self, hier, dtype: str, sigma, dsdx=None, dsdy=None, fx=None,
+                         fy=None, queue_if_full: bool = True, slopes="given",
+                         quantity: str = "force", stream=None):
+        """Submit a solve of a hierarchy the caller has no plan for: the
+        server plans it (off its launch thread, once per distinct
+        hierarchy) and then admits it like any other request."""
+        mode = _SLOPES.get(slopes)
+        if mode is None:
+            raise ValueError(f"slopes must be one of {sorted(_SLOPES)}")
+        torch = _torch()
+        tdt = torch.float32 if dtype == "f32" else torch.float64
+        sizes = [p.n for p in hier.patches]
+        pot = quantity == "potential"
+
+        def chk(arrays, name, required):
+            if arrays is None:
+                if required:
+                    raise ValueError(f"{name} is required")
+                return
+            if len(arrays) != len(sizes):
+                raise ValueError(f"{name}: expected {len(sizes)} arrays")
+            for t, n in zip(arrays, sizes):
+                if t is None:
+                    if required:
+                        raise ValueError(f"{name} has a None entry")
+                    continue
+                if not t.is_cuda or t.dtype != tdt or tuple(t.shape) != (n, n) \
+                        or not t.is_contiguous():
+                    raise ValueError(f"{name}: contiguous {tdt} CUDA tensors of shape (n, n)")
+        chk(sigma, "sigma", True)
+        chk(dsdx, "dsdx", False)
+        chk(dsdy, "dsdy", False)
+        if fx is None:
+            dev = torch.device("cuda", self.ctx.device)
+            fx = [torch.empty((n, n), dtype=tdt, device=dev) for n in sizes]
+            fy = None if pot else [torch.empty((n, n), dtype=tdt, device=dev) for n in sizes]
+        chk(fx, "fx", True)
+        chk(fy, "fy", not pot)
+        h = B.make_hierarchy(hier)
+        req = B.make_request(None, sigma, dsdx, dsdy, fx, fy, mode)
+        req._tensors = (sigma, dsdx, dsdy, fx, fy, h)
+        t = ctypes.c_uint64()
+        B.check(lib().td_server_submit_hierarchy(self.handle, ctypes.byref(h), _DT[dtype],
+                                                 _QUANTITY[quantity], ctypes.byref(req),
+                                                 1 if queue_if_full else 0,
+                                                 _stream_handle(stream), ctypes.byref(t)),
+                "td_server_submit_hierarchy")
         self._live[t.value] = req
         return t.value, fx, fy
 
     def poll(self, ticket: int):
+        """(done, latency_s).  A ticket is reported done once: the server
+        then forgets it (polling it again raises TD_EINVAL)."""
         d, lat = ctypes.c_int32(), ctypes.c_double()
-        B.check(lib().td_server_poll(self.handle, ticket, ctypes.byref(d), ctypes.byref(lat)),
-                "td_server_poll")
+        try:
+            B.check(lib().td_server_poll(self.handle, ticket, ctypes.byref(d),
+                                         ctypes.byref(lat)), "td_server_poll")
+        except TdError:
+            self._live.pop(ticket, None)
+            raise
         if d.value:
             self._live.pop(ticket, None)
         return bool(d.value), lat.value
@@ -315,8 +376,14 @@ class Server:
         v = [ctypes.c_uint64() for _ in range(6)]
         B.check(lib().td_server_stats(self.handle, *[ctypes.byref(x) for x in v]),
                 "td_server_stats")
-        return dict(zip(["completed", "cancelled", "refused", "deferred", "batches",
-                         "peak_queue"], [x.value for x in v]))
+        out = dict(zip(["completed", "cancelled", "refused", "deferred", "batches",
+                        "peak_queue"], [x.value for x in v]))
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        B.check(lib().td_server_stats2(self.handle, ctypes.byref(a), ctypes.byref(b)),
+                "td_server_stats2")
+        out["planned"] = a.value
+        out["failed"] = b.value
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

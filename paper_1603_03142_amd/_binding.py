@@ -27,7 +27,8 @@ EXPORTS = [
     "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_create_quantity",
     "td_plan_footprint", "td_plan_destroy", "td_solve",
     "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_destroy",
-    "td_autotune", "td_timing_enable", "td_timing_read", "td_plan_traffic", "td_server_create", "td_server_set_queue_limit", "td_server_submit", "td_server_poll", "td_server_drain",
+    "td_autotune", "td_timing_enable", "td_timing_read", "td_plan_traffic", "td_server_create", "td_server_set_queue_limit", "td_server_submit",
+    "td_server_submit_hierarchy", "td_server_stats2", "td_server_poll", "td_server_drain",
     "td_server_cancel", "td_server_stats", "td_server_destroy", "td_kernel_table",
     "td_status_string", "td_last_error", "td_version",
 ]
@@ -103,7 +104,11 @@ def lib():
             "td_autotune": ([VP, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p], S),
             "td_server_create": ([VP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(VP)], S),
             "td_server_set_queue_limit": ([VP, ctypes.c_int32], S),
-            "td_server_submit": ([VP, ctypes.POINTER(td_request), ctypes.c_int32, u64], S),
+            "td_server_submit": ([VP, ctypes.POINTER(td_request), ctypes.c_int32, VP, u64], S),
+            "td_server_submit_hierarchy": ([VP, ctypes.POINTER(td_hierarchy), ctypes.c_int,
+                                            ctypes.c_int32, ctypes.POINTER(td_request),
+                                            ctypes.c_int32, VP, u64], S),
+            "td_server_stats2": ([VP, u64, u64], S),
             "td_server_poll": ([VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_double)], S),
             "td_server_drain": ([VP], S),

@@ -142,6 +142,16 @@ struct td_context {
     std::map<std::tuple<int, int, int>, int> tune;               // (pass, M, dtype) -> shape
     hipStream_t stream = nullptr;                                 // plan-time work
     std::vector<void*> allocs;
+    // Scratch of the kernel-spectrum builds (FP64 tables and their row
+    // transforms), kept between builds and grown when a longer lattice
+    // appears, so that a build frees nothing (hipFree waits for the whole
+    // device, flights included).  Used under mu, on `stream` only.
+    void* b_table = nullptr;
+    size_t b_table_bytes = 0;
+    void* b_rows = nullptr;
+    size_t b_rows_bytes = 0;
+    void* b_small = nullptr;  // pointer table, level table, row jobs
+    size_t b_small_bytes = 0;
     // per-pass timing (diagnostics)
     bool timing = false;
     int timing_mask = 0;  // launch kinds timed (bit per kind)
@@ -304,53 +314,80 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int fami
     e.nphase = nphase;
     e.bytes = quarter ? 6 * NCOL * NCOL * elem_size(dt) / 2 : per_phase * nphase * elem_size(dt);
     TD_TRY(ctx->alloc(e.bytes, &e.ptr));
-    // FP64 scratch: the six real tables, their row transforms, pointer table.
-    void *table = nullptr, *rows = nullptr, *dptr = nullptr;
+    // FP64 scratch: the six real tables, their row transforms, and the
+    // small tables of the row launch (6 plane pointers, the level table of
+    // one M x M patch, the row jobs)
+    const int C = std::max(1, std::min(shape_C(default_shape(P_ROWFWD, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
+    std::vector<RowFwdJob> jobs;
+    for (int X = 0; X < 6; ++X)
+        for (int r0 = 0; r0 < M; r0 += 2 * C) {
+            RowFwdJob j;
+            memset(&j, 0, sizeof(j));
+            j.lvl = 0;
+            j.f = X;
+            j.m = 1;
+            j.ld = M;
+            j.row0 = r0;
+            j.nrow = std::min(2 * C, M - r0);
+            j.scale = 1.0;
+            j.est_scale = 1.0;
+            j.out = (int64_t)(X * NCOL * (size_t)M * 16);
+            jobs.push_back(j);
+        }
     const size_t tbytes = 6 * (size_t)M * M * sizeof(double);
     const size_t rbytes = per_phase * 16;
-    td_status st = ctx->alloc(tbytes, &table);
-    if (st == TD_OK) st = ctx->alloc(rbytes, &rows);
-    if (st == TD_OK) st = ctx->alloc(6 * sizeof(void*), &dptr);
-    void* dlp = nullptr;  // the tables as one M x M patch, field X at slot X
-    if (st == TD_OK) st = ctx->alloc(sizeof(LevelPatches), &dlp);
-    if (st == TD_OK) {
+    const size_t o_lp = 256, o_jobs = 256 + ((sizeof(LevelPatches) + 255) & ~size_t(255));
+    const size_t sbytes = o_jobs + jobs.size() * sizeof(RowFwdJob);
+    td_status st = TD_OK;
+    if (ctx->b_table_bytes < tbytes || ctx->b_rows_bytes < rbytes || ctx->b_small_bytes < sbytes) {
+        // earlier builds on the stream still read the old scratch
+        hipError_t he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
+        if (st == TD_OK && ctx->b_table_bytes < tbytes) {
+            ctx->release(ctx->b_table, ctx->b_table_bytes);
+            ctx->b_table = nullptr;
+            ctx->b_table_bytes = 0;
+            st = ctx->alloc(tbytes, &ctx->b_table);
+            if (st == TD_OK) ctx->b_table_bytes = tbytes;
+        }
+        if (st == TD_OK && ctx->b_rows_bytes < rbytes) {
+            ctx->release(ctx->b_rows, ctx->b_rows_bytes);
+            ctx->b_rows = nullptr;
+            ctx->b_rows_bytes = 0;
+            st = ctx->alloc(rbytes, &ctx->b_rows);
+            if (st == TD_OK) ctx->b_rows_bytes = rbytes;
+        }
+        if (st == TD_OK && ctx->b_small_bytes < sbytes) {
+            ctx->release(ctx->b_small, ctx->b_small_bytes);
+            ctx->b_small = nullptr;
+            ctx->b_small_bytes = 0;
+            st = ctx->alloc(sbytes, &ctx->b_small);
+            if (st == TD_OK) ctx->b_small_bytes = sbytes;
+        }
+    }
+    void* table = ctx->b_table;
+    void* rows = ctx->b_rows;
+    void* dptr = ctx->b_small;
+    void* dlp = (char*)ctx->b_small + o_lp;
+    RowFwdJob* djobs = (RowFwdJob*)((char*)ctx->b_small + o_jobs);
+    const void* tw64 = nullptr;
+    if (st == TD_OK) st = twiddles(ctx, M, TD_F64, &tw64);
+    // the small tables, staged once in host memory and copied in stream
+    // order (an earlier build's launches may still read the previous ones)
+    std::vector<char> hsmall(sbytes, 0);
+    {
+        void* hp_ptr[6];
+        for (int X = 0; X < 6; ++X) hp_ptr[X] = (char*)table + X * (size_t)M * M * sizeof(double);
+        memcpy(hsmall.data(), hp_ptr, sizeof(hp_ptr));
         LevelPatches lp;
         memset(&lp, 0, sizeof(lp));
         lp.np = 1;
         lp.pn[0] = M;
-        hipError_t he = hipMemcpy(dlp, &lp, sizeof(lp), hipMemcpyHostToDevice);
-        if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
+        memcpy(hsmall.data() + o_lp, &lp, sizeof(lp));
+        memcpy(hsmall.data() + o_jobs, jobs.data(), jobs.size() * sizeof(RowFwdJob));
     }
-    const void* tw64 = nullptr;
-    if (st == TD_OK) st = twiddles(ctx, M, TD_F64, &tw64);
-    RowFwdJob* djobs = nullptr;
-    std::vector<RowFwdJob> jobs;
-    const int C = std::max(1, std::min(shape_C(default_shape(P_ROWFWD, M, TD_F64)), TD_MAX_THREADS / (M / 8)));
     if (st == TD_OK) {
-        void* hp_ptr[6];
-        for (int X = 0; X < 6; ++X) hp_ptr[X] = (char*)table + X * (size_t)M * M * sizeof(double);
-        hipError_t he = hipMemcpy(dptr, hp_ptr, sizeof(hp_ptr), hipMemcpyHostToDevice);
-        if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
-        for (int X = 0; X < 6; ++X)
-            for (int r0 = 0; r0 < M; r0 += 2 * C) {
-                RowFwdJob j;
-                memset(&j, 0, sizeof(j));
-                j.lvl = 0;
-                j.f = X;
-                j.m = 1;
-                j.ld = M;
-                j.row0 = r0;
-                j.nrow = std::min(2 * C, M - r0);
-                j.scale = 1.0;
-                j.est_scale = 1.0;
-                j.out = (int64_t)(X * NCOL * (size_t)M * 16);
-                jobs.push_back(j);
-            }
-    }
-    if (st == TD_OK) st = ctx->alloc(jobs.size() * sizeof(RowFwdJob), (void**)&djobs);
-    if (st == TD_OK) {
-        hipError_t he = hipMemcpy(djobs, jobs.data(), jobs.size() * sizeof(RowFwdJob),
-                                  hipMemcpyHostToDevice);
+        hipError_t he = hipMemcpyAsync(dptr, hsmall.data(), sbytes, hipMemcpyHostToDevice, ctx->stream);
         if (he != hipSuccess) st = fail(TD_EDEVICE, hipGetErrorString(he));
     }
     for (int p = 0; st == TD_OK && p < nphase; ++p) {
@@ -375,14 +412,16 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int fami
             he = dt == TD_F64
                      ? launch_spec_col<double>(M, Cs, rows, dst, tw64, quarter | (family << 1), ctx->stream)
                      : launch_spec_col<float>(M, Cs, rows, dst, tw64, quarter | (family << 1), ctx->stream);
-        if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
         if (he != hipSuccess) st = fail(TD_EDEVICE, std::string("kernel-table build: ") + hipGetErrorString(he));
     }
-    ctx->release(table, tbytes);
-    ctx->release(rows, rbytes);
-    ctx->release(dptr, 6 * sizeof(void*));
-    ctx->release(dlp, sizeof(LevelPatches));
-    if (djobs) ctx->release(djobs, jobs.size() * sizeof(RowFwdJob));
+    // the staged small tables must outlive their copy, and the entry is
+    // complete for every stream once this returns
+    if (st == TD_OK) {
+        hipError_t he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) st = fail(TD_EDEVICE, std::string("kernel-table build: ") + hipGetErrorString(he));
+    } else {
+        (void)hipStreamSynchronize(ctx->stream);
+    }
     if (st != TD_OK) {
         ctx->release(e.ptr, e.bytes);
         return st;
@@ -542,6 +581,7 @@ namespace {
 // Jobs of one transform length M, on the host and on the device.
 struct Group {
     int M = 0;
+    const void* tw = nullptr;    // twiddles of length M in the plan's dtype
     int C[NSHAPE] = {1, 1, 1};   // sequences / columns / rows per workgroup
     int G[NSHAPE] = {1, 1, 1};   // slots per column or row
     std::vector<RowFwdJob> rowfwd;
@@ -1290,12 +1330,12 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
         }
         for (int M : Ms) {
             const void* tw = nullptr;
-            TD_TRY(twiddles(ctx, M, dt, &tw));
             // partition members by C of this pass
             std::map<int, std::vector<std::pair<Group*, const Member*>>> byC;
             for (auto& m : mem) {
                 Group* g = find_group(m.plan, M);
                 if (!g) continue;
+                if (!tw) tw = g->tw;
                 const int pi = pass == NSHAPE ? P_ROWINV : pass;
                 byC[pack_shape(g->C[pi], g->G[pi])].push_back({g, &m});
             }
@@ -1345,17 +1385,21 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
     return TD_OK;
 }
 
-td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v, size_t base)
+// The 5 field pointers of every patch of a request (sigma, dsdx, dsdy, fx,
+// fy) into v[base ...], checked against the patch count, element size and
+// quantity of the plan that will run it.
+td_status fill_ptrs_for(const td_request& q, int npatches, td_dtype dt, int quantity,
+                        std::vector<void*>& v, size_t base)
 {
-    const bool pot = P.quantity == TD_POTENTIAL;  // fx receives Phi; fy optional
+    const bool pot = quantity == TD_POTENTIAL;  // fx receives Phi; fy optional
     if (!q.sigma || !q.fx || (!q.fy && !pot))
         return fail(TD_EINVAL, pot ? "sigma and fx are required" : "sigma, fx and fy are required");
     if (q.slopes != TD_SLOPES_GIVEN && q.slopes != TD_SLOPES_ESTIMATE)
         return fail(TD_EINVAL, "slopes must be TD_SLOPES_GIVEN or TD_SLOPES_ESTIMATE");
     if (q.slopes == TD_SLOPES_ESTIMATE && (q.dsdx || q.dsdy))
         return fail(TD_EINVAL, "dsdx and dsdy must be NULL with TD_SLOPES_ESTIMATE");
-    const uintptr_t align = P.dt == TD_F64 ? 8 : 4;
-    for (int l = 0; l < P.npatches; ++l) {
+    const uintptr_t align = dt == TD_F64 ? 8 : 4;
+    for (int l = 0; l < npatches; ++l) {
         void* fyl = q.fy ? q.fy[l] : nullptr;
         if (!q.sigma[l] || !q.fx[l] || (!fyl && !pot))
             return fail(TD_EINVAL, "NULL sigma/fx/fy pointer of patch " + std::to_string(l));
@@ -1373,6 +1417,11 @@ td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v
             v[base + 5 * l + 1] = v[base + 5 * l + 2] = (void*)((uintptr_t)f[0] | 1u);
     }
     return TD_OK;
+}
+
+td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v, size_t base)
+{
+    return fill_ptrs_for(q, P.npatches, P.dt, P.quantity, v, base);
 }
 
 }  // namespace
@@ -1417,6 +1466,9 @@ extern "C" td_status td_context_destroy(td_context* c)
     }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     for (auto& kv : c->spectra) c->release(kv.second.ptr, kv.second.bytes);
+    c->release(c->b_table, c->b_table_bytes);
+    c->release(c->b_rows, c->b_rows_bytes);
+    c->release(c->b_small, c->b_small_bytes);
     for (auto& kv : c->tw32) (void)hipFree(kv.second);
     for (auto& kv : c->tw64) (void)hipFree(kv.second);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -1459,6 +1511,10 @@ extern "C" td_status td_plan_create_quantity(td_context* ctx, const td_hierarchy
     size_t elems = 0;
     td_status st = build_jobs(P.get(), &elems, true);
     P->ws_bytes = elems * elem_size(dt);
+    // the twiddles of every length, looked up once here: launches then
+    // take no context lock (a spectrum build on another thread holds it)
+    for (auto& g : P->groups)
+        if (st == TD_OK) st = twiddles(ctx, g.M, dt, &g.tw);
     if (st == TD_OK) st = validate_jobs(P.get());
     if (st == TD_OK) st = plan_upload(P.get());
     if (st != TD_OK) {
@@ -1673,24 +1729,37 @@ extern "C" td_status td_batch_destroy(td_batch* B)
 
 namespace {
 
+enum TicketState { T_QUEUED = 0, T_RUNNING = 1, T_DONE = 2, T_CANCELLED = 3, T_PLANNING = 4,
+                   T_FAILED = 5 };
+
 struct Ticket {
     uint64_t id = 0;
     td_plan* plan = nullptr;
-    std::vector<void*> ptrs;  // 5 per level: sigma, dsdx, dsdy, fx, fy
+    std::vector<void*> ptrs;  // 5 per patch: sigma, dsdx, dsdy, fx, fy
     double t_submit = 0, t_done = 0;
-    int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
+    int state = T_QUEUED;
     size_t need = 0;
+    hipEvent_t inputs = nullptr;  // recorded on the submitter's stream
+    td_status error = TD_OK;      // T_FAILED
+    std::string message;
+    // T_PLANNING: the hierarchy the server plans before admission
+    std::vector<td_patch> patches;
+    td_hierarchy hier{};
+    td_dtype dt = TD_F32;
+    int quantity = TD_FORCE;
 };
 
 struct Flight {
+    td_server* owner = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
     void** d_ptrs = nullptr;
     size_t cap = 0;
     Stager stager;
     std::vector<uint64_t> tickets;
     std::vector<std::pair<void*, size_t>> ws;  // workspace blocks bound to the tickets
     bool active = false;
+    bool finished = false;  // set by the host callback after the flight's work
+    double t_finish = 0;
 };
 
 }  // namespace
@@ -1700,25 +1769,45 @@ struct td_server {
     int max_inflight = 2, max_batch = 16;
     size_t queue_cap = 1 << 16;
     std::mutex mu;
-    std::condition_variable cv, cv_done;
-    std::deque<uint64_t> queue;
+    std::condition_variable cv, cv_done, cv_plan;
+    std::deque<uint64_t> queue;   // admitted to the queue, waiting for a flight
+    std::deque<uint64_t> planq;   // waiting for the planner
     std::map<uint64_t, Ticket> tickets;
-    std::vector<Flight> flights;
+    std::vector<Flight> flights;  // sized once: callbacks hold Flight pointers
     std::multimap<size_t, void*> pool;  // idle workspace blocks (held, counted as used)
     std::vector<std::pair<void*, size_t>> pool_all;
-    std::thread worker;
+    std::vector<hipEvent_t> ev_pool;
+    std::map<std::string, td_plan*> plans;  // plans the server made (planner thread only)
+    std::thread worker, planner;
     bool stop = false;
     uint64_t next_id = 1;
-    uint64_t completed = 0, cancelled = 0, refused = 0, deferred = 0, batches = 0, peak_queue = 0;
+    uint64_t completed = 0, cancelled = 0, refused = 0, deferred = 0, batches = 0, peak_queue = 0,
+             planned = 0, failed = 0;
     std::string worker_error;
 };
 
 namespace {
 
+// Host callback at the end of a flight's stream work: no HIP calls here,
+// only the flag and a wake-up of the worker.
+void flight_finished(void* arg)
+{
+    Flight* f = static_cast<Flight*>(arg);
+    td_server* S = f->owner;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        f->finished = true;
+        f->t_finish = now_s();
+    }
+    S->cv.notify_all();
+}
+
 // Workspace for one admitted solve: reuse an idle block of a close size, or
 // allocate against the context's HBM budget.  Returns nullptr when the
-// budget has no room (the request waits).
-void* pool_get(td_server* S, size_t need, size_t* got)
+// budget has no room (the request waits); idle blocks that would make room
+// are moved to `to_free`, which the caller frees outside the server lock
+// (hipFree waits for the device).
+void* pool_get(td_server* S, size_t need, size_t* got, std::vector<std::pair<void*, size_t>>& to_free)
 {
     auto it = S->pool.lower_bound(need);
     if (it != S->pool.end() && it->first <= 2 * need + (1 << 20)) {
@@ -1728,39 +1817,51 @@ void* pool_get(td_server* S, size_t need, size_t* got)
         return p;
     }
     void* p = nullptr;
-    if (S->ctx->alloc(need, &p) != TD_OK) {
-        // free idle blocks and retry once
-        for (auto& kv : S->pool) {
-            for (auto a = S->pool_all.begin(); a != S->pool_all.end(); ++a)
-                if (a->first == kv.second) {
-                    S->pool_all.erase(a);
-                    break;
-                }
-            S->ctx->release(kv.second, kv.first);
-        }
-        S->pool.clear();
-        if (S->ctx->alloc(need, &p) != TD_OK) return nullptr;
+    if (S->ctx->alloc(need, &p) == TD_OK) {
+        S->pool_all.push_back({p, need});
+        *got = need;
+        return p;
     }
-    S->pool_all.push_back({p, need});
-    *got = need;
-    return p;
+    // no room: give the idle blocks back (freed by the caller), so that a
+    // later attempt can allocate
+    for (auto& kv : S->pool) {
+        for (auto a = S->pool_all.begin(); a != S->pool_all.end(); ++a)
+            if (a->first == kv.second) {
+                S->pool_all.erase(a);
+                break;
+            }
+        to_free.push_back({kv.second, kv.first});
+    }
+    S->pool.clear();
+    return nullptr;
+}
+
+void fail_ticket(td_server* S, Ticket& T, td_status st, const std::string& msg)
+{
+    T.state = T_FAILED;
+    T.error = st;
+    T.message = msg;
+    T.t_done = now_s();
+    S->failed++;
 }
 
 void server_loop(td_server* S)
 {
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->mu);
+    bool mem_blocked = false;  // the queue head waits for memory a flight holds
     while (true) {
-        // retire finished flights
+        // retire finished flights (their host callback has run)
         bool progressed = false;
         for (auto& f : S->flights) {
-            if (!f.active || hipEventQuery(f.done) != hipSuccess) continue;
-            const double t = now_s();
+            if (!f.active || !f.finished) continue;
             for (uint64_t id : f.tickets) {
                 auto it = S->tickets.find(id);
                 if (it != S->tickets.end()) {
-                    it->second.state = 2;
-                    it->second.t_done = t;
+                    it->second.state = T_DONE;
+                    it->second.t_done = f.t_finish;
+                    if (it->second.inputs) S->ev_pool.push_back(it->second.inputs);
+                    it->second.inputs = nullptr;
                 }
                 S->completed++;
             }
@@ -1768,25 +1869,32 @@ void server_loop(td_server* S)
             f.ws.clear();
             f.tickets.clear();
             f.active = false;
+            f.finished = false;
             progressed = true;
         }
-        if (progressed) S->cv_done.notify_all();
-        // continuous batching: every free flight slot takes the requests
-        // that have arrived so far (FIFO, up to max_batch) that fit in HBM
+        if (progressed) {
+            mem_blocked = false;
+            S->cv_done.notify_all();
+        }
+        // continuous batching: a free flight slot takes the requests that
+        // have arrived so far (FIFO, up to max_batch) that fit in HBM
         Flight* slot = nullptr;
         for (auto& f : S->flights)
             if (!f.active) {
                 slot = &f;
                 break;
             }
-        if (slot && !S->queue.empty()) {
+        bool any_active = false;
+        for (auto& f : S->flights) any_active |= f.active;
+        if (slot && !S->queue.empty() && !mem_blocked) {
             std::vector<uint64_t> pick;
             std::vector<Member> mem;
+            std::vector<std::pair<void*, size_t>> blocks, to_free;
             size_t nslots = 0;
             bool waited = false;
             for (auto it = S->queue.begin(); it != S->queue.end() && (int)pick.size() < S->max_batch;) {
                 Ticket& T = S->tickets[*it];
-                if (T.state == 3) {
+                if (T.state == T_CANCELLED) {
                     it = S->queue.erase(it);
                     continue;
                 }
@@ -1795,57 +1903,251 @@ void server_loop(td_server* S)
                     continue;
                 }
                 size_t got = 0;
-                void* ws = pool_get(S, T.need, &got);
+                void* ws = pool_get(S, T.need, &got, to_free);
                 if (!ws) {
                     waited = true;
                     ++it;
                     continue;
                 }
-                slot->ws.push_back({ws, got});
+                blocks.push_back({ws, got});
                 mem.push_back({T.plan, (int)nslots, (char*)ws});
                 nslots += 5 * T.plan->npatches;
                 pick.push_back(*it);
                 it = S->queue.erase(it);
             }
             if (waited) S->deferred++;
-            if (!pick.empty()) {
-                std::vector<void*> v(nslots, nullptr);
-                for (size_t k = 0; k < pick.size(); ++k) {
-                    Ticket& T = S->tickets[pick[k]];
-                    T.state = 1;
-                    std::copy(T.ptrs.begin(), T.ptrs.end(), v.begin() + mem[k].slot_base);
-                }
-                td_status st = TD_OK;
-                if (slot->cap < nslots) {
-                    if (slot->d_ptrs) S->ctx->release(slot->d_ptrs, sizeof(void*) * slot->cap);
-                    slot->stager.destroy();
-                    const size_t cap = std::max<size_t>(nslots, 1024);
-                    st = S->ctx->alloc(sizeof(void*) * cap, (void**)&slot->d_ptrs);
-                    if (st == TD_OK) st = slot->stager.init(cap);
-                    slot->cap = st == TD_OK ? cap : 0;
-                }
-                slot->active = true;
-                slot->tickets = pick;
-                S->batches++;
-                const td_dtype dt = mem[0].plan->dt;
+            if (!to_free.empty()) {
                 lk.unlock();
-                if (st == TD_OK) st = slot->stager.push(slot->d_ptrs, v, slot->stream);
-                if (st == TD_OK) st = launch_members(S->ctx, dt, mem, slot->d_ptrs, FieldPtrs{}, slot->stream);
-                if (st == TD_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess)
-                    st = fail(TD_EDEVICE, "event record");
+                for (auto& b : to_free) S->ctx->release(b.first, b.second);
                 lk.lock();
-                if (st != TD_OK) S->worker_error = td_last_error();
+            }
+            if (pick.empty()) {
+                if (waited && !any_active && S->pool.empty()) {
+                    // nothing runs and nothing idles: the head cannot fit
+                    Ticket& T = S->tickets[S->queue.front()];
+                    fail_ticket(S, T, TD_ENOMEM, "request workspace does not fit in the HBM budget");
+                    S->queue.pop_front();
+                    S->cv_done.notify_all();
+                } else if (waited) {
+                    mem_blocked = any_active;  // wait for a flight to free memory
+                }
                 continue;
             }
+            // the flight's device pointer table: grown before anything is
+            // committed, so a failure leaves the slot as it was and the
+            // requests back at the head of the queue
+            td_status st = TD_OK;
+            if (slot->cap < nslots) {
+                // only this thread touches an idle slot; the allocations and
+                // frees (which wait for the device, hence for the flights'
+                // callbacks, which take the lock) run unlocked
+                lk.unlock();
+                const size_t cap = std::max<size_t>(nslots, 1024);
+                void** d = nullptr;
+                Stager stg;
+                st = S->ctx->alloc(sizeof(void*) * cap, (void**)&d);
+                if (st == TD_OK) {
+                    st = stg.init(cap);
+                    if (st != TD_OK) {
+                        stg.destroy();
+                        S->ctx->release(d, sizeof(void*) * cap);
+                    }
+                }
+                if (st == TD_OK) {
+                    // the old table's last copies are complete: the slot is idle
+                    if (slot->d_ptrs) S->ctx->release(slot->d_ptrs, sizeof(void*) * slot->cap);
+                    slot->stager.destroy();
+                    slot->d_ptrs = d;
+                    slot->stager = stg;
+                    slot->cap = cap;
+                }
+                lk.lock();
+            }
+            if (st != TD_OK) {
+                const std::string why = td_last_error();
+                for (auto it = pick.rbegin(); it != pick.rend(); ++it) S->queue.push_front(*it);
+                for (auto& b : blocks) S->pool.insert({b.second, b.first});
+                mem_blocked = any_active;
+                if (!any_active) {
+                    // cannot make progress: fail the head rather than spin
+                    Ticket& T = S->tickets[S->queue.front()];
+                    fail_ticket(S, T, st, "flight pointer table: " + why);
+                    S->queue.pop_front();
+                    S->cv_done.notify_all();
+                }
+                continue;
+            }
+            std::vector<void*> v(nslots, nullptr);
+            std::vector<hipEvent_t> waits;
+            for (size_t k = 0; k < pick.size(); ++k) {
+                Ticket& T = S->tickets[pick[k]];
+                T.state = T_RUNNING;
+                std::copy(T.ptrs.begin(), T.ptrs.end(), v.begin() + mem[k].slot_base);
+                if (T.inputs) waits.push_back(T.inputs);
+            }
+            slot->ws = blocks;
+            slot->active = true;
+            slot->finished = false;
+            slot->tickets = pick;
+            S->batches++;
+            const td_dtype dt = mem[0].plan->dt;
+            lk.unlock();
+            for (hipEvent_t e : waits)
+                if (st == TD_OK && hipStreamWaitEvent(slot->stream, e, 0) != hipSuccess)
+                    st = fail(TD_EDEVICE, "hipStreamWaitEvent");
+            if (st == TD_OK) st = slot->stager.push(slot->d_ptrs, v, slot->stream);
+            if (st == TD_OK) st = launch_members(S->ctx, dt, mem, slot->d_ptrs, FieldPtrs{}, slot->stream);
+            const bool cb = st == TD_OK &&
+                            hipLaunchHostFunc(slot->stream, flight_finished, slot) == hipSuccess;
+            lk.lock();
+            if (!cb) {
+                // nothing will call back: finish the flight here, after its
+                // stream has drained, with its tickets failed
+                if (st == TD_OK) st = fail(TD_EDEVICE, "hipLaunchHostFunc");
+                S->worker_error = td_last_error();
+                lk.unlock();
+                (void)hipStreamSynchronize(slot->stream);
+                lk.lock();
+                for (uint64_t id : slot->tickets) {
+                    Ticket& T = S->tickets[id];
+                    fail_ticket(S, T, st, S->worker_error);
+                }
+                for (auto& w : slot->ws) S->pool.insert({w.second, w.first});
+                slot->ws.clear();
+                slot->tickets.clear();
+                slot->active = false;
+                S->cv_done.notify_all();
+            }
+            continue;
         }
-        bool any_active = false;
-        for (auto& f : S->flights) any_active |= f.active;
-        if (S->stop && S->queue.empty() && !any_active) break;
-        if (any_active)
-            S->cv.wait_for(lk, std::chrono::microseconds(20));
-        else
-            S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+        if (S->stop && S->queue.empty() && S->planq.empty() && !any_active) break;
+        // sleep until a flight finishes, a request arrives or the server stops
+        S->cv.wait(lk, [&] {
+            for (auto& f : S->flights)
+                if (f.active && f.finished) return true;
+            bool free_slot = false;
+            for (auto& f : S->flights) free_slot |= !f.active;
+            if (free_slot && !S->queue.empty() && !mem_blocked) return true;
+            bool active = false;
+            for (auto& f : S->flights) active |= f.active;
+            return S->stop && S->planq.empty() && !active && (S->queue.empty() || !mem_blocked);
+        });
     }
+}
+
+std::string hierarchy_key(const td_hierarchy& h, td_dtype dt, int quantity)
+{
+    std::ostringstream o;
+    o.precision(17);
+    o << (int)dt << ' ' << quantity << ' ' << h.x0 << ' ' << h.y0 << ' ' << h.h0 << ' ' << h.ratio << ' '
+      << h.aspect;
+    for (int k = 0; k < h.npatches; ++k)
+        o << ' ' << h.patches[k].level << ',' << h.patches[k].n << ',' << h.patches[k].ox << ','
+          << h.patches[k].oy;
+    return o.str();
+}
+
+// Plans the hierarchies of tickets submitted without a plan, off the worker
+// thread: plan creation builds spectra and uploads job lists on the
+// context's own stream and waits only for that stream, so flights keep
+// running meanwhile.  Plans are kept per hierarchy for later requests.
+void planner_loop(td_server* S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        S->cv_plan.wait(lk, [&] { return S->stop || !S->planq.empty(); });
+        if (S->planq.empty()) {
+            if (S->stop) break;
+            continue;
+        }
+        const uint64_t id = S->planq.front();
+        S->planq.pop_front();
+        auto it = S->tickets.find(id);
+        if (it == S->tickets.end() || it->second.state != T_PLANNING) continue;
+        td_hierarchy h = it->second.hier;
+        std::vector<td_patch> pats = it->second.patches;
+        h.patches = pats.data();
+        const td_dtype dt = it->second.dt;
+        const int quantity = it->second.quantity;
+        lk.unlock();
+        const std::string key = hierarchy_key(h, dt, quantity);
+        td_plan* plan = nullptr;
+        td_status st = TD_OK;
+        std::string msg;
+        auto pi = S->plans.find(key);
+        if (pi != S->plans.end()) {
+            plan = pi->second;
+        } else {
+            st = td_plan_create_quantity(S->ctx, &h, dt, quantity, &plan);
+            if (st == TD_OK) S->plans[key] = plan;
+            else msg = td_last_error();
+        }
+        lk.lock();
+        it = S->tickets.find(id);
+        if (it == S->tickets.end() || it->second.state != T_PLANNING) continue;  // cancelled
+        Ticket& T = it->second;
+        if (st != TD_OK) {
+            fail_ticket(S, T, st, "planning: " + msg);
+            S->cv_done.notify_all();
+            continue;
+        }
+        S->planned++;
+        T.plan = plan;
+        T.need = (plan->ws_bytes + 255) & ~size_t(255);
+        if (S->ctx->budget && T.need > S->ctx->budget) {
+            fail_ticket(S, T, TD_ENOMEM, "request workspace exceeds the HBM budget");
+            S->cv_done.notify_all();
+            continue;
+        }
+        T.state = T_QUEUED;
+        S->queue.push_back(id);
+        S->cv.notify_all();
+    }
+}
+
+// Common tail of the two submit calls: the arrival event on the caller's
+// stream, the queue limit, the ticket.
+td_status submit_ticket(td_server* S, Ticket&& T, int32_t queue_if_full, void* stream,
+                        uint64_t* ticket)
+{
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->queue.size() + S->planq.size() >= S->queue_cap && !queue_if_full) {
+            S->refused++;
+            return fail(TD_EBUSY, "server queue full");
+        }
+        if (!S->ev_pool.empty()) {
+            ev = S->ev_pool.back();
+            S->ev_pool.pop_back();
+        }
+    }
+    DeviceGuard dg(S->ctx->device);
+    if (!ev) TD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    // the flight waits for the caller's work on its stream up to this point
+    // (the inputs it wrote, the earlier uses of the output buffers)
+    if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->ev_pool.push_back(ev);
+        return fail(TD_EDEVICE, "hipEventRecord on the submitting stream");
+    }
+    T.inputs = ev;
+    std::lock_guard<std::mutex> lk(S->mu);
+    T.id = S->next_id++;
+    T.t_submit = now_s();
+    *ticket = T.id;
+    const bool planning = T.state == T_PLANNING;
+    S->tickets[T.id] = std::move(T);
+    if (planning) {
+        S->planq.push_back(*ticket);
+        S->cv_plan.notify_all();
+    } else {
+        S->queue.push_back(*ticket);
+        S->cv.notify_all();
+    }
+    S->peak_queue = std::max<uint64_t>(S->peak_queue, S->queue.size() + S->planq.size());
+    return TD_OK;
 }
 
 }  // namespace
@@ -1862,11 +2164,17 @@ extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int
     S->max_batch = max_batch;
     S->flights.resize(max_inflight);
     for (auto& f : S->flights) {
-        TD_HIP(hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking));
-        TD_HIP(hipEventCreateWithFlags(&f.done, hipEventDisableTiming));
+        f.owner = S.get();
+        hipError_t e = hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (auto& g : S->flights)
+                if (g.stream) (void)hipStreamDestroy(g.stream);
+            return fail(TD_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
     }
     td_server* raw = S.release();
     raw->worker = std::thread(server_loop, raw);
+    raw->planner = std::thread(planner_loop, raw);
     *out = raw;
     return TD_OK;
 }
@@ -1880,7 +2188,7 @@ extern "C" td_status td_server_set_queue_limit(td_server* S, int32_t max_queued)
 }
 
 extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32_t queue_if_full,
-                                      uint64_t* ticket)
+                                      void* hip_stream, uint64_t* ticket)
 {
     if (!S || !req || !req->plan || !ticket) return fail(TD_EINVAL, "NULL argument");
     if (req->plan->ctx != S->ctx) return fail(TD_EINVAL, "plan belongs to another context");
@@ -1890,34 +2198,55 @@ extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32
     T.ptrs.assign(5 * P->npatches, nullptr);
     TD_TRY(fill_ptrs(*req, *P, T.ptrs, 0));
     T.need = (P->ws_bytes + 255) & ~size_t(255);
-    std::lock_guard<std::mutex> lk(S->mu);
     if (S->ctx->budget && T.need > S->ctx->budget) {
+        std::lock_guard<std::mutex> lk(S->mu);
         S->refused++;
         return fail(TD_ENOMEM, "request workspace exceeds the HBM budget");
     }
-    if (S->queue.size() >= S->queue_cap && !queue_if_full) {
-        S->refused++;
-        return fail(TD_EBUSY, "server queue full");
-    }
-    T.id = S->next_id++;
-    T.t_submit = now_s();
-    *ticket = T.id;
-    S->tickets[T.id] = std::move(T);
-    S->queue.push_back(*ticket);
-    S->peak_queue = std::max<uint64_t>(S->peak_queue, S->queue.size());
-    S->cv.notify_all();
-    return TD_OK;
+    return submit_ticket(S, std::move(T), queue_if_full, hip_stream, ticket);
+}
+
+extern "C" td_status td_server_submit_hierarchy(td_server* S, const td_hierarchy* h, td_dtype dtype,
+                                                int32_t quantity, const td_request* req,
+                                                int32_t queue_if_full, void* hip_stream,
+                                                uint64_t* ticket)
+{
+    if (!S || !h || !req || !ticket) return fail(TD_EINVAL, "NULL argument");
+    if (req->plan) return fail(TD_EINVAL, "req->plan must be NULL: the server plans the hierarchy");
+    if (dtype != TD_F32 && dtype != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
+    if (quantity != TD_FORCE && quantity != TD_POTENTIAL)
+        return fail(TD_EINVAL, "quantity must be TD_FORCE or TD_POTENTIAL");
+    TD_TRY(td_hierarchy_check(h));
+    Ticket T;
+    T.state = T_PLANNING;
+    T.dt = dtype;
+    T.quantity = quantity;
+    T.patches.assign(h->patches, h->patches + h->npatches);
+    T.hier = *h;
+    T.hier.patches = nullptr;
+    T.ptrs.assign(5 * h->npatches, nullptr);
+    TD_TRY(fill_ptrs_for(*req, h->npatches, dtype, quantity, T.ptrs, 0));
+    return submit_ticket(S, std::move(T), queue_if_full, hip_stream, ticket);
 }
 
 extern "C" td_status td_server_poll(td_server* S, uint64_t ticket, int32_t* done, double* lat)
 {
     if (!S || !done) return fail(TD_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
-    if (!S->worker_error.empty()) return fail(TD_EDEVICE, "server: " + S->worker_error);
+    if (!S->worker_error.empty() && S->tickets.count(ticket) &&
+        S->tickets[ticket].state == T_RUNNING)
+        return fail(TD_EDEVICE, "server: " + S->worker_error);
     auto it = S->tickets.find(ticket);
-    if (it == S->tickets.end()) return fail(TD_EINVAL, "unknown ticket");
-    *done = it->second.state == 2 ? 1 : 0;
-    if (lat) *lat = it->second.state == 2 ? it->second.t_done - it->second.t_submit : 0.0;
+    if (it == S->tickets.end()) return fail(TD_EINVAL, "unknown ticket (or already reported done)");
+    if (it->second.state == T_FAILED) {
+        const td_status st = it->second.error;
+        const std::string msg = it->second.message;
+        S->tickets.erase(it);
+        return fail(st, "request failed: " + msg);
+    }
+    *done = it->second.state == T_DONE ? 1 : 0;
+    if (lat) *lat = *done ? it->second.t_done - it->second.t_submit : 0.0;
+    if (*done) S->tickets.erase(it);  // reported once; the map does not grow without bound
     return TD_OK;
 }
 
@@ -1927,8 +2256,9 @@ extern "C" td_status td_server_drain(td_server* S)
     std::unique_lock<std::mutex> lk(S->mu);
     S->cv.notify_all();
     S->cv_done.wait(lk, [&] {
-        if (!S->worker_error.empty()) return true;
-        if (!S->queue.empty()) return false;
+        if (!S->queue.empty() || !S->planq.empty()) return false;
+        for (auto& kv : S->tickets)
+            if (kv.second.state == T_PLANNING) return false;
         for (auto& f : S->flights)
             if (f.active) return false;
         return true;
@@ -1942,11 +2272,13 @@ extern "C" td_status td_server_cancel(td_server* S, uint64_t ticket)
     if (!S) return fail(TD_EINVAL, "NULL server");
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->tickets.find(ticket);
-    if (it == S->tickets.end() || it->second.state != 0)
+    if (it == S->tickets.end() || (it->second.state != T_QUEUED && it->second.state != T_PLANNING))
         return fail(TD_EINVAL, "ticket unknown or already started");
-    it->second.state = 3;
+    if (it->second.inputs) S->ev_pool.push_back(it->second.inputs);
     S->cancelled++;
     S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), ticket), S->queue.end());
+    S->planq.erase(std::remove(S->planq.begin(), S->planq.end(), ticket), S->planq.end());
+    S->tickets.erase(it);
     S->cv_done.notify_all();
     return TD_OK;
 }
@@ -1967,6 +2299,16 @@ extern "C" td_status td_server_stats(const td_server* S, uint64_t* completed, ui
     return TD_OK;
 }
 
+extern "C" td_status td_server_stats2(const td_server* S, uint64_t* planned, uint64_t* failed)
+{
+    if (!S) return fail(TD_EINVAL, "NULL server");
+    auto* s = const_cast<td_server*>(S);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (planned) *planned = s->planned;
+    if (failed) *failed = s->failed;
+    return TD_OK;
+}
+
 extern "C" td_status td_server_destroy(td_server* S)
 {
     if (!S) return fail(TD_EINVAL, "NULL server");
@@ -1975,16 +2317,22 @@ extern "C" td_status td_server_destroy(td_server* S)
         S->stop = true;
     }
     S->cv.notify_all();
+    S->cv_plan.notify_all();
+    if (S->planner.joinable()) S->planner.join();
+    S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
     DeviceGuard dg(S->ctx->device);
     for (auto& f : S->flights) {
         if (f.stream) (void)hipStreamSynchronize(f.stream);
         if (f.d_ptrs) S->ctx->release(f.d_ptrs, sizeof(void*) * f.cap);
         f.stager.destroy();
-        if (f.done) (void)hipEventDestroy(f.done);
         if (f.stream) (void)hipStreamDestroy(f.stream);
     }
+    for (auto& kv : S->tickets)
+        if (kv.second.inputs) S->ev_pool.push_back(kv.second.inputs);
+    for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
     for (auto& a : S->pool_all) S->ctx->release(a.first, a.second);
+    for (auto& kv : S->plans) td_plan_destroy(kv.second);
     delete S;
     return TD_OK;
 }

@@ -70,3 +70,28 @@ def sampled(hier, gx, gy, targets):
 def rel_l2(ax, ay, bx, by):
     return math.sqrt((((ax - bx) ** 2).sum() + ((ay - by) ** 2).sum()) /
                      ((bx ** 2).sum() + (by ** 2).sum()))
+
+
+def level_rel_l2(hier, targets, gx, gy, ox, oy):
+    """rel-L2 of sampled values per level of the hierarchy ({level: err}),
+    each over the targets on that level's patches; gx, gy, ox, oy are flat
+    arrays aligned with ``targets``."""
+    tp = np.asarray(targets[0])
+    lev = np.array([hier.patches[p].level for p in tp])
+    out = {}
+    for l in sorted(set(lev.tolist())):
+        s = lev == l
+        out[l] = rel_l2(gx[s], gy[s], ox[s], oy[s])
+    return out
+
+
+def report(name, hier, targets, gx, gy, ox, oy):
+    """Overall rel-L2, per-level rel-L2 and the largest absolute error of a
+    sampled comparison, printed for the log and returned."""
+    err = rel_l2(gx, gy, ox, oy)
+    per = level_rel_l2(hier, targets, gx, gy, ox, oy)
+    amax = float(max(np.abs(gx - ox).max(), np.abs(gy - oy).max()))
+    print(f"{name}: rel-L2 {err:.3e}, per level "
+          + ", ".join(f"{l}: {e:.3e}" for l, e in per.items())
+          + f", max abs {amax:.3e} ({len(gx)} targets)", flush=True)
+    return err, per, amax

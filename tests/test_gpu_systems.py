@@ -344,3 +344,102 @@ def test_server_queue_limit_refuses(ctx):
     assert busy > 0 and ok >= 2
     assert st["completed"] == ok and st["refused"] == busy
     srv.close()
+
+
+def test_server_plans_unseen_hierarchies(ctx):
+    """Requests submitted with a hierarchy and no plan: the server plans each
+    distinct hierarchy once (off its launch thread) while other requests run,
+    and every result equals a single solve of its own plan bit for bit."""
+    import torch
+    import paper_1603_03142_amd as td
+    hiers = _mix(seed=41, count=5)
+    fields = [_dev_fields(h, 700 + k, "f32")[0] for k, h in enumerate(hiers)]
+    known = ctx.plan(hiers[0], "f32")
+    srv = td.Server(ctx, max_inflight=2, max_batch=4)
+    tickets = []
+    for rep in range(2):
+        for k, (h, f) in enumerate(zip(hiers, fields)):
+            if k == 0:
+                tickets.append((k, *srv.submit(known, *f)))
+            else:
+                tickets.append((k, *srv.submit_hierarchy(h, "f32", *f)))
+    srv.drain()
+    st = srv.stats()
+    assert st["planned"] == 2 * (len(hiers) - 1) and st["failed"] == 0
+    assert st["completed"] == len(tickets)
+    for k, tk, fx, fy in tickets:
+        done, lat = srv.poll(tk)
+        assert done and lat > 0
+        p = ctx.plan(hiers[k], "f32")
+        wx, wy = p.solve(*fields[k])
+        torch.cuda.synchronize()
+        for a, b in zip(fx + fy, wx + wy):
+            assert torch.equal(a, b), k
+        p.close()
+    # a polled ticket is forgotten
+    with pytest.raises(td.TdError) as ei:
+        srv.poll(tickets[0][1])
+    assert ei.value.status == 1
+    srv.close()
+
+
+def test_server_waits_for_the_submitting_stream(ctx):
+    """Inputs written on the caller's stream right before submission (behind
+    a long kernel there) are the ones the flight reads."""
+    import torch
+    import paper_1603_03142_amd as td
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / 128, 2, [(128, 0, 0), (128, 64, 64)])
+    plan = ctx.plan(hier, "f32")
+    (s, x, y), _ = _dev_fields(hier, 77, "f32")
+    want = plan.solve(s, x, y)
+    torch.cuda.synchronize()
+    srv = td.Server(ctx, max_inflight=2, max_batch=2)
+    side = torch.cuda.Stream()
+    s2 = [torch.zeros_like(a) for a in s]
+    with torch.cuda.stream(side):
+        m = torch.randn(2048, 2048, device="cuda")
+        for _ in range(20):
+            m = m @ m
+            m = m / m.norm()
+        for a, b in zip(s2, s):
+            a.copy_(b)
+    t, fx, fy = srv.submit(plan, s2, x, y, stream=side)
+    srv.drain()
+    assert srv.poll(t)[0]
+    torch.cuda.synchronize()
+    for a, b in zip(fx + fy, want[0] + want[1]):
+        assert torch.equal(a, b)
+    srv.close()
+
+
+def test_server_budget_admits_workspace_not_pointer_table():
+    """A budget that holds a request's workspace but not the flight's device
+    pointer table: the request fails with TD_ENOMEM, is never reported done,
+    and the server stays usable."""
+    import torch
+    import paper_1603_03142_amd as td
+    hier = synth.nested_hierarchy(-1.0, -1.0, 2.0 / 64, 2, [(64, 0, 0), (64, 32, 32)])
+    probe = td.Context(0)
+    p = probe.plan(hier, "f32")
+    used, _ = probe.usage()
+    p.close()
+    probe.close()
+    ws = td.check_plan(hier, "f32")
+    # the plan's own allocations, its workspace (256-byte rounded), and less
+    # than the 1024-entry pointer table of a flight
+    budget = used + ((ws + 255) & ~255) + 4096
+    c = td.Context(0, hbm_budget=budget)
+    plan = c.plan(hier, "f32")
+    (s, x, y), _ = _dev_fields(hier, 3, "f32")
+    srv = td.Server(c, max_inflight=1, max_batch=1)
+    tk = srv.submit(plan, s, x, y)[0]
+    srv.drain()
+    with pytest.raises(td.TdError) as ei:
+        srv.poll(tk)
+    assert ei.value.status == 4  # TD_ENOMEM
+    st = srv.stats()
+    assert st["completed"] == 0 and st["failed"] == 1
+    srv.close()
+    plan.close()
+    c.close()
+    torch.cuda.synchronize()
