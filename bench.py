@@ -350,14 +350,24 @@ def serve_block(args, td, torch, synth):
     arrivals = [t for t, _, _ in reqs]
     pick = rng.integers(0, ntypes, len(arrivals))
     unseen = rng.random(len(arrivals)) < args.unseen
-    # unseen arrivals: their own hierarchy, fields prepared before the run
-    # (input generation is the caller's work, not the server's)
+    # unseen arrivals keep their own hierarchy (no plan exists for it); their
+    # input and output buffers depend only on the patch sides, so they reuse
+    # those of a planned type of the same shape (every level of a request
+    # has N^2 cells), or of a shape prepared here, before the run
+    shape_bufs = {}
+    for plan, f, outs in types:
+        shape_bufs.setdefault(tuple(plan.sizes), (f, outs))
     fresh = {}
     for k in np.nonzero(unseen)[0]:
-        _, hier, (order, alpha, fseed) = reqs[k]
-        fn = synth.request_sigma(order, alpha, fseed, hier.h0)
-        f = dev_fields(torch, tdt, host_fields(synth, hier, fn, args.slopes), args.slopes)
-        fresh[int(k)] = (hier, f)
+        _, hier, _ = reqs[k]
+        shp = tuple(p.n for p in hier.patches)
+        if shp not in shape_bufs:
+            fn = synth.disk_dn(3, 0.8)
+            f = dev_fields(torch, tdt, host_fields(synth, hier, fn, args.slopes), args.slopes)
+            outs = [tuple([torch.empty((n, n), dtype=tdt, device="cuda") for n in shp]
+                          for _ in range(2)) for _ in range(2)]
+            shape_bufs[shp] = (f, outs)
+        fresh[int(k)] = (hier, shp)
     tickets = []
     refused = 0
     t0 = time.perf_counter()
@@ -367,8 +377,9 @@ def serve_block(args, td, torch, synth):
             pass
         try:
             if k in fresh:
-                hier, f = fresh[k]
-                tk, _, _ = srv.submit_hierarchy(hier, args.dtype, *f[:3],
+                hier, shp = fresh[k]
+                f, outs = shape_bufs[shp]
+                tk, _, _ = srv.submit_hierarchy(hier, args.dtype, *f[:3], *outs[k % 2],
                                                 queue_if_full=False, slopes=f[3])
                 tickets.append((tk, hier.cells, True))
             else:

@@ -1777,8 +1777,9 @@ struct td_server {
     std::multimap<size_t, void*> pool;  // idle workspace blocks (held, counted as used)
     std::vector<std::pair<void*, size_t>> pool_all;
     std::vector<hipEvent_t> ev_pool;
-    std::map<std::string, td_plan*> plans;  // plans the server made (planner thread only)
-    std::thread worker, planner;
+    std::map<std::string, td_plan*> plans;  // plans the server made, by hierarchy
+    std::thread worker;
+    std::vector<std::thread> planners;
     bool stop = false;
     uint64_t next_id = 1;
     uint64_t completed = 0, cancelled = 0, refused = 0, deferred = 0, batches = 0, peak_queue = 0,
@@ -2075,13 +2076,23 @@ void planner_loop(td_server* S)
         td_plan* plan = nullptr;
         td_status st = TD_OK;
         std::string msg;
-        auto pi = S->plans.find(key);
-        if (pi != S->plans.end()) {
-            plan = pi->second;
-        } else {
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            auto pi = S->plans.find(key);
+            if (pi != S->plans.end()) plan = pi->second;
+        }
+        if (!plan) {
             st = td_plan_create_quantity(S->ctx, &h, dt, quantity, &plan);
-            if (st == TD_OK) S->plans[key] = plan;
-            else msg = td_last_error();
+            if (st == TD_OK) {
+                std::lock_guard<std::mutex> g(S->mu);
+                auto ins = S->plans.emplace(key, plan);
+                if (!ins.second) {  // another planner made it meanwhile
+                    td_plan_destroy(plan);
+                    plan = ins.first->second;
+                }
+            } else {
+                msg = td_last_error();
+            }
         }
         lk.lock();
         it = S->tickets.find(id);
@@ -2174,7 +2185,7 @@ extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int
     }
     td_server* raw = S.release();
     raw->worker = std::thread(server_loop, raw);
-    raw->planner = std::thread(planner_loop, raw);
+    for (int k = 0; k < 2; ++k) raw->planners.emplace_back(planner_loop, raw);
     *out = raw;
     return TD_OK;
 }
@@ -2318,7 +2329,8 @@ extern "C" td_status td_server_destroy(td_server* S)
     }
     S->cv.notify_all();
     S->cv_plan.notify_all();
-    if (S->planner.joinable()) S->planner.join();
+    for (auto& t : S->planners)
+        if (t.joinable()) t.join();
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
     DeviceGuard dg(S->ctx->device);

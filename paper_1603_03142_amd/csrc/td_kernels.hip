@@ -314,7 +314,7 @@ using gptr = const __attribute__((address_space(1))) T*;
 template <typename T>
 using vec2 = T __attribute__((ext_vector_type(2)));
 template <typename T>
-__device__ __forceinline__ cpx<T> ldg(gptr<cpx<T>> p, size_t i)
+__device__ __forceinline__ cpx<T> ldg(gptr<cpx<T>> p, ptrdiff_t i)
 {
     const vec2<T> v = ((gptr<vec2<T>>)p)[i];
     return cpx<T>{v.x, v.y};
@@ -328,10 +328,9 @@ __device__ __forceinline__ cpx<T> ldg(gptr<cpx<T>> p, size_t i)
 //  otherwise a polyphase phase stored complex for all ky; bits 0 / 1 select
 //    its x- / y-mirror image: S'(kx, ky) = s_x conj S(kx, -ky),
 //    s_y S(kx, -ky), or s_x s_y conj S(kx, ky).
-// Branch-free apart from the layout test, which is uniform per slot.
-// kern_load issues the reads (the real layout fills only .re) and
-// kern_apply forms the values, so that the reads can be in flight across
-// other work in between; kern_column does both at once.
+// kern_load issues the reads (the real layout fills only .re), so that they
+// can be in flight across other work; kern_mac (below) forms the values and
+// multiplies.
 template <typename T, int M>
 __device__ __forceinline__ void kern_load(cpx<T> (&z)[8], const void* Kv, int X, int kx, int flip,
                                           int lane)
@@ -347,72 +346,17 @@ __device__ __forceinline__ void kern_load(cpx<T> (&z)[8], const void* Kv, int X,
     } else {
         gptr<cpx<T>> K = (gptr<cpx<T>>)Kv + ((size_t)X * H + kx) * M;
         const int mir = flip & 3;
-        const bool rev = mir == 1 || mir == 2;
+        if (mir == 1 || mir == 2) {
+            // the mirror reads frequency -ky: (M - ky) mod M, i.e. M - lane
+            // - q M/8 for q > 0 and (M - lane) mod M for q = 0
+            gptr<cpx<T>> Kr = K + (M - lane);
+            z[0] = ldg<T>(K, (M - lane) & (M - 1));
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int ky = lane + q * TPS;
-            z[q] = ldg<T>(K, rev ? ((M - ky) & (M - 1)) : ky);
-        }
-    }
-}
-
-template <typename T, int M>
-__device__ __forceinline__ void kern_apply(cpx<T> (&kv)[8], const cpx<T> (&z)[8], int X, int flip,
-                                           int lane)
-{
-    const int fam = (flip >> 3) & 1;
-    if (flip & 4) {
-        const T sy = (T)sign_y(X, fam);
-        const bool imag = sign_x(X, fam) * sign_y(X, fam) < 0;
+            for (int q = 1; q < 8; ++q) z[q] = ldg<T>(Kr, -(ptrdiff_t)(q * TPS));
+        } else {
+            gptr<cpx<T>> Kf = K + lane;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            T v = z[q].re;
-            if (q > 4 || (q == 4 && lane > 0)) v *= sy;  // ky = M/2 is stored directly
-            kv[q] = imag ? cpx<T>{0, v} : cpx<T>{v, 0};
-        }
-    } else {
-        const int mir = flip & 3;
-        const T s = (T)(((mir & 1) ? sign_x(X, fam) : 1) * ((mir & 2) ? sign_y(X, fam) : 1));
-        const T si = (mir & 1) ? -s : s;  // x-mirrors conjugate
-#pragma unroll
-        for (int q = 0; q < 8; ++q) kv[q] = cpx<T>{s * z[q].re, si * z[q].im};
-    }
-}
-
-// The same in one step (no reads left in flight).
-template <typename T, int M>
-__device__ __forceinline__ void kern_column(cpx<T>* kv, const void* Kv, int X, int kx, int flip,
-                                            int lane)
-{
-    constexpr int TPS = M / 8, H = M / 2 + 1;
-    const int fam = (flip >> 3) & 1;
-    if (flip & 4) {
-        gptr<T> R = (gptr<T>)Kv + ((size_t)X * H + kx) * H;
-        const T sy = (T)sign_y(X, fam);
-        const bool imag = sign_x(X, fam) * sign_y(X, fam) < 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            T v;
-            if (q < 4) {
-                v = R[lane + q * TPS];                        // ky < M/2
-            } else {
-                const int ky = lane + q * TPS;                // ky >= M/2
-                v = R[M - ky];
-                if (q > 4 || lane > 0) v *= sy;               // ky = M/2 is stored directly
-            }
-            kv[q] = imag ? cpx<T>{0, v} : cpx<T>{v, 0};
-        }
-    } else {
-        gptr<cpx<T>> K = (gptr<cpx<T>>)Kv + ((size_t)X * H + kx) * M;
-        const int mir = flip & 3;
-        const bool rev = mir == 1 || mir == 2;
-        const T s = (T)(((mir & 1) ? sign_x(X, fam) : 1) * ((mir & 2) ? sign_y(X, fam) : 1));
-        const T si = (mir & 1) ? -s : s;  // x-mirrors conjugate
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int ky = lane + q * TPS;
-            const cpx<T> z = ldg<T>(K, rev ? ((M - ky) & (M - 1)) : ky);
-            kv[q] = cpx<T>{s * z.re, si * z.im};
+            for (int q = 0; q < 8; ++q) z[q] = ldg<T>(Kf, q * TPS);
         }
     }
 }
@@ -425,6 +369,83 @@ __device__ __forceinline__ int slot_uniform(int i)
 {
     if constexpr (M / 8 >= 64) return __builtin_amdgcn_readfirstlane(i);
     return i;
+}
+
+// A column-pass descriptor (ColIn / ColOut) at a slot's item index.  When a
+// slot is a whole wavefront the index is uniform and the tables are
+// read-only during the launch: a constant-address-space (scalar) load, so
+// every branch on the descriptor's fields is uniform.
+template <int M, typename D>
+__device__ __forceinline__ D load_desc(const D* tab, int i)
+{
+    if constexpr (M / 8 >= 64) return load_const(tab, i);
+    else return tab[i];
+}
+
+// acc += (S z.re + i S C z.im) * v over the thread's 8 frequencies, with the
+// signs S, C = +-1 fixed at compile time (they become operand modifiers of
+// the fused multiply-adds).
+template <typename T, int S, int C>
+__device__ __forceinline__ void mac_signed(cpx<T> (&acc)[8], const cpx<T> (&z)[8], const cpx<T> (&v)[8])
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        acc[q].re = fma((T)S * z[q].re, v[q].re, acc[q].re);
+        acc[q].re = fma((T)(-S * C) * z[q].im, v[q].im, acc[q].re);
+        acc[q].im = fma((T)S * z[q].re, v[q].im, acc[q].im);
+        acc[q].im = fma((T)(S * C) * z[q].im, v[q].re, acc[q].im);
+    }
+}
+
+// acc += K v, K the kernel X of a stored spectrum column z as kern_load
+// read it (raw values), seen through the layout and mirror bits of `flip`
+// as described above; flip and X uniform over the slot.  No per-value
+// sign or select work: the sign pattern picks one of four products.
+template <typename T, int M>
+__device__ __forceinline__ void kern_mac(cpx<T> (&acc)[8], const cpx<T> (&z)[8], const cpx<T> (&v)[8],
+                                         int X, int flip, int lane)
+{
+    const int fam = (flip >> 3) & 1;
+    if (flip & 4) {
+        // same-level kernel: one real R per frequency; the spectrum is R or
+        // i R, and frequencies above M/2 (q > 4, and q = 4 but for lane 0,
+        // ky = M/2, which is stored directly) carry the y-parity s_y
+        const bool imag = sign_x(X, fam) * sign_y(X, fam) < 0;
+        T r[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = z[q].re;
+        if (sign_y(X, fam) < 0) {
+#pragma unroll
+            for (int q = 5; q < 8; ++q) r[q] = -r[q];
+            r[4] = lane > 0 ? -r[4] : r[4];
+        }
+        if (imag) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                acc[q].re = fma(-r[q], v[q].im, acc[q].re);
+                acc[q].im = fma(r[q], v[q].re, acc[q].im);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                acc[q].re = fma(r[q], v[q].re, acc[q].re);
+                acc[q].im = fma(r[q], v[q].im, acc[q].im);
+            }
+        }
+    } else {
+        // polyphase phase: mirror bits 0 / 1 give the sign s (x- and
+        // y-parities) and x-mirrors conjugate
+        const int mir = flip & 3;
+        const int s = ((mir & 1) ? sign_x(X, fam) : 1) * ((mir & 2) ? sign_y(X, fam) : 1);
+        const bool cj = mir & 1;
+        if (s > 0) {
+            if (cj) mac_signed<T, 1, -1>(acc, z, v);
+            else mac_signed<T, 1, 1>(acc, z, v);
+        } else {
+            if (cj) mac_signed<T, -1, -1>(acc, z, v);
+            else mac_signed<T, -1, 1>(acc, z, v);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -512,7 +533,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
     const void* aux;
     char* ws;
     const ColJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
-    const ColTables tabs = *reinterpret_cast<const ColTables*>(aux);
+    const ColTables tabs = load_const(reinterpret_cast<const ColTables*>(aux), 0);
     const int slot = threadIdx.x / TPS, lane_c = threadIdx.x % TPS;
     const int lane = lane_c;
     const int c = slot / G, g = slot % G;
@@ -537,7 +558,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         {
             const int i = slot_uniform<M>(g);
             okn = col_ok && i < J.nin;
-            if (okn) In = tabs.ins[J.in0 + i];
+            if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
             load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
         }
         for (int r0 = 0; r0 < J.nin; r0 += G) {
@@ -552,7 +573,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                 const int i = slot_uniform<M>(r0 + G + g);
                 okn = col_ok && i < J.nin;
                 In = ColIn{0, nullptr, 0, 0, 0, 0};
-                if (okn) In = tabs.ins[J.in0 + i];
+                if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
                 load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
             }
             // FP32 with M >= 512: the input's kernel columns are read
@@ -571,15 +592,12 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             // are ordered within their wavefront only (M/8 <= 64)
             if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
             if (ok) {
-                cpx<T> kv[8];
-                if constexpr (EARLY) kern_apply<T, M>(kv, z0, kern_of(0, I.f), I.flip, lane);
-                else kern_column<T, M>(kv, I.kern, kern_of(0, I.f), kx, I.flip, lane);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) ax[q] = ax[q] + cmul(kv[q], v[q]);
-                if constexpr (EARLY) kern_apply<T, M>(kv, z1, kern_of(1, I.f), I.flip, lane);
-                else kern_column<T, M>(kv, I.kern, kern_of(1, I.f), kx, I.flip, lane);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) ay[q] = ay[q] + cmul(kv[q], v[q]);
+                if constexpr (!EARLY) {
+                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                }
+                kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
+                kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
             }
         }
         // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
@@ -620,13 +638,14 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
 #pragma unroll
         for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
         if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
-        if (col_ok && g == 0) store_column<T, M>(w, ws, tabs.outs[J.out0], kx, lane);
-        if (col_ok && G > 1 && g == 1) store_column<T, M>(w, ws, tabs.outs[J.out0 + 1], kx, lane);
+        if (col_ok && g == 0) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0), kx, lane);
+        if (col_ok && G > 1 && g == 1)
+            store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
         if (G == 1) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) w[q] = sy[q];
             fft_regs<T, M, true, false, true>(w, A, tw);
-            if (col_ok) store_column<T, M>(w, ws, tabs.outs[J.out0 + 1], kx, lane);
+            if (col_ok) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
         }
         return;
     }
@@ -638,7 +657,7 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         const int i = slot_uniform<M>(r0 + g);
         const bool ok = col_ok && i < 3;
         ColIn I{0, nullptr, 0, 0, 0, 0};
-        if (ok) I = tabs.ins[J.in0 + i];
+        if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
         cpx<T> v[8];
         load_column<T, M>(v, ws, I, kx, ok, lane);
         fft_regs<T, M, false, true>(v, A, tw);
@@ -664,13 +683,12 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
         for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
         ColOut O{0, nullptr, 0, 0, 0, 0};
         if (ok) {
-            O = tabs.outs[J.out0 + o];
+            O = load_desc<M>(tabs.outs, J.out0 + o);
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                cpx<T> kv[8];
-                kern_column<T, M>(kv, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) acc[q] = acc[q] + cmul(kv[q], vin[f][q]);
+                cpx<T> z[8];
+                kern_load<T, M>(z, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
+                kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
             }
         }
         if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);

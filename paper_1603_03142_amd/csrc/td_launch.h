@@ -13,6 +13,23 @@ namespace td {
 // or row contributions).  Passed by value as a kernel argument.
 #define TD_MAX_SEGS 40
 
+// Copy a read-only descriptor (tab[i]) through a constant-address-space
+// pointer, dword by dword: with an index that is uniform over the
+// wavefront the loads are scalar and the fields land in scalar registers.
+template <typename D>
+__device__ __forceinline__ D load_const(const D* tab, int i)
+{
+    static_assert(sizeof(D) % 4 == 0, "descriptor size");
+    typedef const __attribute__((address_space(4))) uint32_t* cwords;
+    cwords w = (cwords)(tab + i);
+    uint32_t buf[sizeof(D) / 4];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(D) / 4); ++k) buf[k] = w[k];
+    D d;
+    __builtin_memcpy(&d, buf, sizeof(D));
+    return d;
+}
+
 template <typename Job>
 struct SegTable {
     int32_t nseg;
@@ -34,7 +51,10 @@ struct SegTable {
         *slot = slot_base[lo];
         *aux_out = aux[lo];
         *ws_out = ws[lo];
-        return jobs[lo][block - start[lo]];
+        // job tables are read-only while a launch runs and the index is the
+        // same for the whole workgroup: a constant-address-space load, so
+        // the descriptor lands in scalar registers
+        return load_const(jobs[lo], block - start[lo]);
     }
 };
 
