@@ -47,6 +47,20 @@ td_status fail(td_status s, const std::string& msg)
             return fail(TD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));    \
     } while (0)
 
+// The HIP runtime keeps a per-thread "last error" that the caller's own
+// code (PyTorch checks it after every kernel launch) reads.  Entry points
+// leave it as they found it: an error the library's own calls raised and
+// handled (a query of an unfinished event, an allocation refused and
+// retried) is cleared on the way out unless one was already pending.
+struct ErrScope {
+    bool clean;
+    ErrScope() : clean(hipPeekAtLastError() == hipSuccess) {}
+    ~ErrScope()
+    {
+        if (clean) (void)hipGetLastError();
+    }
+};
+
 #define TD_TRY(expr)                    \
     do {                                \
         td_status _s = (expr);          \
@@ -489,6 +503,7 @@ void level_window(const td_hierarchy* h, int level, int* ox, int* oy, int* nx, i
 
 extern "C" td_status td_hierarchy_check(const td_hierarchy* h)
 {
+    ErrScope es_;
     int L = 0;
     TD_TRY(patch_levels(h, &L));
     if (!std::isfinite(h->aspect) || h->aspect < 0 ||
@@ -545,6 +560,7 @@ extern "C" td_status td_hierarchy_check(const td_hierarchy* h)
 extern "C" td_status td_hierarchy_snap(td_hierarchy* h, td_patch* patches, const double* cx,
                                        const double* cy)
 {
+    ErrScope es_;
     if (!h || !patches || (h->npatches > 1 && (!cx || !cy))) return fail(TD_EINVAL, "NULL argument");
     if (h->npatches < 1 || h->npatches > TD_MAX_LEVELS) return fail(TD_EINVAL, "bad npatches");
     if (h->ratio < 2 || h->ratio > 4) return fail(TD_EUNSUPPORTED, "ratio must be 2, 3 or 4");
@@ -1389,7 +1405,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
 // fy) into v[base ...], checked against the patch count, element size and
 // quantity of the plan that will run it.
 td_status fill_ptrs_for(const td_request& q, int npatches, td_dtype dt, int quantity,
-                        std::vector<void*>& v, size_t base)
+                        void** v, size_t base)
 {
     const bool pot = quantity == TD_POTENTIAL;  // fx receives Phi; fy optional
     if (!q.sigma || !q.fx || (!q.fy && !pot))
@@ -1421,8 +1437,9 @@ td_status fill_ptrs_for(const td_request& q, int npatches, td_dtype dt, int quan
 
 td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v, size_t base)
 {
-    return fill_ptrs_for(q, P.npatches, P.dt, P.quantity, v, base);
+    return fill_ptrs_for(q, P.npatches, P.dt, P.quantity, v.data(), base);
 }
+
 
 }  // namespace
 
@@ -1432,6 +1449,7 @@ td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v
 
 extern "C" td_status td_context_create(int dev, size_t budget, td_context** out)
 {
+    ErrScope es_;
     if (!out) return fail(TD_EINVAL, "out is NULL");
     *out = nullptr;
     int ndev = 0;
@@ -1457,6 +1475,7 @@ extern "C" td_status td_context_create(int dev, size_t budget, td_context** out)
 
 extern "C" td_status td_context_destroy(td_context* c)
 {
+    ErrScope es_;
     if (!c) return fail(TD_EINVAL, "NULL context");
     DeviceGuard g(c->device);
     (void)hipDeviceSynchronize();
@@ -1478,6 +1497,7 @@ extern "C" td_status td_context_destroy(td_context* c)
 
 extern "C" td_status td_context_usage(const td_context* c, size_t* in_use, size_t* spectra)
 {
+    ErrScope es_;
     if (!c) return fail(TD_EINVAL, "NULL context");
     if (in_use) *in_use = c->used.load();
     if (spectra) *spectra = c->spectra_bytes.load();
@@ -1491,12 +1511,14 @@ extern "C" td_status td_context_usage(const td_context* c, size_t* in_use, size_
 extern "C" td_status td_plan_create(td_context* ctx, const td_hierarchy* h, td_dtype dt,
                                     td_plan** out)
 {
+    ErrScope es_;
     return td_plan_create_quantity(ctx, h, dt, TD_FORCE, out);
 }
 
 extern "C" td_status td_plan_create_quantity(td_context* ctx, const td_hierarchy* h, td_dtype dt,
                                              int32_t quantity, td_plan** out)
 {
+    ErrScope es_;
     if (!ctx || !out) return fail(TD_EINVAL, "NULL argument");
     *out = nullptr;
     if (dt != TD_F32 && dt != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
@@ -1548,6 +1570,7 @@ extern "C" td_status td_plan_create_quantity(td_context* ctx, const td_hierarchy
 
 extern "C" td_status td_plan_check(const td_hierarchy* h, td_dtype dt, size_t* workspace_bytes)
 {
+    ErrScope es_;
     if (dt != TD_F32 && dt != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
     TD_TRY(td_hierarchy_check(h));
     static td_context host_ctx;  // default launch shapes, no device
@@ -1565,6 +1588,7 @@ extern "C" td_status td_plan_check(const td_hierarchy* h, td_dtype dt, size_t* w
 
 extern "C" td_status td_plan_footprint(const td_plan* p, size_t* ws, size_t* spec)
 {
+    ErrScope es_;
     if (!p) return fail(TD_EINVAL, "NULL plan");
     if (ws) *ws = p->ws_bytes + p->job_bytes;
     if (spec) *spec = p->spectra_bytes;
@@ -1573,6 +1597,7 @@ extern "C" td_status td_plan_footprint(const td_plan* p, size_t* ws, size_t* spe
 
 extern "C" td_status td_plan_destroy(td_plan* p)
 {
+    ErrScope es_;
     if (!p) return fail(TD_EINVAL, "NULL plan");
     DeviceGuard g(p->ctx->device);
     plan_free(p);
@@ -1582,6 +1607,7 @@ extern "C" td_status td_plan_destroy(td_plan* p)
 
 extern "C" td_status td_solve(const td_request* req, void* stream)
 {
+    ErrScope es_;
     if (!req || !req->plan) return fail(TD_EINVAL, "NULL request or plan");
     td_plan* P = req->plan;
     DeviceGuard g(P->ctx->device);
@@ -1625,6 +1651,7 @@ struct td_batch {
 extern "C" td_status td_batch_create(td_context* ctx, int32_t count, td_plan* const* plans,
                                      td_batch** out)
 {
+    ErrScope es_;
     if (!ctx || !plans || !out || count < 1) return fail(TD_EINVAL, "bad batch arguments");
     *out = nullptr;
     DeviceGuard dg(ctx->device);
@@ -1659,6 +1686,7 @@ extern "C" td_status td_batch_create(td_context* ctx, int32_t count, td_plan* co
 extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use_graph,
                                     void* stream)
 {
+    ErrScope es_;
     if (!B || !reqs) return fail(TD_EINVAL, "NULL batch or requests");
     DeviceGuard dg(B->ctx->device);
     hipStream_t st = (hipStream_t)stream;
@@ -1703,6 +1731,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
 
 extern "C" td_status td_batch_footprint(const td_batch* B, size_t* ws)
 {
+    ErrScope es_;
     if (!B) return fail(TD_EINVAL, "NULL batch");
     if (ws) *ws = B->ws_bytes;
     return TD_OK;
@@ -1710,6 +1739,7 @@ extern "C" td_status td_batch_footprint(const td_batch* B, size_t* ws)
 
 extern "C" td_status td_batch_destroy(td_batch* B)
 {
+    ErrScope es_;
     if (!B) return fail(TD_EINVAL, "NULL batch");
     DeviceGuard dg(B->ctx->device);
     (void)hipDeviceSynchronize();
@@ -1758,8 +1788,18 @@ struct Flight {
     std::vector<uint64_t> tickets;
     std::vector<std::pair<void*, size_t>> ws;  // workspace blocks bound to the tickets
     bool active = false;
-    bool finished = false;  // set by the host callback after the flight's work
-    double t_finish = 0;
+    // set by the host callback after the flight's work (the callback takes
+    // no lock a HIP call could be made under: see flight_finished)
+    std::atomic<bool> finished{false};
+    std::atomic<double> t_finish{0.0};
+};
+
+// The server's flights, sized once at creation (callbacks hold pointers).
+struct FlightArray {
+    std::unique_ptr<Flight[]> p;
+    int n = 0;
+    Flight* begin() { return p.get(); }
+    Flight* end() { return p.get() + n; }
 };
 
 }  // namespace
@@ -1769,11 +1809,16 @@ struct td_server {
     int max_inflight = 2, max_batch = 16;
     size_t queue_cap = 1 << 16;
     std::mutex mu;
-    std::condition_variable cv, cv_done, cv_plan;
+    std::condition_variable cv_done, cv_plan;
+    // wake-ups of the worker: a counter bumped under wake_mu, which is never
+    // held across a HIP call (the flights' host callbacks bump it too)
+    std::mutex wake_mu;
+    std::condition_variable wake_cv;
+    std::atomic<uint64_t> wake_seq{0};
     std::deque<uint64_t> queue;   // admitted to the queue, waiting for a flight
     std::deque<uint64_t> planq;   // waiting for the planner
     std::map<uint64_t, Ticket> tickets;
-    std::vector<Flight> flights;  // sized once: callbacks hold Flight pointers
+    FlightArray flights;
     std::multimap<size_t, void*> pool;  // idle workspace blocks (held, counted as used)
     std::vector<std::pair<void*, size_t>> pool_all;
     std::vector<hipEvent_t> ev_pool;
@@ -1789,18 +1834,26 @@ struct td_server {
 
 namespace {
 
-// Host callback at the end of a flight's stream work: no HIP calls here,
-// only the flag and a wake-up of the worker.
+void wake(td_server* S)
+{
+    {
+        std::lock_guard<std::mutex> g(S->wake_mu);
+        S->wake_seq.fetch_add(1, std::memory_order_acq_rel);
+    }
+    S->wake_cv.notify_all();
+}
+
+// Host callback at the end of a flight's stream work.  It runs on a HIP
+// runtime thread, so it makes no HIP call and takes no lock that another
+// thread may hold while inside the HIP runtime (the server mutex is held
+// around allocations): the flag is atomic, and the wake-up mutex is only
+// ever held for a counter increment or a condition wait.
 void flight_finished(void* arg)
 {
     Flight* f = static_cast<Flight*>(arg);
-    td_server* S = f->owner;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        f->finished = true;
-        f->t_finish = now_s();
-    }
-    S->cv.notify_all();
+    f->t_finish.store(now_s(), std::memory_order_relaxed);
+    f->finished.store(true, std::memory_order_release);
+    wake(f->owner);
 }
 
 // Workspace for one admitted solve: reuse an idle block of a close size, or
@@ -1852,15 +1905,17 @@ void server_loop(td_server* S)
     std::unique_lock<std::mutex> lk(S->mu);
     bool mem_blocked = false;  // the queue head waits for memory a flight holds
     while (true) {
+        // wake-ups from here on are seen by the wait at the bottom
+        const uint64_t seen = S->wake_seq.load(std::memory_order_acquire);
         // retire finished flights (their host callback has run)
         bool progressed = false;
         for (auto& f : S->flights) {
-            if (!f.active || !f.finished) continue;
+            if (!f.active || !f.finished.load(std::memory_order_acquire)) continue;
             for (uint64_t id : f.tickets) {
                 auto it = S->tickets.find(id);
                 if (it != S->tickets.end()) {
                     it->second.state = T_DONE;
-                    it->second.t_done = f.t_finish;
+                    it->second.t_done = f.t_finish.load(std::memory_order_relaxed);
                     if (it->second.inputs) S->ev_pool.push_back(it->second.inputs);
                     it->second.inputs = nullptr;
                 }
@@ -1870,7 +1925,7 @@ void server_loop(td_server* S)
             f.ws.clear();
             f.tickets.clear();
             f.active = false;
-            f.finished = false;
+            f.finished.store(false, std::memory_order_relaxed);
             progressed = true;
         }
         if (progressed) {
@@ -1923,7 +1978,8 @@ void server_loop(td_server* S)
                 lk.lock();
             }
             if (pick.empty()) {
-                if (waited && !any_active && S->pool.empty()) {
+                if (!to_free.empty()) continue;  // idle blocks were just freed: retry
+                if (waited && !any_active) {
                     // nothing runs and nothing idles: the head cannot fit
                     Ticket& T = S->tickets[S->queue.front()];
                     fail_ticket(S, T, TD_ENOMEM, "request workspace does not fit in the HBM budget");
@@ -1934,9 +1990,15 @@ void server_loop(td_server* S)
                 }
                 continue;
             }
-            // the flight's device pointer table: grown before anything is
-            // committed, so a failure leaves the slot as it was and the
-            // requests back at the head of the queue
+            // the flight holds its requests from here on (drain sees them
+            // in flight while the lock is released below)
+            slot->active = true;
+            slot->finished.store(false, std::memory_order_relaxed);
+            slot->tickets = pick;
+            slot->ws = blocks;
+            // the flight's device pointer table: grown before the launch,
+            // so a failure leaves the slot idle and the requests back at the
+            // head of the queue
             td_status st = TD_OK;
             if (slot->cap < nslots) {
                 // only this thread touches an idle slot; the allocations and
@@ -1966,6 +2028,9 @@ void server_loop(td_server* S)
             }
             if (st != TD_OK) {
                 const std::string why = td_last_error();
+                slot->active = false;
+                slot->tickets.clear();
+                slot->ws.clear();
                 for (auto it = pick.rbegin(); it != pick.rend(); ++it) S->queue.push_front(*it);
                 for (auto& b : blocks) S->pool.insert({b.second, b.first});
                 mem_blocked = any_active;
@@ -1986,10 +2051,6 @@ void server_loop(td_server* S)
                 std::copy(T.ptrs.begin(), T.ptrs.end(), v.begin() + mem[k].slot_base);
                 if (T.inputs) waits.push_back(T.inputs);
             }
-            slot->ws = blocks;
-            slot->active = true;
-            slot->finished = false;
-            slot->tickets = pick;
             S->batches++;
             const td_dtype dt = mem[0].plan->dt;
             lk.unlock();
@@ -2022,17 +2083,15 @@ void server_loop(td_server* S)
             continue;
         }
         if (S->stop && S->queue.empty() && S->planq.empty() && !any_active) break;
-        // sleep until a flight finishes, a request arrives or the server stops
-        S->cv.wait(lk, [&] {
-            for (auto& f : S->flights)
-                if (f.active && f.finished) return true;
-            bool free_slot = false;
-            for (auto& f : S->flights) free_slot |= !f.active;
-            if (free_slot && !S->queue.empty() && !mem_blocked) return true;
-            bool active = false;
-            for (auto& f : S->flights) active |= f.active;
-            return S->stop && S->planq.empty() && !active && (S->queue.empty() || !mem_blocked);
-        });
+        if (progressed) continue;  // retired flights may let the queue move
+        // sleep until a flight finishes, a request arrives or the server
+        // stops (any of which bumps the wake counter)
+        lk.unlock();
+        {
+            std::unique_lock<std::mutex> wk(S->wake_mu);
+            S->wake_cv.wait(wk, [&] { return S->wake_seq.load(std::memory_order_acquire) != seen; });
+        }
+        lk.lock();
     }
 }
 
@@ -2113,7 +2172,9 @@ void planner_loop(td_server* S)
         }
         T.state = T_QUEUED;
         S->queue.push_back(id);
-        S->cv.notify_all();
+        lk.unlock();
+        wake(S);
+        lk.lock();
     }
 }
 
@@ -2144,20 +2205,22 @@ td_status submit_ticket(td_server* S, Ticket&& T, int32_t queue_if_full, void* s
         return fail(TD_EDEVICE, "hipEventRecord on the submitting stream");
     }
     T.inputs = ev;
-    std::lock_guard<std::mutex> lk(S->mu);
-    T.id = S->next_id++;
-    T.t_submit = now_s();
-    *ticket = T.id;
-    const bool planning = T.state == T_PLANNING;
-    S->tickets[T.id] = std::move(T);
-    if (planning) {
-        S->planq.push_back(*ticket);
-        S->cv_plan.notify_all();
-    } else {
-        S->queue.push_back(*ticket);
-        S->cv.notify_all();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        T.id = S->next_id++;
+        T.t_submit = now_s();
+        *ticket = T.id;
+        const bool planning = T.state == T_PLANNING;
+        S->tickets[T.id] = std::move(T);
+        if (planning) {
+            S->planq.push_back(*ticket);
+            S->cv_plan.notify_all();
+        } else {
+            S->queue.push_back(*ticket);
+        }
+        S->peak_queue = std::max<uint64_t>(S->peak_queue, S->queue.size() + S->planq.size());
     }
-    S->peak_queue = std::max<uint64_t>(S->peak_queue, S->queue.size() + S->planq.size());
+    wake(S);
     return TD_OK;
 }
 
@@ -2166,6 +2229,7 @@ td_status submit_ticket(td_server* S, Ticket&& T, int32_t queue_if_full, void* s
 extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int32_t max_batch,
                                       td_server** out)
 {
+    ErrScope es_;
     if (!ctx || !out || max_inflight < 1 || max_batch < 1 || max_batch > 4096)
         return fail(TD_EINVAL, "bad server arguments");
     DeviceGuard dg(ctx->device);
@@ -2173,7 +2237,8 @@ extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int
     S->ctx = ctx;
     S->max_inflight = max_inflight;
     S->max_batch = max_batch;
-    S->flights.resize(max_inflight);
+    S->flights.p.reset(new Flight[max_inflight]);
+    S->flights.n = max_inflight;
     for (auto& f : S->flights) {
         f.owner = S.get();
         hipError_t e = hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking);
@@ -2192,6 +2257,7 @@ extern "C" td_status td_server_create(td_context* ctx, int32_t max_inflight, int
 
 extern "C" td_status td_server_set_queue_limit(td_server* S, int32_t max_queued)
 {
+    ErrScope es_;
     if (!S || max_queued < 1) return fail(TD_EINVAL, "bad server or queue limit");
     std::lock_guard<std::mutex> lk(S->mu);
     S->queue_cap = (size_t)max_queued;
@@ -2201,6 +2267,7 @@ extern "C" td_status td_server_set_queue_limit(td_server* S, int32_t max_queued)
 extern "C" td_status td_server_submit(td_server* S, const td_request* req, int32_t queue_if_full,
                                       void* hip_stream, uint64_t* ticket)
 {
+    ErrScope es_;
     if (!S || !req || !req->plan || !ticket) return fail(TD_EINVAL, "NULL argument");
     if (req->plan->ctx != S->ctx) return fail(TD_EINVAL, "plan belongs to another context");
     const td_plan* P = req->plan;
@@ -2222,6 +2289,7 @@ extern "C" td_status td_server_submit_hierarchy(td_server* S, const td_hierarchy
                                                 int32_t queue_if_full, void* hip_stream,
                                                 uint64_t* ticket)
 {
+    ErrScope es_;
     if (!S || !h || !req || !ticket) return fail(TD_EINVAL, "NULL argument");
     if (req->plan) return fail(TD_EINVAL, "req->plan must be NULL: the server plans the hierarchy");
     if (dtype != TD_F32 && dtype != TD_F64) return fail(TD_EINVAL, "dtype must be TD_F32 or TD_F64");
@@ -2236,12 +2304,13 @@ extern "C" td_status td_server_submit_hierarchy(td_server* S, const td_hierarchy
     T.hier = *h;
     T.hier.patches = nullptr;
     T.ptrs.assign(5 * h->npatches, nullptr);
-    TD_TRY(fill_ptrs_for(*req, h->npatches, dtype, quantity, T.ptrs, 0));
+    TD_TRY(fill_ptrs_for(*req, h->npatches, dtype, quantity, T.ptrs.data(), 0));
     return submit_ticket(S, std::move(T), queue_if_full, hip_stream, ticket);
 }
 
 extern "C" td_status td_server_poll(td_server* S, uint64_t ticket, int32_t* done, double* lat)
 {
+    ErrScope es_;
     if (!S || !done) return fail(TD_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
     if (!S->worker_error.empty() && S->tickets.count(ticket) &&
@@ -2263,9 +2332,10 @@ extern "C" td_status td_server_poll(td_server* S, uint64_t ticket, int32_t* done
 
 extern "C" td_status td_server_drain(td_server* S)
 {
+    ErrScope es_;
     if (!S) return fail(TD_EINVAL, "NULL server");
+    wake(S);
     std::unique_lock<std::mutex> lk(S->mu);
-    S->cv.notify_all();
     S->cv_done.wait(lk, [&] {
         if (!S->queue.empty() || !S->planq.empty()) return false;
         for (auto& kv : S->tickets)
@@ -2280,6 +2350,7 @@ extern "C" td_status td_server_drain(td_server* S)
 
 extern "C" td_status td_server_cancel(td_server* S, uint64_t ticket)
 {
+    ErrScope es_;
     if (!S) return fail(TD_EINVAL, "NULL server");
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->tickets.find(ticket);
@@ -2298,6 +2369,7 @@ extern "C" td_status td_server_stats(const td_server* S, uint64_t* completed, ui
                                      uint64_t* refused, uint64_t* deferred, uint64_t* batches,
                                      uint64_t* peak_queue)
 {
+    ErrScope es_;
     if (!S) return fail(TD_EINVAL, "NULL server");
     auto* s = const_cast<td_server*>(S);
     std::lock_guard<std::mutex> lk(s->mu);
@@ -2312,6 +2384,7 @@ extern "C" td_status td_server_stats(const td_server* S, uint64_t* completed, ui
 
 extern "C" td_status td_server_stats2(const td_server* S, uint64_t* planned, uint64_t* failed)
 {
+    ErrScope es_;
     if (!S) return fail(TD_EINVAL, "NULL server");
     auto* s = const_cast<td_server*>(S);
     std::lock_guard<std::mutex> lk(s->mu);
@@ -2322,16 +2395,17 @@ extern "C" td_status td_server_stats2(const td_server* S, uint64_t* planned, uin
 
 extern "C" td_status td_server_destroy(td_server* S)
 {
+    ErrScope es_;
     if (!S) return fail(TD_EINVAL, "NULL server");
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
     }
-    S->cv.notify_all();
+    wake(S);
     S->cv_plan.notify_all();
     for (auto& t : S->planners)
         if (t.joinable()) t.join();
-    S->cv.notify_all();
+    wake(S);
     if (S->worker.joinable()) S->worker.join();
     DeviceGuard dg(S->ctx->device);
     for (auto& f : S->flights) {
@@ -2397,6 +2471,7 @@ void db_load(td_context* ctx, const char* path, const std::string& arch)
 
 extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, const char* db_path)
 {
+    ErrScope es_;
     if (!ctx || max_M < 16) return fail(TD_EINVAL, "bad autotune arguments");
     DeviceGuard dg(ctx->device);
     const std::string arch = arch_name(ctx->device);
@@ -2492,6 +2567,7 @@ extern "C" td_status td_kernel_table(td_context* ctx, int32_t quantity, double a
                                      int32_t kind, int32_t m, int32_t kx, int32_t ky,
                                      double* out_host)
 {
+    ErrScope es_;
     if (!ctx || !out_host) return fail(TD_EINVAL, "NULL argument");
     if (!std::isfinite(aspect) || aspect < 0 || (aspect != 0 && (aspect < 1.0 / 64 || aspect > 64)))
         return fail(TD_EINVAL, "aspect must be 0 (square cells) or in [1/64, 64]");
@@ -2526,6 +2602,7 @@ extern "C" td_status td_kernel_table(td_context* ctx, int32_t quantity, double a
 
 extern "C" td_status td_timing_enable(td_context* ctx, int enable)
 {
+    ErrScope es_;
     if (!ctx) return fail(TD_EINVAL, "NULL context");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->timing = (enable & ((1 << NTIMED) - 1)) != 0;
@@ -2535,6 +2612,7 @@ extern "C" td_status td_timing_enable(td_context* ctx, int enable)
 
 extern "C" td_status td_timing_read(td_context* ctx, double* ms, int64_t* launches)
 {
+    ErrScope es_;
     if (!ctx) return fail(TD_EINVAL, "NULL context");
     DeviceGuard dg(ctx->device);
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -2559,6 +2637,7 @@ extern "C" td_status td_timing_read(td_context* ctx, double* ms, int64_t* launch
 
 extern "C" td_status td_plan_traffic(const td_plan* P, int32_t slopes, double* bytes)
 {
+    ErrScope es_;
     if (!P || !bytes) return fail(TD_EINVAL, "NULL argument");
     if (slopes != TD_SLOPES_GIVEN && slopes != TD_SLOPES_ESTIMATE)
         return fail(TD_EINVAL, "slopes must be TD_SLOPES_GIVEN or TD_SLOPES_ESTIMATE");

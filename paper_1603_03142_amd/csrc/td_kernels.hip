@@ -536,7 +536,9 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
     const ColTables tabs = load_const(reinterpret_cast<const ColTables*>(aux), 0);
     const int slot = threadIdx.x / TPS, lane_c = threadIdx.x % TPS;
     const int lane = lane_c;
-    const int c = slot / G, g = slot % G;
+    // uniform over a wavefront when a slot is one (or more): the column,
+    // its validity and every descriptor derived from them stay scalar
+    const int c = slot_uniform<M>(slot / G), g = slot_uniform<M>(slot % G);
     const int kx = J.kx0 + c;
     const bool col_ok = c < J.ncol;
     cpx<T>* a = A + slot * SP;
@@ -1014,8 +1016,11 @@ hipError_t launch_table(const TableJob& job, hipStream_t st)
     const long long n = (long long)job.M * job.M;
     const int threads = 256;
     const int blocks = (int)((n + threads - 1) / threads);
-    hipLaunchKernelGGL(k_table, dim3(blocks), dim3(threads), 0, st, job);
-    return hipGetLastError();
+    TableJob j = job;
+    void* args[] = {&j};
+    // the launch's own status (not the thread's last error, which an
+    // unrelated earlier call may have left behind)
+    return launch_common(k_table, blocks, threads, 0, st, args);
 }
 
 template hipError_t launch_row_fwd<float>(int, int, int, const SegTable<RowFwdJob>&,
