@@ -207,6 +207,23 @@ td_status td_plan_destroy(td_plan* plan);
  * pointers. */
 td_status td_solve(const td_request* req, void* hip_stream);
 
+/* td_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * runs the same kernels and jobs as td_solve (identical results) but takes
+ * its workspace from a fixed device array of TD_NOALLOC_SCRATCH_BYTES
+ * (32 MiB) per GPU, part of the library's code object and held until the
+ * process ends, instead of the plan's own workspace; it calls no hipMalloc,
+ * hipFree or other allocating routine.  A plan whose workspace exceeds the
+ * array (td_plan_footprint minus the job tables; e.g. more than two
+ * 256^2 FP64 levels) is refused with TD_ENOMEM, nothing enqueued.  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (no solve reads workspace it has not written first): calls that
+ * overlap on one GPU -- on different streams, or with another thread's call
+ * -- race and must be ordered by the caller.  Plans, inputs and outputs as
+ * for td_solve. */
+#define TD_NOALLOC_SCRATCH_BYTES (32u << 20)
+td_status td_solve_noalloc(const td_request* req, void* hip_stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /* A batch plan fuses `count` plans (same dtype, same context) into one set

@@ -25,7 +25,7 @@ TD_MAX_PATCHES = 8
 EXPORTS = [
     "td_context_create", "td_context_destroy", "td_context_usage", "td_hierarchy_check",
     "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_create_quantity",
-    "td_plan_footprint", "td_plan_destroy", "td_solve",
+    "td_plan_footprint", "td_plan_destroy", "td_solve", "td_solve_noalloc",
     "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_destroy",
     "td_autotune", "td_timing_enable", "td_timing_read", "td_plan_traffic", "td_server_create", "td_server_set_queue_limit", "td_server_submit",
     "td_server_submit_hierarchy", "td_server_stats2", "td_server_poll", "td_server_drain",
@@ -97,6 +97,7 @@ def lib():
             "td_plan_check": ([ctypes.POINTER(td_hierarchy), ctypes.c_int, sz], S),
             "td_plan_destroy": ([VP], S),
             "td_solve": ([ctypes.POINTER(td_request), VP], S),
+            "td_solve_noalloc": ([ctypes.POINTER(td_request), VP], S),
             "td_batch_create": ([VP, ctypes.c_int32, ctypes.POINTER(VP), ctypes.POINTER(VP)], S),
             "td_batch_solve": ([VP, ctypes.POINTER(td_request), ctypes.c_int, VP], S),
             "td_batch_footprint": ([VP, sz], S),

@@ -1440,6 +1440,39 @@ td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v
     return fill_ptrs_for(q, P.npatches, P.dt, P.quantity, v.data(), base);
 }
 
+// The passes of one plan on one workspace, in pass order, with the field
+// pointers in the kernel arguments: no host or device allocation, no
+// context lock (twiddles were looked up when the plan was made).
+td_status launch_plan_direct(const td_plan* P, char* ws, const FieldPtrs& fp, hipStream_t st)
+{
+    const bool f64 = P->dt == TD_F64;
+    for (int pass = 0; pass < NTIMED; ++pass)
+        for (const Group& g : P->groups) {
+            hipError_t e = hipSuccess;
+            if (pass == P_ROWFWD) {
+                const int n = (int)g.rowfwd.size();
+                if (!n) continue;
+                const auto t = single_seg<RowFwdJob>(g.d_rowfwd, n, 0, (const void*)P->d_lp, ws);
+                e = f64 ? launch_row_fwd<double>(g.M, g.C[P_ROWFWD], n, t, nullptr, fp, g.tw, true, st)
+                        : launch_row_fwd<float>(g.M, g.C[P_ROWFWD], n, t, nullptr, fp, g.tw, true, st);
+            } else if (pass == P_COL) {
+                const int n = (int)g.col.size();
+                if (!n) continue;
+                const auto t = single_seg<ColJob>(g.d_col, n, 0, (const void*)g.d_coltabs, ws);
+                e = f64 ? launch_col<double>(g.M, g.C[P_COL], g.G[P_COL], n, t, g.tw, st)
+                        : launch_col<float>(g.M, g.C[P_COL], g.G[P_COL], n, t, g.tw, st);
+            } else {
+                const int a = pass == P_ROWINV ? 0 : 1;
+                const int n = (int)g.rinv[a].size();
+                if (!n) continue;
+                const auto t = single_seg<RowInvJob>(g.d_rinv[a], n, 0, (const void*)g.d_rinv_tabs, ws);
+                e = f64 ? launch_row_inv<double>(g.M, g.C[P_ROWINV], g.G[P_ROWINV], n, t, nullptr, fp, g.tw, st)
+                        : launch_row_inv<float>(g.M, g.C[P_ROWINV], g.G[P_ROWINV], n, t, nullptr, fp, g.tw, st);
+            }
+            if (e != hipSuccess) return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+        }
+    return TD_OK;
+}
 
 }  // namespace
 
@@ -1461,6 +1494,12 @@ extern "C" td_status td_context_create(int dev, size_t budget, td_context** out)
     if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos)
         return fail(TD_EUNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
     TD_HIP(prepare_kernels());
+    // the allocation-free solve's device workspace on this device (looked
+    // up once per device, with it current)
+    {
+        void* scratch = nullptr;
+        TD_HIP(noalloc_scratch(dev, &scratch));
+    }
     auto* c = new td_context();
     c->device = dev;
     c->budget = budget;
@@ -1622,6 +1661,27 @@ extern "C" td_status td_solve(const td_request* req, void* stream)
     for (size_t i = 0; i < v.size(); ++i) fp.p[i] = v[i];
     std::vector<Member> mem{{P, 0, (char*)P->ws}};
     return launch_members(P->ctx, P->dt, mem, nullptr, fp, st);
+}
+
+extern "C" td_status td_solve_noalloc(const td_request* req, void* stream)
+{
+    ErrScope es_;
+    if (!req || !req->plan) return fail(TD_EINVAL, "NULL request or plan");
+    const td_plan* P = req->plan;
+    if (P->ws_bytes > TD_NOALLOC_SCRATCH_BYTES)
+        return fail(TD_ENOMEM, "td_solve_noalloc: the plan's workspace (" + std::to_string(P->ws_bytes) +
+                                   " bytes) exceeds the fixed scratch of " +
+                                   std::to_string((size_t)TD_NOALLOC_SCRATCH_BYTES) + " bytes");
+    DeviceGuard g(P->ctx->device);
+    void* v[5 * TD_MAX_PATCHES];
+    TD_TRY(fill_ptrs_for(*req, P->npatches, P->dt, P->quantity, v, 0));
+    void* scratch = nullptr;
+    TD_HIP(noalloc_scratch(P->ctx->device, &scratch));
+    static_assert(5 * TD_MAX_PATCHES <= TD_KARG_PTRS, "kernel-argument pointer table too small");
+    FieldPtrs fp{};
+    fp.n = 5 * P->npatches;
+    for (int i = 0; i < fp.n; ++i) fp.p[i] = v[i];
+    return launch_plan_direct(P, (char*)scratch, fp, (hipStream_t)stream);
 }
 
 // ===========================================================================

@@ -5,6 +5,8 @@
 // Convolution: zero-padded 2-D FFTs along rows (real <-> half-complex,
 // written / read transposed so that every spectral column is contiguous) and
 // along columns (fused with the kernel-spectrum products), Section 2.2.
+#include <mutex>
+
 #include "td_fft.hpp"
 #include "td_jobs.h"
 #include "td_launch.h"
@@ -1041,6 +1043,39 @@ template hipError_t launch_spec_col<float>(int, int, const void*, void*, const v
                                            hipStream_t);
 template hipError_t launch_spec_col<double>(int, int, const void*, void*, const void*, int,
                                             hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free solve (td_solve_noalloc): one file-scope
+// device array per GPU, held until the process ends.  Host code never uses
+// the array's name as an address: its device address is looked up once per
+// device (hipGetSymbolAddress, that device current) and cached here.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[TD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[TD_NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= TD_NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes it current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 // Raise the dynamic-LDS limit of every instantiation to the CU's 160 KiB,
 // less a margin for what a kernel declares statically.

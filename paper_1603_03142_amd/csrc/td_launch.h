@@ -92,6 +92,16 @@ hipError_t launch_table(const TableJob& job, hipStream_t st);
 // Lift the dynamic-LDS cap of every pass instantiation (call once per device).
 hipError_t prepare_kernels();
 
+// The allocation-free solve's workspace: a device array of
+// TD_NOALLOC_SCRATCH_BYTES per GPU (see td_solve_noalloc).  noalloc_scratch
+// returns its device address on `device`, which must be the current device
+// (looked up there once, then cached).
+#ifndef TD_NOALLOC_SCRATCH_BYTES
+#define TD_NOALLOC_SCRATCH_BYTES (32u << 20)
+#endif
+#define TD_NOALLOC_MAX_DEVICES 64
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // Largest workgroup of any pass.  The launch bound lets the compiler give
 // every thread up to 256 VGPRs (two waves per SIMD), so the per-thread
 // FFT operands and partial sums stay in registers.
