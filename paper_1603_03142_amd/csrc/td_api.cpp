@@ -345,6 +345,8 @@ td_status spectra(td_context* ctx, int M, int kind, int m, td_dtype dt, int fami
             j.nrow = std::min(2 * C, M - r0);
             j.scale = 1.0;
             j.est_scale = 1.0;
+            j.lc_lo = 0;
+            j.lc_hi = M;
             j.out = (int64_t)(X * NCOL * (size_t)M * 16);
             jobs.push_back(j);
         }
@@ -735,6 +737,15 @@ void row_scales(const td_plan* P, double h, int f, RowFwdJob* j)
     j->est_scale = f == 2 ? q / P->aspect : q;
 }
 
+// The lattice columns lc of a row job whose source column m lc + col_off
+// lies inside the source level's window [0, nx): the others read nothing.
+void row_columns(RowFwdJob* j, int nx, int ncols)
+{
+    const int lo = ceil_div(-j->col_off, j->m), hi = ceil_div(nx - j->col_off, j->m);
+    j->lc_lo = std::max(0, std::min(lo, ncols));
+    j->lc_hi = std::max(j->lc_lo, std::min(hi, ncols));
+}
+
 // Emit every job of a plan (workspace addresses as byte offsets) and the
 // workspace size in complex elements.
 //
@@ -809,6 +820,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 j.row0 = r0;
                 j.nrow = std::min(R, G.ny - r0);
                 row_scales(P, G.h, f, &j);
+                row_columns(&j, G.nx, G.M / 2);
                 j.out = ptr(own_in[l] + f * plane);
                 g.rowfwd.push_back(j);
             }
@@ -840,6 +852,7 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                             j.row0 = r0;
                             j.nrow = std::min(R, nr - r0);
                             row_scales(P, S.h, f, &j);
+                            row_columns(&j, S.nx, G.M / 2);
                             j.out = ptr(in);
                             g.rowfwd.push_back(j);
                         }
@@ -1048,6 +1061,11 @@ td_status validate_jobs(td_plan* P)
             }
             if (j.row0 < 0 || j.nrow < 1 || j.nrow > 2 * g.C[P_ROWFWD] || j.row0 + j.nrow > j.ld)
                 return bad("row range");
+            // the columns the gather skips map outside the source window
+            if (j.lc_lo < 0 || j.lc_hi < j.lc_lo || j.lc_hi > M / 2 ||
+                (j.lc_lo > 0 && (int64_t)j.m * (j.lc_lo - 1) + j.col_off >= 0) ||
+                (j.lc_hi < M / 2 && (int64_t)j.m * j.lc_hi + j.col_off < P->lv[j.lvl].nx))
+                return bad("row column range");
             if (!in_ws(j.out, (int64_t)H * j.ld)) return bad("row output");
             auto& w = rows_written[j.out];
             if ((int)w.size() < j.ld) w.resize(j.ld, 0);

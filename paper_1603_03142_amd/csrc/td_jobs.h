@@ -44,6 +44,8 @@ struct RowFwdJob {
     int32_t ld;         // stored rows per spectral column
     int32_t row0;       // first stored row of this job
     int32_t nrow;       // rows of this job
+    int32_t lc_lo, lc_hi;  // lattice columns that can hold a source cell (the
+                           // others map outside the source level's window)
     int32_t pad;
     double scale;       // multiplies every value read (sigma, or a given slope)
     double est_scale;   // multiplies a slope estimated from sigma (per-cell units)

@@ -181,6 +181,27 @@ __device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __rest
 // Pass 1: zero-padded real row FFTs, transposed write
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ int floor_div(int a, int b)
+{
+    int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// Workgroups are dispatched to the eight XCDs round-robin, and each XCD has
+// its own L2.  Renumbering them so that runs of K consecutive jobs go to one
+// XCD keeps neighbouring target rows -- which read the same cache lines of
+// the transposed spectra (K rows of 8 bytes fill a 128-byte line) -- in one
+// L2, while the runs still rotate over the XCDs for load balance.
+__device__ __forceinline__ int xcd_block(int bid, int nblk)
+{
+    constexpr int NXCD = 8, K = 16;
+    const int full = nblk - nblk % (NXCD * K);
+    if (bid >= full) return bid;
+    const int x = bid % NXCD, l = bid / NXCD;
+    return (x + NXCD * (l / K)) * K + l % K;
+}
+
+
 // Patch tables are read through global-address-space pointers (uniform per
 // job, so the loads are scalar).
 typedef const __attribute__((address_space(1))) LevelPatches* gpatches;
@@ -228,7 +249,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     int slot_base;
     const void* aux;
     char* ws;
-    const RowFwdJob J = segs.find(blockIdx.x, &slot_base, &aux, &ws);
+    // consecutive jobs (neighbouring stored rows, whose transposed outputs
+    // share cache lines) run on one XCD, so their partial-line writes merge
+    // in that XCD's L2
+    const RowFwdJob J = segs.find(xcd_block(blockIdx.x, gridDim.x), &slot_base, &aux, &ws);
     const int C = blockDim.x / (M / 8);
     constexpr int SP = lds_stride<T>(M);
     cpx<T>* tw = buf + C * SP;
@@ -242,6 +266,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     constexpr int NG = ZP ? M / 2 : M;  // columns gathered
     for (int idx = threadIdx.x; idx < C * NG; idx += blockDim.x) {
         const int p = idx / NG, lc = idx % NG;
+        if (lc < J.lc_lo || lc >= J.lc_hi) {  // outside the source level's window
+            buf[p * SP + lds_pos<T>(lc)] = cpx<T>{0, 0};
+            continue;
+        }
         const int s0 = J.row0 + 2 * p;
         const int scol = J.m * lc + J.col_off;
         const int sr0 = J.m * (J.lr_first + s0) + J.row_off, sr1 = sr0 + J.m;
@@ -580,26 +608,16 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                 if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
                 load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
             }
-            // FP32 with M >= 512: the input's kernel columns are read
-            // before its transform and formed after it, so that the reads
-            // are in flight meanwhile (32 more VGPRs, still 3 waves per
-            // SIMD there; smaller M and FP64 would lose occupancy or spill)
-            constexpr bool EARLY = sizeof(T) == 4 && M >= 512;
-            cpx<T> z0[8], z1[8];
-            if constexpr (EARLY) {
-                if (ok) {
-                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
-                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
-                }
-            }
             // a slot without an input skips its transform when sequences
             // are ordered within their wavefront only (M/8 <= 64)
             if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
             if (ok) {
-                if constexpr (!EARLY) {
-                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
-                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
-                }
+                // the kernel columns are read after the transform: holding
+                // them across it costs 32 VGPRs, and the other waves of the
+                // CU hide the read latency better than that (measured)
+                cpx<T> z0[8], z1[8];
+                kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
                 kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
                 kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
             }
@@ -703,26 +721,6 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
 // ---------------------------------------------------------------------------
 // Pass 4: complex-to-real row FFTs, window / phase extraction, accumulation
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int floor_div(int a, int b)
-{
-    int q = a / b;
-    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
-}
-
-// Workgroups are dispatched to the eight XCDs round-robin, and each XCD has
-// its own L2.  Renumbering them so that runs of K consecutive jobs go to one
-// XCD keeps neighbouring target rows -- which read the same cache lines of
-// the transposed spectra (K rows of 8 bytes fill a 128-byte line) -- in one
-// L2, while the runs still rotate over the XCDs for load balance.
-__device__ __forceinline__ int xcd_block(int bid, int nblk)
-{
-    constexpr int NXCD = 8, K = 16;
-    const int full = nblk - nblk % (NXCD * K);
-    if (bid >= full) return bid;
-    const int x = bid % NXCD, l = bid / NXCD;
-    return (x + NXCD * (l / K)) * K + l % K;
-}
 
 // a / m for a >= 0: a shift when m = 2^sh (sh >= 0), else a division.
 __device__ __forceinline__ int ratio_div(int a, int m, int sh)
