@@ -1034,7 +1034,7 @@ td_status validate_jobs(td_plan* P)
         for (int pass = 0; pass < NSHAPE; ++pass) {
             const int C = g.C[pass], Gs = g.G[pass];
             if (C < 1 || Gs < 1 || Gs > 16 || C * Gs * (M / 8) > TD_MAX_THREADS ||
-                lds_bytes(M, C, es, Gs) > TD_MAX_DYN_LDS)
+                (C & (C - 1)) || (Gs & (Gs - 1)) || lds_bytes(M, C, es, Gs) > TD_MAX_DYN_LDS)
                 return bad("launch shape");
         }
         // pass 1: rows written per row-pass plane, and the lattice row of

@@ -749,8 +749,12 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* tw = A + S * SP;
     // per slot of the current round: contribution (-1: none), x-phase, and
-    // the contribution's ratio shift, origin column and plane base
-    __shared__ int it_c[16], it_kxp[16], it_sh[16], it_oxs[16];
+    // the contribution's ratio shift, origin column, leading dimension and
+    // x-to-y plane distance; per (slot, row) sequence the workspace byte
+    // offset of its stored row in the x plane (-1: none)
+    __shared__ int it_c[16], it_kxp[16], it_sh[16], it_oxs[16], it_ld[16];
+    __shared__ int64_t it_cs[16];
+    __shared__ int64_t it_off[TD_MAX_THREADS / 2];
     stage_twiddles<T, M>(tw, tw_g);
     int slot_base;
     const void* aux;
@@ -766,10 +770,13 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     T accx[NQ], accy[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) { accx[q] = 0; accy[q] = 0; }
+    // C and G are powers of two: sequence index -> (slot, row) by shifts
+    const int lgC = __builtin_ctz(C), lgS = __builtin_ctz(S);
     for (int r0 = 0; r0 < nitems; r0 += G) {
         if (threadIdx.x < G) {
             const int it = r0 + threadIdx.x;
-            int c = -1, kxp = 0, sh = 0, oxs = 0;
+            int c = -1, kxp = 0, sh = 0, oxs = 0, ld = 0;
+            int64_t cs = 0;
             if (it < nitems) {
                 int k = 0, rem = it;
                 while (rem >= contribs[k].m) rem -= contribs[k].m, ++k;
@@ -777,27 +784,45 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
                 kxp = rem;
                 sh = contribs[k].mshift >= 0 ? contribs[k].mshift : -contribs[k].m;
                 oxs = contribs[k].ox_s;
+                ld = contribs[k].ld;
+                cs = contribs[k].comp_stride;
             }
             it_c[threadIdx.x] = c;
             it_kxp[threadIdx.x] = kxp;
             it_sh[threadIdx.x] = sh;
             it_oxs[threadIdx.x] = oxs;
+            it_ld[threadIdx.x] = ld;
+            it_cs[threadIdx.x] = cs;
         }
         __syncthreads();
-        // load: element e -> (slot g, frequency kx, row c), rows fastest
-        for (int e = threadIdx.x; e < G * H * C; e += blockDim.x) {
-            const int cc = e % C, kx = (e / C) % H, gg = e / (C * H);
+        // the stored row each (slot, row) sequence reads: the target row's
+        // coarse-lattice row and y-phase (Case 3'), the slot's x-phase
+        for (int sq = threadIdx.x; sq < S; sq += blockDim.x) {
+            const int gg = sq >> lgC, cc = sq & (C - 1);
             const int ci = it_c[gg];
-            cpx<T> z{0, 0}, zr{0, 0};
+            int64_t off = -1;
             if (ci >= 0 && cc < J.ny) {
                 const RowInvContrib& Q = contribs[ci];
                 const int gy = J.oy_t + J.y0 + cc;  // >= 0
                 const int Jc = ratio_div(gy, Q.m, Q.mshift), kyp = gy - Jc * Q.m;
                 const int sr = Jc - Q.oy_s - Q.lr_first;
-                gptr<cpx<T>> P = (gptr<cpx<T>>)(ws + Q.base) +
-                                 (int64_t)(kyp * Q.m + it_kxp[gg]) * Q.phase_stride;
-                cpx<T> X = ldg<T>(P, (size_t)kx * Q.ld + sr);
-                cpx<T> Y = ldg<T>(P, Q.comp_stride + (size_t)kx * Q.ld + sr);
+                off = Q.base + ((int64_t)(kyp * Q.m + it_kxp[gg]) * Q.phase_stride + sr) *
+                                   (int64_t)sizeof(cpx<T>);
+            }
+            it_off[sq] = off;
+        }
+        __syncthreads();
+        // load: element e -> (sequence = slot x row, frequency kx), rows
+        // fastest, so the threads of one kx read consecutive stored rows
+        for (int e = threadIdx.x; e < S * H; e += blockDim.x) {
+            const int sq = e & (S - 1), kx = e >> lgS;
+            const int gg = sq >> lgC, cc = sq & (C - 1);
+            const int64_t off = it_off[sq];
+            cpx<T> z{0, 0}, zr{0, 0};
+            if (off >= 0) {
+                gptr<cpx<T>> P = (gptr<cpx<T>>)(ws + off) + (int64_t)kx * it_ld[gg];
+                cpx<T> X = ldg<T>(P, 0);
+                cpx<T> Y = ldg<T>(P, it_cs[gg]);
                 if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
                 z = cpx<T>{X.re - Y.im, X.im + Y.re};
                 zr = cpx<T>{X.re + Y.im, Y.re - X.im};

@@ -108,8 +108,8 @@ hipError_t noalloc_scratch(int device, void** ptr);
 #define TD_MAX_THREADS 512
 
 // Largest dynamic LDS a workgroup may request: 160 KiB less a margin for
-// the kernels' static LDS.
-#define TD_MAX_DYN_LDS (160u * 1024u - 512u)
+// the kernels' static LDS (the row inverse's per-round tables, 2.4 KiB).
+#define TD_MAX_DYN_LDS (160u * 1024u - 3072u)
 
 // Dynamic LDS of one workgroup of each pass: C sequences (row_fwd) or C
 // columns / rows x G slots, each padded to lds_stride(M), plus the twiddle
