@@ -149,6 +149,18 @@ td_status td_context_destroy(td_context* ctx);
 /* Bytes currently held by the context and its plans. */
 td_status td_context_usage(const td_context* ctx, size_t* bytes_in_use, size_t* spectra_bytes);
 
+/* Debug mode (flags 0 = off).  With TD_DEBUG_NONFINITE every solve of the
+ * context -- td_solve, td_solve_noalloc, batches, served requests -- also
+ * counts the NaN / Inf values it wrote to its outputs, on the solve's
+ * stream after its passes (one small launch per output array; none under
+ * graph capture, where a batch replay is counted after the replay).  The
+ * counter is allocated when the mode is first enabled. */
+#define TD_DEBUG_NONFINITE 1
+td_status td_context_set_debug(td_context* ctx, int32_t flags);
+/* Wait for the device, return the number of non-finite outputs counted
+ * since the previous call (0 if debug mode was never enabled), clear it. */
+td_status td_debug_nonfinite(td_context* ctx, uint64_t* count);
+
 /* ---------------------------------------------------------------- geometry */
 
 /* Validate a hierarchy (ratio, sizes, alignment, nesting, overlap, aspect).

@@ -86,6 +86,19 @@ class Context:
                 "td_context_usage")
         return a.value, b.value
 
+    def set_debug(self, nonfinite: bool = True):
+        """Debug mode: count NaN / Inf outputs of every solve (see
+        nonfinite_count)."""
+        B.check(lib().td_context_set_debug(self.handle, B.TD_DEBUG_NONFINITE if nonfinite else 0),
+                "td_context_set_debug")
+
+    def nonfinite_count(self) -> int:
+        """Non-finite output values counted since the previous call (waits
+        for the device)."""
+        n = ctypes.c_uint64()
+        B.check(lib().td_debug_nonfinite(self.handle, ctypes.byref(n)), "td_debug_nonfinite")
+        return n.value
+
     def plan(self, hier, dtype: str = "f32", quantity: str = "force") -> "Plan":
         """quantity "force" (solves return (fx, fy)) or "potential" (solves
         return (phi, None))."""

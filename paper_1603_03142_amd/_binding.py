@@ -18,12 +18,14 @@ TD_OK, TD_EINVAL, TD_EALIGN, TD_ENEST, TD_ENOMEM, TD_EDEVICE, TD_EBUSY, TD_EUNSU
 TD_F32, TD_F64 = 0, 1
 TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE = 0, 1
 TD_FORCE, TD_POTENTIAL = 0, 1
+TD_DEBUG_NONFINITE = 1
 TD_MAX_LEVELS = 8
 TD_MAX_PATCHES = 8
 
 # Every entry point the header declares.
 EXPORTS = [
-    "td_context_create", "td_context_destroy", "td_context_usage", "td_hierarchy_check",
+    "td_context_create", "td_context_destroy", "td_context_usage", "td_context_set_debug",
+    "td_debug_nonfinite", "td_hierarchy_check",
     "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_create_quantity",
     "td_plan_footprint", "td_plan_destroy", "td_solve", "td_solve_noalloc",
     "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_destroy",
@@ -85,6 +87,8 @@ def lib():
             "td_context_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(VP)], S),
             "td_context_destroy": ([VP], S),
             "td_context_usage": ([VP, sz, sz], S),
+            "td_context_set_debug": ([VP, ctypes.c_int32], S),
+            "td_debug_nonfinite": ([VP, u64], S),
             "td_hierarchy_check": ([ctypes.POINTER(td_hierarchy)], S),
             "td_hierarchy_snap": ([ctypes.POINTER(td_hierarchy), ctypes.POINTER(td_patch),
                                    ctypes.POINTER(ctypes.c_double),

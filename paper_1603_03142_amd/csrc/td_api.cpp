@@ -166,6 +166,9 @@ struct td_context {
     size_t b_rows_bytes = 0;
     void* b_small = nullptr;  // pointer table, level table, row jobs
     size_t b_small_bytes = 0;
+    // debug mode (td_context_set_debug): non-finite outputs are counted here
+    std::atomic<int> debug{0};
+    unsigned long long* d_nonfinite = nullptr;
     // per-pass timing (diagnostics)
     bool timing = false;
     int timing_mask = 0;  // launch kinds timed (bit per kind)
@@ -1461,6 +1464,22 @@ td_status fill_ptrs(const td_request& q, const td_plan& P, std::vector<void*>& v
 // The passes of one plan on one workspace, in pass order, with the field
 // pointers in the kernel arguments: no host or device allocation, no
 // context lock (twiddles were looked up when the plan was made).
+// Debug mode: count the non-finite values a solve wrote to its outputs
+// (fx, fy of every patch; v holds the 5 field pointers per patch from
+// `base`), on the solve's stream, after its passes.
+td_status debug_count(td_context* ctx, const td_plan* P, void* const* v, size_t base, hipStream_t st)
+{
+    if (!(ctx->debug.load() & TD_DEBUG_NONFINITE) || !ctx->d_nonfinite) return TD_OK;
+    for (int k = 0; k < P->npatches; ++k)
+        for (int c = 3; c < 5; ++c) {
+            const void* p = v[base + 5 * k + c];
+            if (!p) continue;
+            const int64_t n = (int64_t)P->patch_n[k] * P->patch_n[k];
+            TD_HIP(launch_count_nonfinite(P->dt == TD_F64, p, n, ctx->d_nonfinite, st));
+        }
+    return TD_OK;
+}
+
 td_status launch_plan_direct(const td_plan* P, char* ws, const FieldPtrs& fp, hipStream_t st)
 {
     const bool f64 = P->dt == TD_F64;
@@ -1545,6 +1564,7 @@ extern "C" td_status td_context_destroy(td_context* c)
     c->release(c->b_table, c->b_table_bytes);
     c->release(c->b_rows, c->b_rows_bytes);
     c->release(c->b_small, c->b_small_bytes);
+    if (c->d_nonfinite) (void)hipFree(c->d_nonfinite);
     for (auto& kv : c->tw32) (void)hipFree(kv.second);
     for (auto& kv : c->tw64) (void)hipFree(kv.second);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -1558,6 +1578,35 @@ extern "C" td_status td_context_usage(const td_context* c, size_t* in_use, size_
     if (!c) return fail(TD_EINVAL, "NULL context");
     if (in_use) *in_use = c->used.load();
     if (spectra) *spectra = c->spectra_bytes.load();
+    return TD_OK;
+}
+
+extern "C" td_status td_context_set_debug(td_context* c, int32_t flags)
+{
+    if (!c) return fail(TD_EINVAL, "NULL context");
+    if (flags & ~TD_DEBUG_NONFINITE) return fail(TD_EINVAL, "unknown debug flag");
+    DeviceGuard g(c->device);
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if ((flags & TD_DEBUG_NONFINITE) && !c->d_nonfinite) {
+        TD_HIP(hipMalloc((void**)&c->d_nonfinite, sizeof(unsigned long long)));
+        TD_HIP(hipMemset(c->d_nonfinite, 0, sizeof(unsigned long long)));
+    }
+    c->debug.store(flags);
+    return TD_OK;
+}
+
+extern "C" td_status td_debug_nonfinite(td_context* c, uint64_t* count)
+{
+    if (!c || !count) return fail(TD_EINVAL, "NULL argument");
+    *count = 0;
+    if (!c->d_nonfinite) return TD_OK;
+    DeviceGuard g(c->device);
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    unsigned long long h = 0;
+    TD_HIP(hipDeviceSynchronize());
+    TD_HIP(hipMemcpy(&h, c->d_nonfinite, sizeof(h), hipMemcpyDeviceToHost));
+    TD_HIP(hipMemset(c->d_nonfinite, 0, sizeof(unsigned long long)));
+    *count = h;
     return TD_OK;
 }
 
@@ -1678,7 +1727,8 @@ extern "C" td_status td_solve(const td_request* req, void* stream)
     fp.n = (int32_t)v.size();
     for (size_t i = 0; i < v.size(); ++i) fp.p[i] = v[i];
     std::vector<Member> mem{{P, 0, (char*)P->ws}};
-    return launch_members(P->ctx, P->dt, mem, nullptr, fp, st);
+    TD_TRY(launch_members(P->ctx, P->dt, mem, nullptr, fp, st));
+    return debug_count(P->ctx, P, v.data(), 0, st);
 }
 
 extern "C" td_status td_solve_noalloc(const td_request* req, void* stream)
@@ -1699,7 +1749,8 @@ extern "C" td_status td_solve_noalloc(const td_request* req, void* stream)
     FieldPtrs fp{};
     fp.n = 5 * P->npatches;
     for (int i = 0; i < fp.n; ++i) fp.p[i] = v[i];
-    return launch_plan_direct(P, (char*)scratch, fp, (hipStream_t)stream);
+    TD_TRY(launch_plan_direct(P, (char*)scratch, fp, (hipStream_t)stream));
+    return debug_count(P->ctx, P, v, 0, (hipStream_t)stream);
 }
 
 // ===========================================================================
@@ -1802,8 +1853,9 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
         B->last_stream = st;
         B->pushed = true;
     }
-    if (!use_graph) return launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, st);
-    TD_HIP(hipGraphLaunch(B->exec, st));
+    if (!use_graph) TD_TRY(launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, st));
+    else TD_HIP(hipGraphLaunch(B->exec, st));
+    for (auto& m : B->mem) TD_TRY(debug_count(B->ctx, m.plan, v.data(), m.slot_base, st));
     return TD_OK;
 }
 
@@ -2137,6 +2189,8 @@ void server_loop(td_server* S)
                     st = fail(TD_EDEVICE, "hipStreamWaitEvent");
             if (st == TD_OK) st = slot->stager.push(slot->d_ptrs, v, slot->stream);
             if (st == TD_OK) st = launch_members(S->ctx, dt, mem, slot->d_ptrs, FieldPtrs{}, slot->stream);
+            for (size_t k = 0; st == TD_OK && k < mem.size(); ++k)
+                st = debug_count(S->ctx, mem[k].plan, v.data(), mem[k].slot_base, slot->stream);
             const bool cb = st == TD_OK &&
                             hipLaunchHostFunc(slot->stream, flight_finished, slot) == hipSuccess;
             lk.lock();

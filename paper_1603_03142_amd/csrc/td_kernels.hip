@@ -5,6 +5,7 @@
 // Convolution: zero-padded 2-D FFTs along rows (real <-> half-complex,
 // written / read transposed so that every spectral column is contiguous) and
 // along columns (fused with the kernel-spectrum products), Section 2.2.
+#include <algorithm>
 #include <mutex>
 
 #include "td_fft.hpp"
@@ -936,6 +937,23 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_spec_col(const cpx<double>* 
 }
 
 // ---------------------------------------------------------------------------
+// Debug check: non-finite values of an output array, added to a counter
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_count_nonfinite(const T* __restrict__ p, int64_t n,
+                                                       unsigned long long* counter)
+{
+    unsigned int c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        c += isfinite(p[i]) ? 0u : 1u;
+    // one atomic per wavefront that saw any
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(counter, (unsigned long long)c);
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers (dispatch on M)
 // ---------------------------------------------------------------------------
 
@@ -1034,6 +1052,24 @@ hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void
 #undef X
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_count_nonfinite(bool f64, const void* p, int64_t n, unsigned long long* counter,
+                                  hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    const int blocks = (int)std::min<int64_t>((n + threads - 1) / threads, 1024);
+    int64_t nn = n;
+    unsigned long long* c = counter;
+    if (f64) {
+        const double* pp = static_cast<const double*>(p);
+        void* args[] = {&pp, &nn, &c};
+        return launch_common(k_count_nonfinite<double>, blocks, threads, 0, st, args);
+    }
+    const float* pp = static_cast<const float*>(p);
+    void* args[] = {&pp, &nn, &c};
+    return launch_common(k_count_nonfinite<float>, blocks, threads, 0, st, args);
 }
 
 hipError_t launch_table(const TableJob& job, hipStream_t st)

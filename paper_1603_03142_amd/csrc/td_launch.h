@@ -88,6 +88,9 @@ template <typename TO>
 hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void* tw64,
                            int quarter, hipStream_t st);
 hipError_t launch_table(const TableJob& job, hipStream_t st);
+// Add the number of non-finite values of p[0 .. n) to *counter (debug mode).
+hipError_t launch_count_nonfinite(bool f64, const void* p, int64_t n, unsigned long long* counter,
+                                  hipStream_t st);
 
 // Lift the dynamic-LDS cap of every pass instantiation (call once per device).
 hipError_t prepare_kernels();
