@@ -251,6 +251,21 @@ td_status td_batch_create(td_context* ctx, int32_t count, td_plan* const* plans,
 td_status td_batch_solve(td_batch* batch, const td_request* reqs, int use_graph,
                          void* hip_stream);
 td_status td_batch_footprint(const td_batch* batch, size_t* workspace_bytes);
+/* How the batch launches its column pass (the fused column FFTs and
+ * spectral products; the row passes always run one workgroup per job).
+ * TD_LAUNCH_PERSISTENT (the default): each column launch has a grid of
+ * about as many workgroups as the device holds at once, and each workgroup
+ * takes jobs from work lists built at creation, one per XCD (the jobs of
+ * one spectral column together, longest first); a workgroup whose list is
+ * drained takes jobs from the others.  The lists' counters live in the
+ * batch and are zeroed by a kernel ahead of each solve (also inside a
+ * captured graph), so two solves of one batch must not run concurrently,
+ * as for its workspace.  TD_LAUNCH_DIRECT: one workgroup per job.  Results
+ * are identical.  Changing the mode drops a captured graph (after waiting
+ * for the device). */
+#define TD_LAUNCH_DIRECT 0
+#define TD_LAUNCH_PERSISTENT 1
+td_status td_batch_set_launch(td_batch* batch, int32_t mode);
 td_status td_batch_destroy(td_batch* batch);
 
 /* ---------------------------------------------------------------- autotune */

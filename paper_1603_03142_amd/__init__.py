@@ -268,6 +268,12 @@ class Batch:
                                      _stream_handle(stream)), "td_batch_solve")
         return res
 
+    def set_launch(self, mode: str):
+        """'persistent' (default: work lists per XCD, about one wave of
+        workgroups per launch) or 'direct' (one workgroup per job)."""
+        m = {"direct": B.TD_LAUNCH_DIRECT, "persistent": B.TD_LAUNCH_PERSISTENT}[mode]
+        B.check(lib().td_batch_set_launch(self.handle, m), "td_batch_set_launch")
+
     def footprint(self) -> int:
         a = ctypes.c_size_t()
         B.check(lib().td_batch_footprint(self.handle, ctypes.byref(a)), "td_batch_footprint")

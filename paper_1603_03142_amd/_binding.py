@@ -19,6 +19,7 @@ TD_F32, TD_F64 = 0, 1
 TD_SLOPES_GIVEN, TD_SLOPES_ESTIMATE = 0, 1
 TD_FORCE, TD_POTENTIAL = 0, 1
 TD_DEBUG_NONFINITE = 1
+TD_LAUNCH_DIRECT, TD_LAUNCH_PERSISTENT = 0, 1
 TD_MAX_LEVELS = 8
 TD_MAX_PATCHES = 8
 
@@ -28,7 +29,8 @@ EXPORTS = [
     "td_debug_nonfinite", "td_hierarchy_check",
     "td_hierarchy_snap", "td_plan_check", "td_plan_create", "td_plan_create_quantity",
     "td_plan_footprint", "td_plan_destroy", "td_solve", "td_solve_noalloc",
-    "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_destroy",
+    "td_batch_create", "td_batch_solve", "td_batch_footprint", "td_batch_set_launch",
+    "td_batch_destroy",
     "td_autotune", "td_timing_enable", "td_timing_read", "td_plan_traffic", "td_server_create", "td_server_set_queue_limit", "td_server_submit",
     "td_server_submit_hierarchy", "td_server_stats2", "td_server_poll", "td_server_drain",
     "td_server_cancel", "td_server_stats", "td_server_destroy", "td_kernel_table",
@@ -105,6 +107,7 @@ def lib():
             "td_batch_create": ([VP, ctypes.c_int32, ctypes.POINTER(VP), ctypes.POINTER(VP)], S),
             "td_batch_solve": ([VP, ctypes.POINTER(td_request), ctypes.c_int, VP], S),
             "td_batch_footprint": ([VP, sz], S),
+            "td_batch_set_launch": ([VP, ctypes.c_int32], S),
             "td_batch_destroy": ([VP], S),
             "td_autotune": ([VP, ctypes.c_int, ctypes.c_int32, ctypes.c_char_p], S),
             "td_server_create": ([VP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(VP)], S),

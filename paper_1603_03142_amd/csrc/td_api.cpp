@@ -146,6 +146,7 @@ struct SpecEntry {
 
 struct td_context {
     int device = 0;
+    int cus = 256;  // compute units of the device
     size_t budget = 0;
     std::atomic<size_t> used{0};
     std::atomic<size_t> spectra_bytes{0};
@@ -933,6 +934,34 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                                      std::min(chunk, nout - o0), 0});
         }
     }
+    // ---- XCD affinity of the column pass.  Workgroups are dispatched to
+    // the eight XCDs round-robin, each with its own L2; every job of one
+    // spectral column reads the same stored kernel columns (same lattice,
+    // same spectra).  Placing the jobs of column kx at list positions
+    // congruent to kx mod 8 keeps each column's kernel reads in one L2, and
+    // each residue's jobs run longest first.
+    for (auto& g : P->groups) {
+        constexpr int NX = 8;
+        std::vector<ColJob> bucket[NX];
+        for (const ColJob& j : g.col) bucket[j.kx0 % NX].push_back(j);
+        auto cost = [](const ColJob& j) { return j.kind == 0 ? j.nin : 3 + j.nout; };
+        for (auto& b : bucket)
+            std::stable_sort(b.begin(), b.end(), [&](const ColJob& a, const ColJob& c) { return cost(a) > cost(c); });
+        size_t pos[NX] = {};
+        std::vector<ColJob> order;
+        order.reserve(g.col.size());
+        while (order.size() < g.col.size()) {
+            const int x = (int)(order.size() % NX);
+            int take = x;
+            if (pos[take] == bucket[take].size()) {  // residue exhausted: the fullest other
+                take = 0;
+                for (int k = 1; k < NX; ++k)
+                    if (bucket[k].size() - pos[k] > bucket[take].size() - pos[take]) take = k;
+            }
+            order.push_back(bucket[take][pos[take]++]);
+        }
+        g.col.swap(order);
+    }
     // ---- pass 4: row inverse, grouped by lattice length
     for (int t = 0; t < L; ++t) {
         const LevelG& T = P->lv[t];
@@ -1328,10 +1357,75 @@ void push_seg(std::vector<SegTable<Job>>& tabs, std::vector<int>& totals, const 
     s.start[s.nseg] = totals.back();
 }
 
-// One launch per (pass, M, <= TD_MAX_SEGS members), in pass order.
-td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>& mem,
-                         void* const* d_ptrs, const FieldPtrs& fp, hipStream_t st)
+// The persistent column launches of a fixed member set (a batch): one work
+// queue per column launch, in launch order, recorded once by running
+// launch_members with `building` set (which launches nothing).
+struct QueueRec {
+    JobQueue q;
+    int grid;
+};
+struct Queues {
+    bool building = false;
+    std::vector<QueueRec> recs;
+    // while recording: each launch's job order and list starts
+    std::vector<std::vector<int32_t>> order, start;
+    void* dev = nullptr;  // counters of every launch, then starts and orders
+    size_t dev_bytes = 0;
+};
+
+// Record one persistent column launch over the jobs of `segs` (in launch
+// order).  A job goes to the list of its spectral column mod TD_NXCD (the
+// jobs of one column read the same kernel columns: one L2), unless that
+// list already holds its share of the launch's work; then to the least
+// loaded list.  Jobs are placed and listed longest first, so that the
+// short ones fill the tail.  The grid holds as many workgroups as the
+// device runs at once, at most one per job.
+void record_col_launch(const td_context* ctx, const std::vector<std::pair<const ColJob*, int>>& segs,
+                       bool f64, int M, int C, int G, Queues* qs)
 {
+    struct Item { int cost, col, idx; };
+    std::vector<Item> items;
+    int base = 0;
+    long long total = 0;
+    for (auto& sg : segs) {
+        for (int k = 0; k < sg.second; ++k) {
+            const ColJob& j = sg.first[k];
+            const int cost = j.kind == 0 ? std::max(1, j.nin) : 3 + j.nout;
+            items.push_back({cost, j.kx0 % TD_NXCD, base + k});
+            total += cost;
+        }
+        base += sg.second;
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    const long long share = (total + TD_NXCD - 1) / TD_NXCD;
+    std::vector<std::vector<int32_t>> lists(TD_NXCD);
+    long long load[TD_NXCD] = {0};
+    for (const Item& it : items) {
+        int l = it.col;
+        if (load[l] + it.cost > share) l = int(std::min_element(load, load + TD_NXCD) - load);
+        lists[l].push_back(it.idx);
+        load[l] += it.cost;
+    }
+    std::vector<int32_t> order, start(1, 0);
+    for (auto& l : lists) {
+        order.insert(order.end(), l.begin(), l.end());
+        start.push_back((int32_t)order.size());
+    }
+    const int per_xcd = std::max(1, ctx->cus / TD_NXCD) * col_resident_blocks(f64, M, C, G);
+    const int grid = TD_NXCD * std::max(1, std::min(per_xcd, (base + TD_NXCD - 1) / TD_NXCD));
+    qs->order.push_back(std::move(order));
+    qs->start.push_back(std::move(start));
+    qs->recs.push_back({JobQueue{}, grid});
+}
+
+// One launch per (pass, M, <= TD_MAX_SEGS members), in pass order.  With
+// `qs`: persistent launches on the batch's recorded queues (or, while
+// qs->building, record them and launch nothing).
+td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>& mem,
+                         void* const* d_ptrs, const FieldPtrs& fp, hipStream_t st,
+                         Queues* qs = nullptr)
+{
+    size_t launch_index = 0;
     std::vector<int> Ms;
     for (auto& m : mem)
         for (auto& g : m.plan->groups)
@@ -1344,7 +1438,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
     };
     const bool f64 = dt == TD_F64;
     bool timed = false;
-    if (ctx->timing) {
+    if (ctx->timing && !(qs && qs->building)) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         timed = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
     }
@@ -1385,18 +1479,41 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                     for (auto& gs : kv.second)
                         push_seg(t, n, gs.first->d_rowfwd, (int)gs.first->rowfwd.size(), gs.second->slot_base,
                                  (const void*)gs.second->plan->d_lp, gs.second->ws);
+                    if (qs && qs->building) continue;
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
                         e = f64 ? launch_row_fwd<double>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, true, st)
                                 : launch_row_fwd<float>(M, C, n[i], t[i], (const void* const*)d_ptrs, fp, tw, true, st);
                 } else if (pass == P_COL) {
                     std::vector<SegTable<ColJob>> t;
                     std::vector<int> n;
-                    for (auto& gs : kv.second)
+                    // the host job lists of each launch's segments
+                    std::vector<std::vector<std::pair<const ColJob*, int>>> host;
+                    for (auto& gs : kv.second) {
+                        const size_t before = t.size();
                         push_seg(t, n, gs.first->d_col, (int)gs.first->col.size(), gs.second->slot_base,
                                  (const void*)gs.first->d_coltabs, gs.second->ws);
-                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_col<double>(M, C, Gs, n[i], t[i], tw, st)
-                                : launch_col<float>(M, C, Gs, n[i], t[i], tw, st);
+                        if (gs.first->col.empty()) continue;
+                        if (t.size() > before) host.emplace_back();
+                        host.back().push_back({gs.first->col.data(), (int)gs.first->col.size()});
+                    }
+                    for (size_t i = 0; i < t.size() && e == hipSuccess; ++i, ++launch_index) {
+                        JobQueue q{};
+                        int blocks = n[i];
+                        if (qs && qs->building) {
+                            record_col_launch(ctx, host[i], f64, M, C, Gs, qs);
+                            continue;
+                        }
+                        if (qs) {
+                            if (launch_index >= qs->recs.size()) {
+                                e = hipErrorInvalidValue;
+                                break;
+                            }
+                            q = qs->recs[launch_index].q;
+                            blocks = qs->recs[launch_index].grid;
+                        }
+                        e = f64 ? launch_col<double>(M, C, Gs, blocks, t[i], tw, st, q)
+                                : launch_col<float>(M, C, Gs, blocks, t[i], tw, st, q);
+                    }
                 } else {
                     const int a = pass == P_ROWINV ? 0 : 1;
                     std::vector<SegTable<RowInvJob>> t;
@@ -1405,6 +1522,7 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                         push_seg(t, n, gs.first->d_rinv[a], (int)gs.first->rinv[a].size(),
                                  gs.second->slot_base, (const void*)gs.first->d_rinv_tabs,
                                  gs.second->ws);
+                    if (qs && qs->building) continue;
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
                         e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st)
                                 : launch_row_inv<float>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st);
@@ -1539,6 +1657,7 @@ extern "C" td_status td_context_create(int dev, size_t budget, td_context** out)
     }
     auto* c = new td_context();
     c->device = dev;
+    c->cus = prop.multiProcessorCount;
     c->budget = budget;
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -1775,7 +1894,64 @@ struct td_batch {
     std::vector<void*> last_ptrs;
     hipStream_t last_stream = nullptr;
     bool pushed = false;
+    // persistent launches (td_batch_set_launch): the recorded work queues
+    int launch_mode = TD_LAUNCH_PERSISTENT;
+    Queues queues;
 };
+
+namespace {
+
+// Record the batch's column launches and upload their work lists: the
+// TD_NXCD counters of every launch (zeroed by a kernel ahead of each
+// solve), then per launch the TD_NXCD + 1 list starts and the job order.
+td_status build_queues(td_batch* B)
+{
+    Queues& qs = B->queues;
+    qs.building = true;
+    td_status s = launch_members(B->ctx, B->dt, B->mem, nullptr, FieldPtrs{}, nullptr, &qs);
+    qs.building = false;
+    if (s != TD_OK) return s;
+    const size_t nl = qs.recs.size();
+    size_t words = nl * TD_NXCD + nl * (TD_NXCD + 1);
+    for (auto& o : qs.order) words += o.size();
+    std::vector<int32_t> host(words, 0);
+    size_t at = nl * TD_NXCD;
+    std::vector<size_t> st_at(nl), or_at(nl);
+    for (size_t i = 0; i < nl; ++i) {
+        st_at[i] = at;
+        std::copy(qs.start[i].begin(), qs.start[i].end(), host.begin() + at);
+        at += TD_NXCD + 1;
+        or_at[i] = at;
+        std::copy(qs.order[i].begin(), qs.order[i].end(), host.begin() + at);
+        at += qs.order[i].size();
+    }
+    qs.dev_bytes = std::max<size_t>(4, words * sizeof(int32_t));
+    TD_TRY(B->ctx->alloc(qs.dev_bytes, &qs.dev));
+    TD_HIP(hipMemcpy(qs.dev, host.data(), words * sizeof(int32_t), hipMemcpyHostToDevice));
+    int32_t* d = (int32_t*)qs.dev;
+    for (size_t i = 0; i < nl; ++i) {
+        qs.recs[i].q.counter = (unsigned int*)(d + i * TD_NXCD);
+        qs.recs[i].q.start = d + st_at[i];
+        qs.recs[i].q.order = d + or_at[i];
+    }
+    qs.order.clear();
+    qs.start.clear();
+    return TD_OK;
+}
+
+// The batch's launches on stream st: with persistent launches, first zero
+// the work-list counters.
+td_status batch_launch(td_batch* B, hipStream_t st)
+{
+    Queues* qs = nullptr;
+    if (B->launch_mode == TD_LAUNCH_PERSISTENT && !B->queues.recs.empty()) {
+        qs = &B->queues;
+        TD_HIP(launch_zero_counters((unsigned int*)qs->dev, (int)(qs->recs.size() * TD_NXCD), st));
+    }
+    return launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, st, qs);
+}
+
+}  // namespace
 
 extern "C" td_status td_batch_create(td_context* ctx, int32_t count, td_plan* const* plans,
                                      td_batch** out)
@@ -1808,7 +1984,31 @@ extern "C" td_status td_batch_create(td_context* ctx, int32_t count, td_plan* co
         return st;
     }
     for (size_t k = 0; k < B->mem.size(); ++k) B->mem[k].ws = (char*)B->ws + ws_off[k];
+    st = build_queues(B.get());
+    if (st != TD_OK) {
+        ctx->release(B->ws, B->ws_bytes);
+        ctx->release(B->d_ptrs, sizeof(void*) * B->nslots);
+        B->stager.destroy();
+        return st;
+    }
     *out = B.release();
+    return TD_OK;
+}
+
+extern "C" td_status td_batch_set_launch(td_batch* B, int32_t mode)
+{
+    ErrScope es_;
+    if (!B) return fail(TD_EINVAL, "NULL batch");
+    if (mode != TD_LAUNCH_DIRECT && mode != TD_LAUNCH_PERSISTENT) return fail(TD_EINVAL, "unknown launch mode");
+    if (mode == B->launch_mode) return TD_OK;
+    DeviceGuard dg(B->ctx->device);
+    // the captured graph holds the old launches
+    if (B->exec || B->graph) TD_HIP(hipDeviceSynchronize());
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->launch_mode = mode;
     return TD_OK;
 }
 
@@ -1834,7 +2034,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
                 TD_TRY(twiddles(B->ctx, g.M, B->dt, &tw));
             }
         TD_HIP(hipStreamBeginCapture(B->graph_stream, hipStreamCaptureModeThreadLocal));
-        td_status s = launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, B->graph_stream);
+        td_status s = batch_launch(B, B->graph_stream);
         hipGraph_t gph = nullptr;
         hipError_t e = hipStreamEndCapture(B->graph_stream, &gph);
         if (s != TD_OK) {
@@ -1853,7 +2053,7 @@ extern "C" td_status td_batch_solve(td_batch* B, const td_request* reqs, int use
         B->last_stream = st;
         B->pushed = true;
     }
-    if (!use_graph) TD_TRY(launch_members(B->ctx, B->dt, B->mem, B->d_ptrs, FieldPtrs{}, st));
+    if (!use_graph) TD_TRY(batch_launch(B, st));
     else TD_HIP(hipGraphLaunch(B->exec, st));
     for (auto& m : B->mem) TD_TRY(debug_count(B->ctx, m.plan, v.data(), m.slot_base, st));
     return TD_OK;
@@ -1878,6 +2078,7 @@ extern "C" td_status td_batch_destroy(td_batch* B)
     if (B->graph_stream) (void)hipStreamDestroy(B->graph_stream);
     if (B->ws) B->ctx->release(B->ws, B->ws_bytes);
     if (B->d_ptrs) B->ctx->release(B->d_ptrs, sizeof(void*) * B->nslots);
+    if (B->queues.dev) B->ctx->release(B->queues.dev, B->queues.dev_bytes);
     B->stager.destroy();
     delete B;
     return TD_OK;

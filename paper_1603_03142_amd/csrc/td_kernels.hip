@@ -179,6 +179,63 @@ __device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __rest
 }
 
 // ---------------------------------------------------------------------------
+// Job order of a column launch (see JobQueue): a direct launch runs job
+// blockIdx.x; a persistent one pulls jobs from the work lists until all are
+// drained.  Every thread of the workgroup takes part (the job is broadcast
+// through LDS), so every wave reaches the same loop exit.
+// ---------------------------------------------------------------------------
+
+// Workgroup b takes the next job of the list of its own XCD (b mod TD_NXCD:
+// workgroups are dispatched to the XCDs round-robin), then, once that list
+// is drained, of the other lists in turn, skipping (by a plain read of its
+// counter) a list already drained.  s[0] is the job handed to the
+// workgroup, s[1] the list offset thread 0 has reached.
+__device__ __forceinline__ int pull_job(const JobQueue& q, int* s)
+{
+    __syncthreads();  // the previous job's use of LDS is over
+    if (threadIdx.x == 0) {
+        int item = -1;
+        for (int d = s[1]; d < TD_NXCD; ++d) {
+            const int l = (blockIdx.x + d) % TD_NXCD;
+            const int first = q.start[l], len = q.start[l + 1] - first;
+            if (d > 0 && (int)__hip_atomic_load(q.counter + l, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) >= len) {
+                s[1] = d + 1;
+                continue;
+            }
+            const int k = (int)atomicAdd(q.counter + l, 1u);
+            if (k < len) {
+                item = q.order[first + k];
+                break;
+            }
+            s[1] = d + 1;
+        }
+        s[0] = item;
+    }
+    __syncthreads();
+    return s[0];
+}
+
+__device__ __forceinline__ int first_job(const JobQueue& q, int* s)
+{
+    if (!q.order) return blockIdx.x;
+    if (threadIdx.x == 0) s[1] = 0;
+    return pull_job(q, s);
+}
+
+__device__ __forceinline__ int next_job(const JobQueue& q, int* s)
+{
+    return q.order ? pull_job(q, s) : -1;
+}
+
+// Zero n work-list counters (launched ahead of a solve's persistent
+// launches; a kernel rather than a memset, so that it can be captured).
+__global__ void __launch_bounds__(256) k_zero_counters(unsigned int* c, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Pass 1: zero-padded real row FFTs, transposed write
 // ---------------------------------------------------------------------------
 
@@ -551,7 +608,8 @@ __device__ __forceinline__ void store_column(const cpx<T> (&w)[8], char* ws, con
 
 template <typename T, int M>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
-                                                        const cpx<T>* __restrict__ tw_g, int G)
+                                                        const cpx<T>* __restrict__ tw_g, int G,
+                                                        const JobQueue q)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TPS = M / 8;
@@ -560,162 +618,165 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* tw = A + S * SP;
     stage_twiddles<T, M>(tw, tw_g);
-    int slot_unused;
-    const void* aux;
-    char* ws;
-    const ColJob J = segs.find(blockIdx.x, &slot_unused, &aux, &ws);
-    const ColTables tabs = load_const(reinterpret_cast<const ColTables*>(aux), 0);
-    const int slot = threadIdx.x / TPS, lane_c = threadIdx.x % TPS;
-    const int lane = lane_c;
-    // uniform over a wavefront when a slot is one (or more): the column,
-    // its validity and every descriptor derived from them stay scalar
-    const int c = slot_uniform<M>(slot / G), g = slot_uniform<M>(slot % G);
-    const int kx = J.kx0 + c;
-    const bool col_ok = c < J.ncol;
-    cpx<T>* a = A + slot * SP;
-    cpx<T>* col0 = A + c * G * SP;  // the column's first slot
-    // Inside the loops the lane index is re-derived through an empty asm
-    // barrier, so that the per-frequency addresses are recomputed in each
-    // iteration instead of being hoisted and held in registers throughout.
+    __shared__ int s_item[2];
+    for (int item = first_job(q, s_item); item >= 0; item = next_job(q, s_item)) {
+        int slot_unused;
+        const void* aux;
+        char* ws;
+        const ColJob J = segs.find(item, &slot_unused, &aux, &ws);
+        const ColTables tabs = load_const(reinterpret_cast<const ColTables*>(aux), 0);
+        const int slot = threadIdx.x / TPS, lane_c = threadIdx.x % TPS;
+        const int lane = lane_c;
+        // uniform over a wavefront when a slot is one (or more): the column,
+        // its validity and every descriptor derived from them stay scalar
+        const int c = slot_uniform<M>(slot / G), g = slot_uniform<M>(slot % G);
+        const int kx = J.kx0 + c;
+        const bool col_ok = c < J.ncol;
+        cpx<T>* a = A + slot * SP;
+        cpx<T>* col0 = A + c * G * SP;  // the column's first slot
+        // Inside the loops the lane index is re-derived through an empty asm
+        // barrier, so that the per-frequency addresses are recomputed in each
+        // iteration instead of being hoisted and held in registers throughout.
 
-    if (J.kind == 0) {
-        cpx<T> ax[8], ay[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
-        // each input's column is loaded one iteration ahead, while the
-        // previous input is transformed and multiplied
-        ColIn In{0, nullptr, 0, 0, 0, 0};
-        bool okn;
-        cpx<T> xn[4];
-        bool vn[4];
-        {
-            const int i = slot_uniform<M>(g);
-            okn = col_ok && i < J.nin;
-            if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
-            load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
+        if (J.kind == 0) {
+            cpx<T> ax[8], ay[8];
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
+            // each input's column is loaded one iteration ahead, while the
+            // previous input is transformed and multiplied
+            ColIn In{0, nullptr, 0, 0, 0, 0};
+            bool okn;
+            cpx<T> xn[4];
+            bool vn[4];
+            {
+                const int i = slot_uniform<M>(g);
+                okn = col_ok && i < J.nin;
+                if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
+                load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
+            }
+            for (int r0 = 0; r0 < J.nin; r0 += G) {
+                int lane = lane_c;
+                asm volatile("" : "+v"(lane));
+                const ColIn I = In;
+                const bool ok = okn;
+                cpx<T> v[8];
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
+                {
+                    const int i = slot_uniform<M>(r0 + G + g);
+                    okn = col_ok && i < J.nin;
+                    In = ColIn{0, nullptr, 0, 0, 0, 0};
+                    if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
+                    load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
+                }
+                // a slot without an input skips its transform when sequences
+                // are ordered within their wavefront only (M/8 <= 64)
+                if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
+                if (ok) {
+                    // the kernel columns are read after the transform: holding
+                    // them across it costs 32 VGPRs, and the other waves of the
+                    // CU hide the read latency better than that (measured)
+                    cpx<T> z0[8], z1[8];
+                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                    kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
+                    kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
+                }
+            }
+            // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
+            // (slot 0 as well when G == 1)
+            const int gy = G > 1 ? 1 : 0;
+            cpx<T> sx[8], sy[8];
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) sx[q] = sy[q] = cpx<T>{0, 0};
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ax[q];
+            __syncthreads();
+            if (g == 0) {
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int p = lds_pos<T>(lane + q * TPS);
+                    cpx<T> sum = col0[p];
+                    for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
+                    sx[q] = sum;
+                }
+            }
+            __syncthreads();
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ay[q];
+            __syncthreads();
+            if (g == gy) {
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int p = lds_pos<T>(lane + q * TPS);
+                    cpx<T> sum = col0[p];
+                    for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
+                    sy[q] = sum;
+                }
+            }
+            __syncthreads();  // the sums are read: the slots' LDS is free again
+            // inverse column transforms in registers (every slot transforms:
+            // slot 0 Fx, slot gy Fy, the others zeros)
+            cpx<T> w[8];
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
+            if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
+            if (col_ok && g == 0) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0), kx, lane);
+            if (col_ok && G > 1 && g == 1)
+                store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
+            if (G == 1) {
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) w[q] = sy[q];
+                fft_regs<T, M, true, false, true>(w, A, tw);
+                if (col_ok) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
+            }
+            continue;
         }
-        for (int r0 = 0; r0 < J.nin; r0 += G) {
+
+        // kind 1: transform the three inputs, keeping this thread's frequencies
+        // of all three in registers
+        cpx<T> vin[3][8];
+        for (int r0 = 0; r0 < 3; r0 += G) {
+            const int i = slot_uniform<M>(r0 + g);
+            const bool ok = col_ok && i < 3;
+            ColIn I{0, nullptr, 0, 0, 0, 0};
+            if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
+            cpx<T> v[8];
+            load_column<T, M>(v, ws, I, kx, ok, lane);
+            fft_regs<T, M, false, true>(v, A, tw);
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = v[q];
+            __syncthreads();  // every slot reads the three transformed inputs
+    #pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (f >= r0 && f < r0 + G) {
+    #pragma unroll
+                    for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos<T>(lane + q * TPS)];
+                }
+            }
+            __syncthreads();
+        }
+        for (int o0 = 0; o0 < J.nout; o0 += G) {
             int lane = lane_c;
             asm volatile("" : "+v"(lane));
-            const ColIn I = In;
-            const bool ok = okn;
-            cpx<T> v[8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
-            {
-                const int i = slot_uniform<M>(r0 + G + g);
-                okn = col_ok && i < J.nin;
-                In = ColIn{0, nullptr, 0, 0, 0, 0};
-                if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
-                load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
-            }
-            // a slot without an input skips its transform when sequences
-            // are ordered within their wavefront only (M/8 <= 64)
-            if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
+            const int o = slot_uniform<M>(o0 + g);
+            const bool ok = col_ok && o < J.nout;
+            cpx<T> acc[8];
+    #pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
+            ColOut O{0, nullptr, 0, 0, 0, 0};
             if (ok) {
-                // the kernel columns are read after the transform: holding
-                // them across it costs 32 VGPRs, and the other waves of the
-                // CU hide the read latency better than that (measured)
-                cpx<T> z0[8], z1[8];
-                kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
-                kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
-                kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
-                kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
+                O = load_desc<M>(tabs.outs, J.out0 + o);
+    #pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    cpx<T> z[8];
+                    kern_load<T, M>(z, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
+                    kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
+                }
             }
+            if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);
+            if (ok) store_column<T, M>(acc, ws, O, kx, lane);
         }
-        // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
-        // (slot 0 as well when G == 1)
-        const int gy = G > 1 ? 1 : 0;
-        cpx<T> sx[8], sy[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) sx[q] = sy[q] = cpx<T>{0, 0};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ax[q];
-        __syncthreads();
-        if (g == 0) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int p = lds_pos<T>(lane + q * TPS);
-                cpx<T> sum = col0[p];
-                for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
-                sx[q] = sum;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ay[q];
-        __syncthreads();
-        if (g == gy) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int p = lds_pos<T>(lane + q * TPS);
-                cpx<T> sum = col0[p];
-                for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
-                sy[q] = sum;
-            }
-        }
-        __syncthreads();  // the sums are read: the slots' LDS is free again
-        // inverse column transforms in registers (every slot transforms:
-        // slot 0 Fx, slot gy Fy, the others zeros)
-        cpx<T> w[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
-        if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
-        if (col_ok && g == 0) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0), kx, lane);
-        if (col_ok && G > 1 && g == 1)
-            store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
-        if (G == 1) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) w[q] = sy[q];
-            fft_regs<T, M, true, false, true>(w, A, tw);
-            if (col_ok) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
-        }
-        return;
-    }
-
-    // kind 1: transform the three inputs, keeping this thread's frequencies
-    // of all three in registers
-    cpx<T> vin[3][8];
-    for (int r0 = 0; r0 < 3; r0 += G) {
-        const int i = slot_uniform<M>(r0 + g);
-        const bool ok = col_ok && i < 3;
-        ColIn I{0, nullptr, 0, 0, 0, 0};
-        if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
-        cpx<T> v[8];
-        load_column<T, M>(v, ws, I, kx, ok, lane);
-        fft_regs<T, M, false, true>(v, A, tw);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = v[q];
-        __syncthreads();  // every slot reads the three transformed inputs
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            if (f >= r0 && f < r0 + G) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos<T>(lane + q * TPS)];
-            }
-        }
-        __syncthreads();
-    }
-    for (int o0 = 0; o0 < J.nout; o0 += G) {
-        int lane = lane_c;
-        asm volatile("" : "+v"(lane));
-        const int o = slot_uniform<M>(o0 + g);
-        const bool ok = col_ok && o < J.nout;
-        cpx<T> acc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
-        ColOut O{0, nullptr, 0, 0, 0, 0};
-        if (ok) {
-            O = load_desc<M>(tabs.outs, J.out0 + o);
-#pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                cpx<T> z[8];
-                kern_load<T, M>(z, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
-                kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
-            }
-        }
-        if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);
-        if (ok) store_column<T, M>(acc, ws, O, kx, lane);
     }
 }
 
@@ -995,7 +1056,7 @@ hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& s
 
 template <typename T>
 hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& segs,
-                      const void* tw, hipStream_t st)
+                      const void* tw, hipStream_t st, const JobQueue& queue)
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * G * (M / 8);
@@ -1003,7 +1064,8 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
     SegTable<ColJob> s = segs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
     int g = G;
-    void* args[] = {&s, &t, &g};
+    JobQueue q = queue;
+    void* args[] = {&s, &t, &g, &q};
     switch (M) {
 #define X(MM) case MM: return launch_common(k_col<T, MM>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
@@ -1054,6 +1116,42 @@ hipError_t launch_spec_col(int M, int C, const void* rows, void* out, const void
     return hipErrorInvalidValue;
 }
 
+// Workgroups of kernel kf (threads, dynamic LDS smem) one CU holds at once,
+// from its register count and LDS: 4 SIMDs of 512 VGPRs per lane and at
+// most 8 waves each, 160 KiB of LDS.
+template <typename KF>
+static int occupancy(KF kf, int threads, size_t smem)
+{
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kf)) != hipSuccess) return 1;
+    const int waves = (threads + 63) / 64, per_simd = (waves + 3) / 4;
+    const int vgpr = std::max(8, (a.numRegs + 7) & ~7);
+    const int by_regs = std::min(8, 512 / vgpr) / per_simd;
+    const int by_lds = (int)((160u * 1024u) / std::max<size_t>(1, smem + a.sharedSizeBytes));
+    return std::max(1, std::min(by_regs, by_lds));
+}
+
+int col_resident_blocks(bool f64, int M, int C, int G)
+{
+    const int threads = C * G * (M / 8);
+    const size_t es = f64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
+    const size_t smem = lds_bytes(M, C, es, G);
+    switch (M) {
+#define X(MM) \
+    case MM: return f64 ? occupancy(k_col<double, MM>, threads, smem) : occupancy(k_col<float, MM>, threads, smem);
+        TD_FOR_EACH_M(X)
+#undef X
+    }
+    return 1;
+}
+
+hipError_t launch_zero_counters(unsigned int* c, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    void* args[] = {&c, &n};
+    return launch_common(k_zero_counters, std::min(64, (n + 255) / 256), 256, 0, st, args);
+}
+
 hipError_t launch_count_nonfinite(bool f64, const void* p, int64_t n, unsigned long long* counter,
                                   hipStream_t st)
 {
@@ -1091,9 +1189,9 @@ template hipError_t launch_row_fwd<double>(int, int, int, const SegTable<RowFwdJ
                                            const void* const*, const FieldPtrs&, const void*, bool,
                                            hipStream_t);
 template hipError_t launch_col<float>(int, int, int, int, const SegTable<ColJob>&, const void*,
-                                      hipStream_t);
+                                      hipStream_t, const JobQueue&);
 template hipError_t launch_col<double>(int, int, int, int, const SegTable<ColJob>&, const void*,
-                                       hipStream_t);
+                                       hipStream_t, const JobQueue&);
 template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
                                           void* const*, const FieldPtrs&, const void*, hipStream_t);
 template hipError_t launch_row_inv<double>(int, int, int, int, const SegTable<RowInvJob>&,

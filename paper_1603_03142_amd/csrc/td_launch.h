@@ -70,18 +70,38 @@ struct FieldPtrs {
     void* p[TD_KARG_PTRS];
 };
 
+// Persistent column launches: the workgroups of a grid pull their jobs from
+// per-XCD work lists instead of each running job blockIdx.x.  List l holds
+// job indices of the launch's SegTable at order[start[l] .. start[l+1]);
+// workgroup b serves list b % TD_NXCD first (workgroups are dispatched to
+// the XCDs round-robin, so a list's jobs share one L2), then the others.
+// counter[l] is list l's next position; the counters must be zero when the
+// launch starts (launch_zero_counters).  order == nullptr: a direct launch.
+#define TD_NXCD 8
+struct JobQueue {
+    const int32_t* order;
+    const int32_t* start;   // [TD_NXCD + 1]
+    unsigned int* counter;  // [TD_NXCD]
+};
+
 // padded: the solve's zero-padded rows (only lattice columns < M/2 can be
 // non-zero); false: full-length rows (the kernel tables, FP64 only).
+// blocks: the grid (direct launches: one workgroup per job).
 template <typename T>
 hipError_t launch_row_fwd(int M, int C, int blocks, const SegTable<RowFwdJob>& segs,
                           const void* const* ptrs, const FieldPtrs& fp, const void* tw,
                           bool padded, hipStream_t st);
 template <typename T>
 hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& segs,
-                      const void* tw, hipStream_t st);
+                      const void* tw, hipStream_t st, const JobQueue& queue = JobQueue{});
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
                           void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st);
+// Column-pass workgroups of a launch shape that one CU holds at once, for
+// sizing persistent grids.
+int col_resident_blocks(bool f64, int M, int C, int G);
+// Zero n work-list counters on stream st.
+hipError_t launch_zero_counters(unsigned int* c, int n, hipStream_t st);
 // quarter: bit 0 = quarter-real layout (same-level spectra), bit 1 = the
 // potential kernel family (its parities decide real vs imaginary planes)
 template <typename TO>

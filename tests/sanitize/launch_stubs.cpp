@@ -15,7 +15,8 @@ hipError_t launch_row_fwd(int, int, int, const SegTable<RowFwdJob>&, const void*
     return hipErrorInvalidValue;
 }
 template <typename T>
-hipError_t launch_col(int, int, int, int, const SegTable<ColJob>&, const void*, hipStream_t)
+hipError_t launch_col(int, int, int, int, const SegTable<ColJob>&, const void*, hipStream_t,
+                      const JobQueue&)
 {
     return hipErrorInvalidValue;
 }
@@ -31,6 +32,8 @@ hipError_t launch_spec_col(int, int, const void*, void*, const void*, int, hipSt
     return hipErrorInvalidValue;
 }
 hipError_t launch_table(const TableJob&, hipStream_t) { return hipErrorInvalidValue; }
+int col_resident_blocks(bool, int, int, int) { return 1; }
+hipError_t launch_zero_counters(unsigned int*, int, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_count_nonfinite(bool, const void*, int64_t, unsigned long long*, hipStream_t)
 {
     return hipErrorInvalidValue;
@@ -49,9 +52,9 @@ template hipError_t launch_row_fwd<double>(int, int, int, const SegTable<RowFwdJ
                                            const void* const*, const FieldPtrs&, const void*,
                                            bool, hipStream_t);
 template hipError_t launch_col<float>(int, int, int, int, const SegTable<ColJob>&, const void*,
-                                      hipStream_t);
+                                      hipStream_t, const JobQueue&);
 template hipError_t launch_col<double>(int, int, int, int, const SegTable<ColJob>&, const void*,
-                                       hipStream_t);
+                                       hipStream_t, const JobQueue&);
 template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
                                           void* const*, const FieldPtrs&, const void*,
                                           hipStream_t);

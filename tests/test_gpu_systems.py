@@ -55,8 +55,9 @@ def _host(outs):
     return [tuple([t.double().cpu().numpy() for t in lst] for lst in pair) for pair in outs]
 
 
+@pytest.mark.parametrize("launch", ["persistent", "direct"])
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_equals_single_solves(ctx, use_graph):
+def test_batch_equals_single_solves(ctx, use_graph, launch):
     import torch
     import paper_1603_03142_amd as td
     hiers = _mix()
@@ -71,9 +72,48 @@ def test_batch_equals_single_solves(ctx, use_graph):
         single.append((fx, fy))
     torch.cuda.synchronize()
     batch = td.Batch(ctx, plans)
+    batch.set_launch(launch)
     res = batch.solve(fields, use_graph=use_graph)
     torch.cuda.synchronize()
     for (ax, ay), (bx, by) in zip(_host(single), _host(res)):
+        for a, b in zip(ax + ay, bx + by):
+            assert np.array_equal(a, b)
+    batch.close()
+
+
+def test_persistent_launches_equal_direct(ctx):
+    """Deep hierarchies of several lengths in one batch: the persistent
+    column launches (work lists per XCD, stealing, counters zeroed by a
+    kernel ahead of each solve) give the direct launches' results bit for
+    bit, eagerly and on every graph replay, with the launch mode switched
+    between."""
+    import torch
+    import paper_1603_03142_amd as td
+    rng = np.random.Generator(np.random.PCG64(808))
+    hiers = [synth._random_nested(rng, n, lv) for n, lv in
+             ((256, 3), (128, 4), (512, 2), (64, 1), (256, 2), (128, 3), (64, 2), (256, 4))]
+    plans = [ctx.plan(h, "f32") for h in hiers]
+    fields = [_dev_fields(h, 300 + k, "f32")[0] for k, h in enumerate(hiers)]
+    batch = td.Batch(ctx, plans)
+    batch.set_launch("direct")
+    want = _host(batch.solve(fields))
+    torch.cuda.synchronize()
+    batch.set_launch("persistent")
+    outs = [p.outputs() for p in plans]
+    for rep, graph in enumerate((False, False, True, True, True)):
+        print(f"persistent batch: solve {rep} graph={graph}", flush=True)
+        batch.solve(fields, outs=outs, use_graph=graph)
+        torch.cuda.synchronize()
+        for k, ((ax, ay), (bx, by)) in enumerate(zip(want, _host(outs))):
+            for a, b in zip(ax + ay, bx + by):
+                assert np.array_equal(a, b), f"solve {rep} member {k}"
+        for o in outs:
+            for t in o[0] + o[1]:
+                t.fill_(float("nan"))
+    batch.set_launch("direct")
+    again = _host(batch.solve(fields, use_graph=True))
+    torch.cuda.synchronize()
+    for (ax, ay), (bx, by) in zip(want, again):
         for a, b in zip(ax + ay, bx + by):
             assert np.array_equal(a, b)
     batch.close()
