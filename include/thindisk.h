@@ -253,16 +253,18 @@ td_status td_batch_solve(td_batch* batch, const td_request* reqs, int use_graph,
 td_status td_batch_footprint(const td_batch* batch, size_t* workspace_bytes);
 /* How the batch launches its column pass (the fused column FFTs and
  * spectral products; the row passes always run one workgroup per job).
- * TD_LAUNCH_PERSISTENT (the default): each column launch has a grid of
- * about as many workgroups as the device holds at once, and each workgroup
- * takes jobs from work lists built at creation, one per XCD (the jobs of
- * one spectral column together, longest first); a workgroup whose list is
+ * TD_LAUNCH_DIRECT (the default): one workgroup per job, dispatched by the
+ * hardware.  TD_LAUNCH_PERSISTENT: each column launch has a grid of about
+ * as many workgroups as the device holds at once, and each workgroup takes
+ * jobs from work lists built at creation, one per XCD (the jobs of one
+ * spectral column together, longest first); a workgroup whose list is
  * drained takes jobs from the others.  The lists' counters live in the
  * batch and are zeroed by a kernel ahead of each solve (also inside a
  * captured graph), so two solves of one batch must not run concurrently,
- * as for its workspace.  TD_LAUNCH_DIRECT: one workgroup per job.  Results
- * are identical.  Changing the mode drops a captured graph (after waiting
- * for the device). */
+ * as for its workspace.  Results are identical; on the 64-disk batch the
+ * persistent launches measured 5% slower than direct ones in FP32 and
+ * FP64.  Changing the mode drops a captured graph (after waiting for the
+ * device). */
 #define TD_LAUNCH_DIRECT 0
 #define TD_LAUNCH_PERSISTENT 1
 td_status td_batch_set_launch(td_batch* batch, int32_t mode);

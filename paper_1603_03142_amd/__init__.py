@@ -269,8 +269,9 @@ class Batch:
         return res
 
     def set_launch(self, mode: str):
-        """'persistent' (default: work lists per XCD, about one wave of
-        workgroups per launch) or 'direct' (one workgroup per job)."""
+        """Column-pass launches: 'direct' (default: one workgroup per job)
+        or 'persistent' (work lists per XCD, about one wave of resident
+        workgroups per launch)."""
         m = {"direct": B.TD_LAUNCH_DIRECT, "persistent": B.TD_LAUNCH_PERSISTENT}[mode]
         B.check(lib().td_batch_set_launch(self.handle, m), "td_batch_set_launch")
 

@@ -1895,7 +1895,7 @@ struct td_batch {
     hipStream_t last_stream = nullptr;
     bool pushed = false;
     // persistent launches (td_batch_set_launch): the recorded work queues
-    int launch_mode = TD_LAUNCH_PERSISTENT;
+    int launch_mode = TD_LAUNCH_DIRECT;
     Queues queues;
 };
 

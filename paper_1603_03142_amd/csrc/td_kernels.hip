@@ -606,7 +606,176 @@ __device__ __forceinline__ void store_column(const cpx<T> (&w)[8], char* ws, con
     }
 }
 
+// One column job of the fused column pass (see ColJob).
 template <typename T, int M>
+__device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, cpx<T>* A,
+                                        const cpx<T>* tw, int G, int tid)
+{
+    constexpr int TPS = M / 8;
+    constexpr int SP = lds_stride<T>(M);
+    int slot_unused;
+    const void* aux;
+    char* ws;
+    const ColJob J = segs.find(item, &slot_unused, &aux, &ws);
+    const ColTables tabs = load_const(reinterpret_cast<const ColTables*>(aux), 0);
+    const int slot = tid / TPS, lane_c = tid % TPS;
+    const int lane = lane_c;
+    // uniform over a wavefront when a slot is one (or more): the column,
+    // its validity and every descriptor derived from them stay scalar
+    const int c = slot_uniform<M>(slot / G), g = slot_uniform<M>(slot % G);
+    const int kx = J.kx0 + c;
+    const bool col_ok = c < J.ncol;
+    cpx<T>* a = A + slot * SP;
+    cpx<T>* col0 = A + c * G * SP;  // the column's first slot
+    // Inside the loops the lane index is re-derived through an empty asm
+    // barrier, so that the per-frequency addresses are recomputed in each
+    // iteration instead of being hoisted and held in registers throughout.
+
+    if (J.kind == 0) {
+        cpx<T> ax[8], ay[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
+        // each input's column is loaded one iteration ahead, while the
+        // previous input is transformed and multiplied
+        ColIn In{0, nullptr, 0, 0, 0, 0};
+        bool okn;
+        cpx<T> xn[4];
+        bool vn[4];
+        {
+            const int i = slot_uniform<M>(g);
+            okn = col_ok && i < J.nin;
+            if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
+            load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
+        }
+        for (int r0 = 0; r0 < J.nin; r0 += G) {
+            int lane = lane_c;
+            asm volatile("" : "+v"(lane));
+            const ColIn I = In;
+            const bool ok = okn;
+            cpx<T> v[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
+            {
+                const int i = slot_uniform<M>(r0 + G + g);
+                okn = col_ok && i < J.nin;
+                In = ColIn{0, nullptr, 0, 0, 0, 0};
+                if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
+                load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
+            }
+            // a slot without an input skips its transform when sequences
+            // are ordered within their wavefront only (M/8 <= 64)
+            if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
+            if (ok) {
+                // the kernel columns are read after the transform: holding
+                // them across it costs 32 VGPRs, and the other waves of the
+                // CU hide the read latency better than that (measured)
+                cpx<T> z0[8], z1[8];
+                kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
+                kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
+            }
+        }
+        // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
+        // (slot 0 as well when G == 1)
+        const int gy = G > 1 ? 1 : 0;
+        cpx<T> sx[8], sy[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sx[q] = sy[q] = cpx<T>{0, 0};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ax[q];
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = lds_pos<T>(lane + q * TPS);
+                cpx<T> sum = col0[p];
+                for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
+                sx[q] = sum;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ay[q];
+        __syncthreads();
+        if (g == gy) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = lds_pos<T>(lane + q * TPS);
+                cpx<T> sum = col0[p];
+                for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
+                sy[q] = sum;
+            }
+        }
+        __syncthreads();  // the sums are read: the slots' LDS is free again
+        // inverse column transforms in registers (every slot transforms:
+        // slot 0 Fx, slot gy Fy, the others zeros)
+        cpx<T> w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
+        if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
+        if (col_ok && g == 0) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0), kx, lane);
+        if (col_ok && G > 1 && g == 1)
+            store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
+        if (G == 1) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) w[q] = sy[q];
+            fft_regs<T, M, true, false, true>(w, A, tw);
+            if (col_ok) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
+        }
+        return;
+    }
+
+    // kind 1: transform the three inputs, keeping this thread's frequencies
+    // of all three in registers
+    cpx<T> vin[3][8];
+    for (int r0 = 0; r0 < 3; r0 += G) {
+        const int i = slot_uniform<M>(r0 + g);
+        const bool ok = col_ok && i < 3;
+        ColIn I{0, nullptr, 0, 0, 0, 0};
+        if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
+        cpx<T> v[8];
+        load_column<T, M>(v, ws, I, kx, ok, lane);
+        fft_regs<T, M, false, true>(v, A, tw);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = v[q];
+        __syncthreads();  // every slot reads the three transformed inputs
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (f >= r0 && f < r0 + G) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos<T>(lane + q * TPS)];
+            }
+        }
+        __syncthreads();
+    }
+    for (int o0 = 0; o0 < J.nout; o0 += G) {
+        int lane = lane_c;
+        asm volatile("" : "+v"(lane));
+        const int o = slot_uniform<M>(o0 + g);
+        const bool ok = col_ok && o < J.nout;
+        cpx<T> acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
+        ColOut O{0, nullptr, 0, 0, 0, 0};
+        if (ok) {
+            O = load_desc<M>(tabs.outs, J.out0 + o);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                cpx<T> z[8];
+                kern_load<T, M>(z, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
+                kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
+            }
+        }
+        if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);
+        if (ok) store_column<T, M>(acc, ws, O, kx, lane);
+    }
+}
+
+// PQ: a persistent launch (jobs pulled from the work lists of q); else one
+// workgroup per job.  Separate instantiations: the job loop costs the direct
+// launch registers and scalar uniformity.
+template <typename T, int M, bool PQ>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
                                                         const cpx<T>* __restrict__ tw_g, int G,
                                                         const JobQueue q)
@@ -618,165 +787,17 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* tw = A + S * SP;
     stage_twiddles<T, M>(tw, tw_g);
-    __shared__ int s_item[2];
-    for (int item = first_job(q, s_item); item >= 0; item = next_job(q, s_item)) {
-        int slot_unused;
-        const void* aux;
-        char* ws;
-        const ColJob J = segs.find(item, &slot_unused, &aux, &ws);
-        const ColTables tabs = load_const(reinterpret_cast<const ColTables*>(aux), 0);
-        const int slot = threadIdx.x / TPS, lane_c = threadIdx.x % TPS;
-        const int lane = lane_c;
-        // uniform over a wavefront when a slot is one (or more): the column,
-        // its validity and every descriptor derived from them stay scalar
-        const int c = slot_uniform<M>(slot / G), g = slot_uniform<M>(slot % G);
-        const int kx = J.kx0 + c;
-        const bool col_ok = c < J.ncol;
-        cpx<T>* a = A + slot * SP;
-        cpx<T>* col0 = A + c * G * SP;  // the column's first slot
-        // Inside the loops the lane index is re-derived through an empty asm
-        // barrier, so that the per-frequency addresses are recomputed in each
-        // iteration instead of being hoisted and held in registers throughout.
-
-        if (J.kind == 0) {
-            cpx<T> ax[8], ay[8];
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
-            // each input's column is loaded one iteration ahead, while the
-            // previous input is transformed and multiplied
-            ColIn In{0, nullptr, 0, 0, 0, 0};
-            bool okn;
-            cpx<T> xn[4];
-            bool vn[4];
-            {
-                const int i = slot_uniform<M>(g);
-                okn = col_ok && i < J.nin;
-                if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
-                load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
-            }
-            for (int r0 = 0; r0 < J.nin; r0 += G) {
-                int lane = lane_c;
-                asm volatile("" : "+v"(lane));
-                const ColIn I = In;
-                const bool ok = okn;
-                cpx<T> v[8];
-    #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
-                {
-                    const int i = slot_uniform<M>(r0 + G + g);
-                    okn = col_ok && i < J.nin;
-                    In = ColIn{0, nullptr, 0, 0, 0, 0};
-                    if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
-                    load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
-                }
-                // a slot without an input skips its transform when sequences
-                // are ordered within their wavefront only (M/8 <= 64)
-                if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
-                if (ok) {
-                    // the kernel columns are read after the transform: holding
-                    // them across it costs 32 VGPRs, and the other waves of the
-                    // CU hide the read latency better than that (measured)
-                    cpx<T> z0[8], z1[8];
-                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
-                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
-                    kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
-                    kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
-                }
-            }
-            // reduce the slots' partial sums: Fx into slot 0, Fy into slot 1
-            // (slot 0 as well when G == 1)
-            const int gy = G > 1 ? 1 : 0;
-            cpx<T> sx[8], sy[8];
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) sx[q] = sy[q] = cpx<T>{0, 0};
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ax[q];
-            __syncthreads();
-            if (g == 0) {
-    #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int p = lds_pos<T>(lane + q * TPS);
-                    cpx<T> sum = col0[p];
-                    for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
-                    sx[q] = sum;
-                }
-            }
-            __syncthreads();
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = ay[q];
-            __syncthreads();
-            if (g == gy) {
-    #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int p = lds_pos<T>(lane + q * TPS);
-                    cpx<T> sum = col0[p];
-                    for (int h = 1; h < G; ++h) sum = sum + col0[h * SP + p];
-                    sy[q] = sum;
-                }
-            }
-            __syncthreads();  // the sums are read: the slots' LDS is free again
-            // inverse column transforms in registers (every slot transforms:
-            // slot 0 Fx, slot gy Fy, the others zeros)
-            cpx<T> w[8];
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
-            if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
-            if (col_ok && g == 0) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0), kx, lane);
-            if (col_ok && G > 1 && g == 1)
-                store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
-            if (G == 1) {
-    #pragma unroll
-                for (int q = 0; q < 8; ++q) w[q] = sy[q];
-                fft_regs<T, M, true, false, true>(w, A, tw);
-                if (col_ok) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
-            }
-            continue;
+    if constexpr (PQ) {
+        __shared__ int s_item[2];
+        for (int item = first_job(q, s_item); item >= 0; item = next_job(q, s_item)) {
+            // opaque thread index: nothing derived from it is hoisted out
+            // of the job loop and held across jobs
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            col_job<T, M>(segs, item, A, tw, G, tid);
         }
-
-        // kind 1: transform the three inputs, keeping this thread's frequencies
-        // of all three in registers
-        cpx<T> vin[3][8];
-        for (int r0 = 0; r0 < 3; r0 += G) {
-            const int i = slot_uniform<M>(r0 + g);
-            const bool ok = col_ok && i < 3;
-            ColIn I{0, nullptr, 0, 0, 0, 0};
-            if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
-            cpx<T> v[8];
-            load_column<T, M>(v, ws, I, kx, ok, lane);
-            fft_regs<T, M, false, true>(v, A, tw);
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = v[q];
-            __syncthreads();  // every slot reads the three transformed inputs
-    #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                if (f >= r0 && f < r0 + G) {
-    #pragma unroll
-                    for (int q = 0; q < 8; ++q) vin[f][q] = col0[(f - r0) * SP + lds_pos<T>(lane + q * TPS)];
-                }
-            }
-            __syncthreads();
-        }
-        for (int o0 = 0; o0 < J.nout; o0 += G) {
-            int lane = lane_c;
-            asm volatile("" : "+v"(lane));
-            const int o = slot_uniform<M>(o0 + g);
-            const bool ok = col_ok && o < J.nout;
-            cpx<T> acc[8];
-    #pragma unroll
-            for (int q = 0; q < 8; ++q) acc[q] = cpx<T>{0, 0};
-            ColOut O{0, nullptr, 0, 0, 0, 0};
-            if (ok) {
-                O = load_desc<M>(tabs.outs, J.out0 + o);
-    #pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    cpx<T> z[8];
-                    kern_load<T, M>(z, O.kern, kern_of(O.comp, f), kx, O.flip, lane);
-                    kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
-                }
-            }
-            if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);
-            if (ok) store_column<T, M>(acc, ws, O, kx, lane);
-        }
+    } else {
+        col_job<T, M>(segs, blockIdx.x, A, tw, G, threadIdx.x);
     }
 }
 
@@ -1067,7 +1088,10 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
     JobQueue q = queue;
     void* args[] = {&s, &t, &g, &q};
     switch (M) {
-#define X(MM) case MM: return launch_common(k_col<T, MM>, blocks, threads, smem, st, args);
+#define X(MM)                                                                                      \
+    case MM:                                                                                       \
+        return q.order ? launch_common(k_col<T, MM, true>, blocks, threads, smem, st, args)       \
+                       : launch_common(k_col<T, MM, false>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -1138,7 +1162,7 @@ int col_resident_blocks(bool f64, int M, int C, int G)
     const size_t smem = lds_bytes(M, C, es, G);
     switch (M) {
 #define X(MM) \
-    case MM: return f64 ? occupancy(k_col<double, MM>, threads, smem) : occupancy(k_col<float, MM>, threads, smem);
+    case MM: return f64 ? occupancy(k_col<double, MM, true>, threads, smem) : occupancy(k_col<float, MM, true>, threads, smem);
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -1243,7 +1267,8 @@ hipError_t prepare_kernels()
 #define SETA(k) if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 #define X(MM) SETA((k_row_fwd<float, MM, true>)) SETA((k_row_fwd<double, MM, true>)) \
     SETA((k_row_fwd<double, MM, false>)) \
-    SETA((k_col<float, MM>)) SETA((k_col<double, MM>)) \
+    SETA((k_col<float, MM, false>)) SETA((k_col<double, MM, false>)) \
+    SETA((k_col<float, MM, true>)) SETA((k_col<double, MM, true>)) \
     SETA((k_row_inv<float, MM>)) SETA((k_row_inv<double, MM>)) \
     SETA((k_spec_col<float, MM>)) SETA((k_spec_col<double, MM>))
     TD_FOR_EACH_M(X)
