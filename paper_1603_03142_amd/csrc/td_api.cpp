@@ -611,6 +611,7 @@ struct Group {
     std::vector<ColIn> colins;
     std::vector<ColOut> colouts;
     std::vector<RowInvJob> rinv[2];  // [0] write, [1] accumulate
+    int nq[2] = {1, 1};              // row inverse: most outputs per thread and row
     std::vector<RowInvContrib> contribs;
     // device copies
     RowFwdJob* d_rowfwd = nullptr;
@@ -937,13 +938,14 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     // ---- XCD affinity of the column pass.  Workgroups are dispatched to
     // the eight XCDs round-robin, each with its own L2; every job of one
     // spectral column reads the same stored kernel columns (same lattice,
-    // same spectra).  Placing the jobs of column kx at list positions
-    // congruent to kx mod 8 keeps each column's kernel reads in one L2, and
-    // each residue's jobs run longest first.
+    // same spectra).  Placing the jobs of column group kx0 / C at list
+    // positions congruent to it mod 8 keeps each column's kernel reads in
+    // one L2, and each residue's jobs run longest first.
     for (auto& g : P->groups) {
         constexpr int NX = 8;
         std::vector<ColJob> bucket[NX];
-        for (const ColJob& j : g.col) bucket[j.kx0 % NX].push_back(j);
+        const int C = g.C[P_COL];  // columns per job: kx0 is a multiple of C
+        for (const ColJob& j : g.col) bucket[(j.kx0 / C) % NX].push_back(j);
         auto cost = [](const ColJob& j) { return j.kind == 0 ? j.nin : 3 + j.nout; };
         for (auto& b : bucket)
             std::stable_sort(b.begin(), b.end(), [&](const ColJob& a, const ColJob& c) { return cost(a) > cost(c); });
@@ -1032,6 +1034,38 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             }
         }
     }
+    for (auto& g : P->groups)
+        for (int a = 0; a < 2; ++a) {
+            const int per = g.G[P_ROWINV] * (g.M / 8);
+            for (auto& j : g.rinv[a]) g.nq[a] = std::max(g.nq[a], (j.nx + per - 1) / per);
+        }
+    // ---- XCD placement of the row inverse.  Workgroups are dispatched to
+    // the eight XCDs round-robin (list position p runs on XCD p mod 8, up to
+    // a rotation that is the same for the whole list), each with its own L2.
+    // A job reads, per frequency, a few consecutive stored rows of each
+    // contribution plane; one cache line holds the rows of 16 m target rows
+    // (f32; 8 m in f64) for a coarser source at ratio m.  Each level's jobs
+    // are cut into eight contiguous runs of target rows, one per XCD, so a
+    // line is fetched by one or two XCDs rather than by all eight, and every
+    // XCD gets the same share of every level's work.
+    for (auto& g : P->groups)
+        for (int a = 0; a < 2; ++a) {
+            std::vector<RowInvJob>& jobs = g.rinv[a];
+            std::vector<std::vector<RowInvJob>> bins(8);
+            for (size_t i = 0; i < jobs.size();) {
+                size_t e = i;
+                while (e < jobs.size() && jobs[e].lvl == jobs[i].lvl) ++e;
+                const size_t n = e - i;
+                for (size_t k = 0; k < n; ++k) bins[k * 8 / n].push_back(jobs[i + k]);
+                i = e;
+            }
+            std::vector<RowInvJob> order;
+            order.reserve(jobs.size());
+            for (size_t r = 0; order.size() < jobs.size(); ++r)
+                for (auto& b : bins)
+                    if (r < b.size()) order.push_back(b[r]);
+            jobs.swap(order);
+        }
     return TD_OK;
 }
 
@@ -1162,7 +1196,8 @@ td_status validate_jobs(td_plan* P)
                     j.ny_t != P->lv[j.lvl].ny || j.ox_t != P->lv[j.lvl].ox || j.oy_t != P->lv[j.lvl].oy)
                     return bad("rinv level");
                 if (j.y0 < 0 || j.ny < 1 || j.ny > g.C[P_ROWINV] || j.y0 + j.ny > j.ny_t) return bad("rinv rows");
-                if (j.x0 < 0 || j.nx < 1 || j.x0 + j.nx > j.nx_t || (long)j.nx > 2L * M)
+                if (j.x0 < 0 || j.nx < 1 || j.x0 + j.nx > j.nx_t || (long)j.nx > 2L * M ||
+                    j.nx > (long)g.nq[a] * g.G[P_ROWINV] * (M / 8))
                     return bad("rinv columns");
                 if (j.c0 < 0 || j.c0 + j.nc > (int)g.contribs.size()) return bad("rinv contribs");
                 if (j.oy_t < 0 || j.ox_t < 0) return bad("rinv offsets");
@@ -1374,7 +1409,7 @@ struct Queues {
 };
 
 // Record one persistent column launch over the jobs of `segs` (in launch
-// order).  A job goes to the list of its spectral column mod TD_NXCD (the
+// order).  A job goes to the list of its column group kx0 / C mod TD_NXCD (the
 // jobs of one column read the same kernel columns: one L2), unless that
 // list already holds its share of the launch's work; then to the least
 // loaded list.  Jobs are placed and listed longest first, so that the
@@ -1391,7 +1426,7 @@ void record_col_launch(const td_context* ctx, const std::vector<std::pair<const 
         for (int k = 0; k < sg.second; ++k) {
             const ColJob& j = sg.first[k];
             const int cost = j.kind == 0 ? std::max(1, j.nin) : 3 + j.nout;
-            items.push_back({cost, j.kx0 % TD_NXCD, base + k});
+            items.push_back({cost, (j.kx0 / C) % TD_NXCD, base + k});
             total += cost;
         }
         base += sg.second;
@@ -1523,9 +1558,11 @@ td_status launch_members(td_context* ctx, td_dtype dt, const std::vector<Member>
                                  gs.second->slot_base, (const void*)gs.first->d_rinv_tabs,
                                  gs.second->ws);
                     if (qs && qs->building) continue;
+                    int nq = 1;
+                    for (auto& gs : kv.second) nq = std::max(nq, gs.first->nq[a]);
                     for (size_t i = 0; i < t.size() && e == hipSuccess; ++i)
-                        e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st)
-                                : launch_row_inv<float>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st);
+                        e = f64 ? launch_row_inv<double>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st, nq)
+                                : launch_row_inv<float>(M, C, Gs, n[i], t[i], d_ptrs, fp, tw, st, nq);
                 }
                 if (e != hipSuccess)
                     return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
@@ -1621,8 +1658,10 @@ td_status launch_plan_direct(const td_plan* P, char* ws, const FieldPtrs& fp, hi
                 const int n = (int)g.rinv[a].size();
                 if (!n) continue;
                 const auto t = single_seg<RowInvJob>(g.d_rinv[a], n, 0, (const void*)g.d_rinv_tabs, ws);
-                e = f64 ? launch_row_inv<double>(g.M, g.C[P_ROWINV], g.G[P_ROWINV], n, t, nullptr, fp, g.tw, st)
-                        : launch_row_inv<float>(g.M, g.C[P_ROWINV], g.G[P_ROWINV], n, t, nullptr, fp, g.tw, st);
+                e = f64 ? launch_row_inv<double>(g.M, g.C[P_ROWINV], g.G[P_ROWINV], n, t, nullptr, fp, g.tw, st,
+                                                 g.nq[a])
+                        : launch_row_inv<float>(g.M, g.C[P_ROWINV], g.G[P_ROWINV], n, t, nullptr, fp, g.tw, st,
+                                                g.nq[a]);
             }
             if (e != hipSuccess) return fail(TD_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
         }

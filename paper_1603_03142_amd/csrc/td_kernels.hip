@@ -816,7 +816,9 @@ __device__ __forceinline__ int ratio_div(int a, int m, int sh)
 // row's G slots.  Spectra are read transposed ([kx][row]), rows fastest.
 // The G M/8 threads of a row own its target columns x0 + t + k G M/8 and
 // accumulate them in registers over all items.
-template <typename T, int M>
+// NQ: outputs per thread and row (nx <= NQ G M/8 for every job of the
+// launch): 4 covers a level's own lattice (nx <= M/2), 16 any job (nx <= 2M).
+template <typename T, int M, int NQ>
 __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> segs,
                                                   void* const* __restrict__ ptrs,
                                                   const FieldPtrs fp,
@@ -831,35 +833,36 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
     const int GT = G * TPS;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* tw = A + S * SP;
-    // per slot of the current round: contribution (-1: none), x-phase, and
-    // the contribution's ratio shift, origin column, leading dimension and
-    // x-to-y plane distance; per (slot, row) sequence the workspace byte
-    // offset of its stored row in the x plane (-1: none)
-    __shared__ int it_c[16], it_kxp[16], it_sh[16], it_oxs[16], it_ld[16];
-    __shared__ int64_t it_cs[16];
-    __shared__ int64_t it_off[TD_MAX_THREADS / 2];
+    // per slot of a round (two rounds in flight: buffers 0 and 1):
+    // contribution (-1: none), x-phase, the contribution's ratio shift and
+    // origin column
+    __shared__ int it_c[2][16], it_kxp[2][16], it_sh[2][16], it_oxs[2][16];
     stage_twiddles<T, M>(tw, tw_g);
     int slot_base;
     const void* aux;
     char* ws;
-    const RowInvJob J = segs.find(xcd_block(blockIdx.x, gridDim.x), &slot_base, &aux, &ws);
+    const RowInvJob J = segs.find(blockIdx.x, &slot_base, &aux, &ws);
     const RowInvTables tabs = *reinterpret_cast<const RowInvTables*>(aux);
     const RowInvContrib* __restrict__ contribs = tabs.contribs + J.c0;
     gpatches L = (gpatches)tabs.levels + J.lvl;
     int nitems = 0;
     for (int k = 0; k < J.nc; ++k) nitems += contribs[k].m;
-    constexpr int NQ = 16;  // nx <= 2M = 16 M/8 <= 16 G M/8
     const int crow = threadIdx.x / GT, t = threadIdx.x % GT;
     T accx[NQ], accy[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) { accx[q] = 0; accy[q] = 0; }
-    // C and G are powers of two: sequence index -> (slot, row) by shifts
+    // C and G are powers of two.  blockDim = S M/8, so the loads of thread
+    // x always serve sequence sq = x mod S (slot gg, row cc), frequencies
+    // kx0 + k M/8: the threads of one kx read consecutive stored rows.
     const int lgC = __builtin_ctz(C), lgS = __builtin_ctz(S);
-    for (int r0 = 0; r0 < nitems; r0 += G) {
+    const int sq = threadIdx.x & (S - 1), gg_l = sq >> lgC, cc_l = sq & (C - 1);
+    const int kx0 = threadIdx.x >> lgS;
+    constexpr int NL = (H + TPS - 1) / TPS;  // frequencies per thread (5)
+    // the slot table of the round starting at item r0, into buffer b
+    auto tables = [&](int r0, int b) {
         if (threadIdx.x < G) {
             const int it = r0 + threadIdx.x;
-            int c = -1, kxp = 0, sh = 0, oxs = 0, ld = 0;
-            int64_t cs = 0;
+            int c = -1, kxp = 0, sh = 0, oxs = 0;
             if (it < nitems) {
                 int k = 0, rem = it;
                 while (rem >= contribs[k].m) rem -= contribs[k].m, ++k;
@@ -867,63 +870,72 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_inv(SegTable<RowInvJob> 
                 kxp = rem;
                 sh = contribs[k].mshift >= 0 ? contribs[k].mshift : -contribs[k].m;
                 oxs = contribs[k].ox_s;
-                ld = contribs[k].ld;
-                cs = contribs[k].comp_stride;
             }
-            it_c[threadIdx.x] = c;
-            it_kxp[threadIdx.x] = kxp;
-            it_sh[threadIdx.x] = sh;
-            it_oxs[threadIdx.x] = oxs;
-            it_ld[threadIdx.x] = ld;
-            it_cs[threadIdx.x] = cs;
+            it_c[b][threadIdx.x] = c;
+            it_kxp[b][threadIdx.x] = kxp;
+            it_sh[b][threadIdx.x] = sh;
+            it_oxs[b][threadIdx.x] = oxs;
         }
-        __syncthreads();
-        // the stored row each (slot, row) sequence reads: the target row's
-        // coarse-lattice row and y-phase (Case 3'), the slot's x-phase
-        for (int sq = threadIdx.x; sq < S; sq += blockDim.x) {
-            const int gg = sq >> lgC, cc = sq & (C - 1);
-            const int ci = it_c[gg];
-            int64_t off = -1;
-            if (ci >= 0 && cc < J.ny) {
-                const RowInvContrib& Q = contribs[ci];
-                const int gy = J.oy_t + J.y0 + cc;  // >= 0
-                const int Jc = ratio_div(gy, Q.m, Q.mshift), kyp = gy - Jc * Q.m;
-                const int sr = Jc - Q.oy_s - Q.lr_first;
-                off = Q.base + ((int64_t)(kyp * Q.m + it_kxp[gg]) * Q.phase_stride + sr) *
-                                   (int64_t)sizeof(cpx<T>);
+    };
+    // this thread's loads of the round in buffer b (the stored row of its
+    // sequence: the target row's coarse-lattice row and y-phase, Case 3',
+    // and the slot's x-phase), held in registers until stored to LDS
+    cpx<T> px[NL], py[NL];
+    auto issue = [&](int b) {
+        const int ci = it_c[b][gg_l];
+        gptr<cpx<T>> P = nullptr;
+        int64_t ld = 0, cs = 0;
+        if (ci >= 0 && cc_l < J.ny) {
+            const RowInvContrib& Q = contribs[ci];
+            const int gy = J.oy_t + J.y0 + cc_l;  // >= 0
+            const int Jc = ratio_div(gy, Q.m, Q.mshift), kyp = gy - Jc * Q.m;
+            const int sr = Jc - Q.oy_s - Q.lr_first;
+            P = (gptr<cpx<T>>)(ws + Q.base) + ((int64_t)(kyp * Q.m + it_kxp[b][gg_l]) * Q.phase_stride + sr);
+            ld = Q.ld;
+            cs = Q.comp_stride;
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int kx = kx0 + k * TPS;
+            px[k] = py[k] = cpx<T>{0, 0};
+            if (P && kx < H) {
+                px[k] = ldg<T>(P, (int64_t)kx * ld);
+                py[k] = ldg<T>(P, (int64_t)kx * ld + cs);
             }
-            it_off[sq] = off;
         }
-        __syncthreads();
-        // load: element e -> (sequence = slot x row, frequency kx), rows
-        // fastest, so the threads of one kx read consecutive stored rows
-        for (int e = threadIdx.x; e < S * H; e += blockDim.x) {
-            const int sq = e & (S - 1), kx = e >> lgS;
-            const int gg = sq >> lgC, cc = sq & (C - 1);
-            const int64_t off = it_off[sq];
-            cpx<T> z{0, 0}, zr{0, 0};
-            if (off >= 0) {
-                gptr<cpx<T>> P = (gptr<cpx<T>>)(ws + off) + (int64_t)kx * it_ld[gg];
-                cpx<T> X = ldg<T>(P, 0);
-                cpx<T> Y = ldg<T>(P, it_cs[gg]);
-                if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
-                z = cpx<T>{X.re - Y.im, X.im + Y.re};
-                zr = cpx<T>{X.re + Y.im, Y.re - X.im};
-            }
-            cpx<T>* row = A + (cc * G + gg) * SP;
-            row[lds_pos<T>(kx)] = z;
-            if (kx > 0 && kx < M / 2) row[lds_pos<T>(M - kx)] = zr;
+    };
+    tables(0, 0);
+    __syncthreads();
+    issue(0);
+    int b = 0;
+    for (int r0 = 0; r0 < nitems; r0 += G, b ^= 1) {
+        // the round's values into LDS: sequence = x + i y of the row's two
+        // components, Hermitian-extended
+        cpx<T>* rowp = A + (cc_l * G + gg_l) * SP;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int kx = kx0 + k * TPS;
+            if (kx >= H) break;
+            cpx<T> X = px[k], Y = py[k];
+            if (kx == 0 || kx == M / 2) { X.im = 0; Y.im = 0; }
+            rowp[lds_pos<T>(kx)] = cpx<T>{X.re - Y.im, X.im + Y.re};
+            if (kx > 0 && kx < M / 2) rowp[lds_pos<T>(M - kx)] = cpx<T>{X.re + Y.im, Y.re - X.im};
         }
+        const bool more = r0 + G < nitems;
+        if (more) tables(r0 + G, b ^ 1);
         __syncthreads();
+        // the next round's loads are in flight during this round's
+        // transform and gather
+        if (more) issue(b ^ 1);
         // a slot without an item need not transform (its zeros are never
         // read); with M/8 <= 64 a sequence is ordered within its wavefront
         // only, so skipping it cannot unbalance a workgroup barrier
-        if (M / 8 > 64 || it_c[(threadIdx.x / TPS) % G] >= 0) fft_lds<T, M, true, false, true>(A, tw);
+        if (M / 8 > 64 || it_c[b][(threadIdx.x / TPS) % G] >= 0) fft_lds<T, M, true, false, true>(A, tw);
         __syncthreads();  // outputs gather from every slot of their row
         for (int gg = 0; gg < G; ++gg) {
-            if (it_c[gg] < 0) break;
+            if (it_c[b][gg] < 0) break;
             // it_sh: log2(m), or -m when m is not a power of two
-            const int sh = it_sh[gg], kxp = it_kxp[gg], oxs = it_oxs[gg];
+            const int sh = it_sh[b][gg], kxp = it_kxp[b][gg], oxs = it_oxs[b][gg];
             const int mm = sh >= 0 ? 1 << sh : -sh;
             const cpx<T>* rowv = A + (crow * G + gg) * SP;
 #pragma unroll
@@ -1100,9 +1112,11 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
 
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
-                          void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st)
+                          void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st,
+                          int nq)
 {
     if (blocks <= 0) return hipSuccess;
+    if (nq < 1 || nq > 16) return hipErrorInvalidValue;
     const int threads = C * G * (M / 8);
     const size_t smem = lds_bytes(M, C, sizeof(cpx<T>), G);
     SegTable<RowInvJob> s = segs;
@@ -1112,7 +1126,10 @@ hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInv
     int g = G;
     void* args[] = {&s, &p, &f, &t, &g};
     switch (M) {
-#define X(MM) case MM: return launch_common(k_row_inv<T, MM>, blocks, threads, smem, st, args);
+#define X(MM)                                                                                   \
+    case MM:                                                                                    \
+        return nq <= 4 ? launch_common(k_row_inv<T, MM, 4>, blocks, threads, smem, st, args)    \
+                       : launch_common(k_row_inv<T, MM, 16>, blocks, threads, smem, st, args);
         TD_FOR_EACH_M(X)
 #undef X
     }
@@ -1217,9 +1234,9 @@ template hipError_t launch_col<float>(int, int, int, int, const SegTable<ColJob>
 template hipError_t launch_col<double>(int, int, int, int, const SegTable<ColJob>&, const void*,
                                        hipStream_t, const JobQueue&);
 template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
-                                          void* const*, const FieldPtrs&, const void*, hipStream_t);
+                                          void* const*, const FieldPtrs&, const void*, hipStream_t, int);
 template hipError_t launch_row_inv<double>(int, int, int, int, const SegTable<RowInvJob>&,
-                                           void* const*, const FieldPtrs&, const void*, hipStream_t);
+                                           void* const*, const FieldPtrs&, const void*, hipStream_t, int);
 template hipError_t launch_spec_col<float>(int, int, const void*, void*, const void*, int,
                                            hipStream_t);
 template hipError_t launch_spec_col<double>(int, int, const void*, void*, const void*, int,
@@ -1269,7 +1286,8 @@ hipError_t prepare_kernels()
     SETA((k_row_fwd<double, MM, false>)) \
     SETA((k_col<float, MM, false>)) SETA((k_col<double, MM, false>)) \
     SETA((k_col<float, MM, true>)) SETA((k_col<double, MM, true>)) \
-    SETA((k_row_inv<float, MM>)) SETA((k_row_inv<double, MM>)) \
+    SETA((k_row_inv<float, MM, 4>)) SETA((k_row_inv<double, MM, 4>)) \
+    SETA((k_row_inv<float, MM, 16>)) SETA((k_row_inv<double, MM, 16>)) \
     SETA((k_spec_col<float, MM>)) SETA((k_spec_col<double, MM>))
     TD_FOR_EACH_M(X)
 #undef X

@@ -84,6 +84,8 @@ struct JobQueue {
     unsigned int* counter;  // [TD_NXCD]
 };
 
+// Row inverse: nq = the most outputs per thread and row of any job of the
+// launch, ceil(nx / (G M/8)) <= 16.
 // padded: the solve's zero-padded rows (only lattice columns < M/2 can be
 // non-zero); false: full-length rows (the kernel tables, FP64 only).
 // blocks: the grid (direct launches: one workgroup per job).
@@ -96,7 +98,8 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
                       const void* tw, hipStream_t st, const JobQueue& queue = JobQueue{});
 template <typename T>
 hipError_t launch_row_inv(int M, int C, int G, int blocks, const SegTable<RowInvJob>& segs,
-                          void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st);
+                          void* const* ptrs, const FieldPtrs& fp, const void* tw, hipStream_t st,
+                          int nq);
 // Column-pass workgroups of a launch shape that one CU holds at once, for
 // sizing persistent grids.
 int col_resident_blocks(bool f64, int M, int C, int G);

@@ -22,7 +22,7 @@ hipError_t launch_col(int, int, int, int, const SegTable<ColJob>&, const void*, 
 }
 template <typename T>
 hipError_t launch_row_inv(int, int, int, int, const SegTable<RowInvJob>&, void* const*,
-                          const FieldPtrs&, const void*, hipStream_t)
+                          const FieldPtrs&, const void*, hipStream_t, int)
 {
     return hipErrorInvalidValue;
 }
@@ -57,10 +57,10 @@ template hipError_t launch_col<double>(int, int, int, int, const SegTable<ColJob
                                        hipStream_t, const JobQueue&);
 template hipError_t launch_row_inv<float>(int, int, int, int, const SegTable<RowInvJob>&,
                                           void* const*, const FieldPtrs&, const void*,
-                                          hipStream_t);
+                                          hipStream_t, int);
 template hipError_t launch_row_inv<double>(int, int, int, int, const SegTable<RowInvJob>&,
                                            void* const*, const FieldPtrs&, const void*,
-                                           hipStream_t);
+                                           hipStream_t, int);
 template hipError_t launch_spec_col<float>(int, int, const void*, void*, const void*, int,
                                            hipStream_t);
 template hipError_t launch_spec_col<double>(int, int, const void*, void*, const void*, int,
