@@ -322,6 +322,39 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     const int np = L->np;
     const int rend = J.row0 + J.nrow;
     constexpr int NG = ZP ? M / 2 : M;  // columns gathered
+    if (np == 1 && L->nc <= 1) {
+        // one patch, at most one covered square (every level of a nested
+        // hierarchy): the patch's and square's bounds are read once, into
+        // scalar registers, instead of per element
+        const uintptr_t raw = (uintptr_t)(fp.n ? fp.p[slot_base + L->pslot[0] + J.f]
+                                               : ptrs[slot_base + L->pslot[0] + J.f]);
+        const T* src = reinterpret_cast<const T*>(raw & ~(uintptr_t)1);
+        const bool est = raw & 1;
+        const int n = L->pn[0], pi0 = L->pi0[0], pj0 = L->pj0[0];
+        const bool hc = L->nc == 1;
+        const int ci0 = hc ? L->ci0[0] : 0, cj0 = hc ? L->cj0[0] : 0, cn = hc ? L->cn[0] : 0;
+        for (int idx = threadIdx.x; idx < C * NG; idx += blockDim.x) {
+            const int p = idx / NG, lc = idx % NG;
+            T a = 0, b = 0;
+            const int s0 = J.row0 + 2 * p;
+            const int scol = J.m * lc + J.col_off;
+            const int i = scol - pi0;
+            // lattice columns outside the source level's window, or outside
+            // the patch, read nothing
+            if (src && lc >= J.lc_lo && lc < J.lc_hi && i >= 0 && i < n) {
+                const int sr0 = J.m * (J.lr_first + s0) + J.row_off, sr1 = sr0 + J.m;
+                const int j0 = sr0 - pj0, j1 = sr1 - pj0;
+                const bool cx = scol >= ci0 && scol < ci0 + cn;
+                if (s0 < rend && j0 >= 0 && j0 < n && !(cx && sr0 >= cj0 && sr0 < cj0 + cn))
+                    a = est ? (T)(J.est_scale * cell_slope(src, n, i, j0, J.f))
+                            : (T)(J.scale * (double)src[(size_t)j0 * n + i]);
+                if (s0 + 1 < rend && j1 >= 0 && j1 < n && !(cx && sr1 >= cj0 && sr1 < cj0 + cn))
+                    b = est ? (T)(J.est_scale * cell_slope(src, n, i, j1, J.f))
+                            : (T)(J.scale * (double)src[(size_t)j1 * n + i]);
+            }
+            buf[p * SP + lds_pos<T>(lc)] = cpx<T>{a, b};
+        }
+    } else
     for (int idx = threadIdx.x; idx < C * NG; idx += blockDim.x) {
         const int p = idx / NG, lc = idx % NG;
         if (lc < J.lc_lo || lc >= J.lc_hi) {  // outside the source level's window
