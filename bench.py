@@ -48,7 +48,11 @@ DEFAULT_WORKLOAD = "four-level-512"
 # pass) and tied to the SHA-256 of the sources they were taken on -- the
 # kernels and the plan builder, whose jobs and launch shapes decide the
 # traffic too: a changed source reports null until it is profiled again.
-TRAFFIC = {}
+TRAFFIC = {
+    ("four-level-512", "f32", "given", "row_fwd"): (244483428, "4c3a8848be9cd64c"),
+    ("four-level-512", "f32", "given", "col"): (3309198664, "4c3a8848be9cd64c"),
+    ("four-level-512", "f32", "given", "row_inv"): (152799321, "4c3a8848be9cd64c"),
+}
 
 
 @contextlib.contextmanager
