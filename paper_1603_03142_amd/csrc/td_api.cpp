@@ -910,14 +910,16 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
         }
         // (b) Case-3 phases of this (coarser) level onto every finer target:
         // the level's three own planes (the first inputs above) are
-        // transformed again by every job; a job forms up to 16 G outputs
+        // transformed again by every job, so a job takes the outputs of all
+        // finer targets in a row (up to 256 of them: about the length of
+        // the longest own-force job)
+        const int c3_out0 = (int)g.colouts.size();
         for (int s = t + 1; s < L; ++s) {
             const LevelG& T = P->lv[s];
             const int m = ipow(r, s - t), ld = c3_ld[t][s];
             const SpecEntry* k3 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 3, m, &k3));
             const size_t per_phase = 6 * H * G.M;
-            const int out0 = (int)g.colouts.size();
             for (const auto& ph : phase_order(m)) {
                 const int kx = ph.first, ky = ph.second;
                 const int phase = ky * m + kx;
@@ -927,13 +929,13 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                     g.colouts.push_back({ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld), kern, ld,
                                          floor_div(T.oy, m) - G.oy, comp, flip | fam});
             }
-            const int nout = (int)g.colouts.size() - out0;
-            const int chunk = 16 * Gs;
-            for (int kx0 = 0; kx0 < (int)H; kx0 += C)
-                for (int o0 = 0; o0 < nout; o0 += chunk)
-                    g.col.push_back({1, kx0, std::min(C, (int)H - kx0), in0, 3, out0 + o0,
-                                     std::min(chunk, nout - o0), 0});
         }
+        const int nout = (int)g.colouts.size() - c3_out0;
+        const int chunk = std::max(16 * Gs, 256);
+        for (int kx0 = 0; kx0 < (int)H; kx0 += C)
+            for (int o0 = 0; o0 < nout; o0 += chunk)
+                g.col.push_back({1, kx0, std::min(C, (int)H - kx0), in0, 3, c3_out0 + o0,
+                                 std::min(chunk, nout - o0), 0});
     }
     // ---- XCD affinity of the column pass.  Workgroups are dispatched to
     // the eight XCDs round-robin, each with its own L2; every job of one
