@@ -387,22 +387,29 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
     __syncthreads();
     fft_lds<T, M, false, ZP>(buf, tw);
     __syncthreads();  // the transposed write reads every sequence
+    // each thread unpacks both rows of one sequence at one frequency (the
+    // two real rows' spectra from z(kx) and conj z(M - kx)) and stores them
+    // with one 16-byte store: the lanes of a frequency write its 2C rows
+    // contiguously
     cpx<T>* out = reinterpret_cast<cpx<T>*>(ws + J.out);
-    const int R = 2 * C;
-    for (int idx = threadIdx.x; idx < (M / 2 + 1) * R; idx += blockDim.x) {
-        const int r = idx % R, kx = idx / R;
+    for (int idx = threadIdx.x; idx < (M / 2 + 1) * C; idx += blockDim.x) {
+        const int p = idx % C, kx = idx / C;
+        const int r = 2 * p;
         if (r >= J.nrow) continue;
-        const int p = r >> 1;
         const cpx<T> z = buf[p * SP + lds_pos<T>(kx)];
         const cpx<T> zc = conj(buf[p * SP + lds_pos<T>((M - kx) & (M - 1))]);
-        cpx<T> X;
-        if ((r & 1) == 0) {
-            X = cpx<T>{(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+        const cpx<T> X0{(T)0.5 * (z.re + zc.re), (T)0.5 * (z.im + zc.im)};
+        const cpx<T> d = z - zc;  // (z - zc) / (2i)
+        const cpx<T> X1{(T)0.5 * d.im, (T)-0.5 * d.re};
+        cpx<T>* o = out + (size_t)kx * J.ld + J.row0 + r;
+        if (r + 1 < J.nrow) {
+            // o is only as aligned as one complex value (ld may be odd):
+            // the type says so, and the compiler picks a store that allows it
+            typedef T __attribute__((ext_vector_type(4), aligned(2 * sizeof(T)))) vec4a;
+            *reinterpret_cast<vec4a*>(o) = vec4a{X0.re, X0.im, X1.re, X1.im};
         } else {
-            const cpx<T> d = z - zc;  // (z - zc) / (2i)
-            X = cpx<T>{(T)0.5 * d.im, (T)-0.5 * d.re};
+            o[0] = X0;
         }
-        out[(size_t)kx * J.ld + J.row0 + r] = X;
     }
 }
 
