@@ -333,26 +333,36 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
         const int n = L->pn[0], pi0 = L->pi0[0], pj0 = L->pj0[0];
         const bool hc = L->nc == 1;
         const int ci0 = hc ? L->ci0[0] : 0, cj0 = hc ? L->cj0[0] : 0, cn = hc ? L->cn[0] : 0;
-        for (int idx = threadIdx.x; idx < C * NG; idx += blockDim.x) {
-            const int p = idx / NG, lc = idx % NG;
-            T a = 0, b = 0;
+        // a given field's values are scaled in the plan's precision
+        const T sc = (T)J.scale;
+        // each thread walks its sequences p (rows 2p, 2p + 1 of the job) and
+        // its columns; the row quantities are formed once per sequence
+        const int LCS = min((int)blockDim.x, NG), RPI = blockDim.x / LCS;
+        for (int p = threadIdx.x / LCS; p < C; p += RPI) {
             const int s0 = J.row0 + 2 * p;
-            const int scol = J.m * lc + J.col_off;
-            const int i = scol - pi0;
-            // lattice columns outside the source level's window, or outside
-            // the patch, read nothing
-            if (src && lc >= J.lc_lo && lc < J.lc_hi && i >= 0 && i < n) {
-                const int sr0 = J.m * (J.lr_first + s0) + J.row_off, sr1 = sr0 + J.m;
-                const int j0 = sr0 - pj0, j1 = sr1 - pj0;
-                const bool cx = scol >= ci0 && scol < ci0 + cn;
-                if (s0 < rend && j0 >= 0 && j0 < n && !(cx && sr0 >= cj0 && sr0 < cj0 + cn))
-                    a = est ? (T)(J.est_scale * cell_slope(src, n, i, j0, J.f))
-                            : (T)(J.scale * (double)src[(size_t)j0 * n + i]);
-                if (s0 + 1 < rend && j1 >= 0 && j1 < n && !(cx && sr1 >= cj0 && sr1 < cj0 + cn))
-                    b = est ? (T)(J.est_scale * cell_slope(src, n, i, j1, J.f))
-                            : (T)(J.scale * (double)src[(size_t)j1 * n + i]);
+            const int sr0 = J.m * (J.lr_first + s0) + J.row_off, sr1 = sr0 + J.m;
+            const int j0 = sr0 - pj0, j1 = sr1 - pj0;
+            const bool ok0 = src && s0 < rend && j0 >= 0 && j0 < n;
+            const bool ok1 = src && s0 + 1 < rend && j1 >= 0 && j1 < n;
+            // rows that cross the covered square
+            const bool cy0 = sr0 >= cj0 && sr0 < cj0 + cn, cy1 = sr1 >= cj0 && sr1 < cj0 + cn;
+            const T* row0 = src + (ptrdiff_t)(ok0 ? j0 : 0) * n;
+            const T* row1 = src + (ptrdiff_t)(ok1 ? j1 : 0) * n;
+            for (int lc = threadIdx.x % LCS; lc < NG; lc += LCS) {
+                T a = 0, b = 0;
+                const int scol = J.m * lc + J.col_off;
+                const int i = scol - pi0;
+                // lattice columns outside the source level's window, or
+                // outside the patch, read nothing
+                if (lc >= J.lc_lo && lc < J.lc_hi && i >= 0 && i < n) {
+                    const bool cx = scol >= ci0 && scol < ci0 + cn;
+                    if (ok0 && !(cx && cy0))
+                        a = est ? (T)(J.est_scale * cell_slope(src, n, i, j0, J.f)) : sc * row0[i];
+                    if (ok1 && !(cx && cy1))
+                        b = est ? (T)(J.est_scale * cell_slope(src, n, i, j1, J.f)) : sc * row1[i];
+                }
+                buf[p * SP + lds_pos<T>(lc)] = cpx<T>{a, b};
             }
-            buf[p * SP + lds_pos<T>(lc)] = cpx<T>{a, b};
         }
     } else
     for (int idx = threadIdx.x; idx < C * NG; idx += blockDim.x) {
@@ -377,10 +387,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_row_fwd(SegTable<RowFwdJob> 
             const int j0 = sr0 - L->pj0[k], j1 = sr1 - L->pj0[k];
             if (s0 < rend && j0 >= 0 && j0 < n && !covered(L, scol, sr0))
                 a = est ? (T)(J.est_scale * cell_slope(src, n, i, j0, J.f))
-                        : (T)(J.scale * (double)src[(size_t)j0 * n + i]);
+                        : (T)J.scale * src[(size_t)j0 * n + i];
             if (s0 + 1 < rend && j1 >= 0 && j1 < n && !covered(L, scol, sr1))
                 b = est ? (T)(J.est_scale * cell_slope(src, n, i, j1, J.f))
-                        : (T)(J.scale * (double)src[(size_t)j1 * n + i]);
+                        : (T)J.scale * src[(size_t)j1 * n + i];
         }
         buf[p * SP + lds_pos<T>(lc)] = cpx<T>{a, b};
     }
