@@ -1101,8 +1101,9 @@ td_status validate_jobs(td_plan* P)
         const int M = g.M, H = M / 2 + 1;
         for (int pass = 0; pass < NSHAPE; ++pass) {
             const int C = g.C[pass], Gs = g.G[pass];
+            const size_t lds = pass == P_COL ? col_lds_bytes(M, C, es, Gs) : lds_bytes(M, C, es, Gs);
             if (C < 1 || Gs < 1 || Gs > 16 || C * Gs * (M / 8) > TD_MAX_THREADS ||
-                (C & (C - 1)) || (Gs & (Gs - 1)) || lds_bytes(M, C, es, Gs) > TD_MAX_DYN_LDS)
+                (C & (C - 1)) || (Gs & (Gs - 1)) || lds > TD_MAX_DYN_LDS)
                 return bad("launch shape");
         }
         // pass 1: rows written per row-pass plane, and the lattice row of
@@ -2882,7 +2883,8 @@ extern "C" td_status td_autotune(td_context* ctx, td_dtype dt, int32_t max_M, co
             for (int C = 1; C * (M / 8) <= TD_MAX_THREADS; C *= 2)
                 for (int Gs = 1; Gs <= (pass == P_ROWFWD ? 1 : 16); Gs *= 2)
                     if (C * Gs * (M / 8) <= TD_MAX_THREADS &&
-                        lds_bytes(M, C, elem_size(dt), Gs) <= TD_MAX_DYN_LDS)
+                        (pass == P_COL ? col_lds_bytes(M, C, elem_size(dt), Gs)
+                                       : lds_bytes(M, C, elem_size(dt), Gs)) <= TD_MAX_DYN_LDS)
                         cands.push_back(pack_shape(C, Gs));
             for (int C : cands) {
                 {

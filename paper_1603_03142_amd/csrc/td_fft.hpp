@@ -188,10 +188,16 @@ __device__ __forceinline__ void seq_sync()
 // vr[k] instead of LDS; TOR leaves the last pass's outputs in vr[r] instead
 // of storing them (and ends without the closing ordering point: the one
 // after its reads already orders them before any later write).
+//
+// Ping-pong (PP): the pass reads x and writes y, a second buffer of the
+// sequence, so no thread can overwrite what another has yet to read and
+// the ordering point after the reads is dropped -- except in a TOR pass,
+// whose reads must complete before the next transform's first pass writes
+// its buffer again.
 template <typename T, int M, int R, int NS, bool INV, int PR, int PW, bool ZIN = false,
-          bool ZOUT = false, bool FROMR = false, bool TOR = false>
+          bool ZOUT = false, bool FROMR = false, bool TOR = false, bool PP = false>
 __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane,
-                                              cpx<T>* vr = nullptr)
+                                              cpx<T>* vr = nullptr, cpx<T>* y = nullptr)
 {
     static_assert(!ZIN || NS == 1, "ZIN applies to the first pass");
     static_assert(!ZOUT || NS * R == M, "ZOUT applies to the last pass");
@@ -231,7 +237,8 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
                 v[q][r] = r < RIN ? x[lds_pos_p<PR>(j + r * STRIDE)] : cpx<T>{0, 0};
         }
     }
-    seq_sync<M>();
+    if constexpr (!PP || TOR) seq_sync<M>();
+    cpx<T>* const out = PP ? y : x;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
         const int j = lane + q * (M / 8);
@@ -251,12 +258,12 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 #pragma unroll
             for (int r = 0; r < ROUT; ++r) vr[r] = v[q][r];
         } else if constexpr (LIN) {
-            cpx<T>* wp = x + lds_pos_p<PW>(base);
+            cpx<T>* wp = out + lds_pos_p<PW>(base);
 #pragma unroll
             for (int r = 0; r < ROUT; ++r) wp[r * NS + (r * NS) / PW] = v[q][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < ROUT; ++r) x[lds_pos_p<PW>(base + r * NS)] = v[q][r];
+            for (int r = 0; r < ROUT; ++r) out[lds_pos_p<PW>(base + r * NS)] = v[q][r];
         }
     }
     if constexpr (!TOR) seq_sync<M>();
@@ -270,16 +277,20 @@ __host__ __device__ constexpr int pass_pad()
     return (sizeof(T) == 4 && NS >= 2 && NS <= 8 && NS * 8 < M) ? 8 : lds_pad<T>();
 }
 
+// PP: each pass reads x and writes y; the next pass reads y and writes x.
 template <typename T, int M, int NS, bool INV, int PR, bool ZIN, bool ZOUT, bool FROMR = false,
-          bool TOR = false>
+          bool TOR = false, bool PP = false>
 __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane,
-                                              cpx<T>* vr = nullptr)
+                                              cpx<T>* vr = nullptr, cpx<T>* y = nullptr)
 {
     if constexpr (NS < M) {
         constexpr int PW = pass_pad<T, M, NS>();
         stockham_pass<T, M, 8, NS, INV, PR, PW, ZIN && NS == 1, ZOUT && NS * 8 == M,
-                      FROMR && NS == 1, TOR && NS * 8 == M>(x, tw, lane, vr);
-        radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, FROMR, TOR>(x, tw, lane, vr);
+                      FROMR && NS == 1, TOR && NS * 8 == M, PP>(x, tw, lane, vr, y);
+        if constexpr (PP)
+            radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, FROMR, TOR, PP>(y, tw, lane, vr, x);
+        else
+            radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, FROMR, TOR>(x, tw, lane, vr);
     }
 }
 
@@ -321,8 +332,14 @@ __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ 
 // are not read; with ZOUT, only v[0..3] are formed.  Must be called by every
 // thread of the workgroup; on return the sequence's LDS may be written
 // again by any of its threads.
-template <typename T, int M, bool INV, bool ZIN = false, bool ZOUT = false>
-__device__ __forceinline__ void fft_regs(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw)
+//
+// buf2 != nullptr: ping-pong between the sequence's LDS buffer and a second
+// one at the same offset from buf2 (one ordering point per pass instead of
+// two; for sequences that span several wavefronts, where each ordering
+// point is a workgroup barrier).
+template <typename T, int M, bool INV, bool ZIN = false, bool ZOUT = false, bool PP = false>
+__device__ __forceinline__ void fft_regs(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                         cpx<T>* buf2 = nullptr)
 {
     static_assert(M >= 16 && (M & (M - 1)) == 0, "M must be a power of two >= 16");
     int tid = threadIdx.x;
@@ -330,16 +347,21 @@ __device__ __forceinline__ void fft_regs(cpx<T> (&v)[8], cpx<T>* buf, const cpx<
     const int f = tid / (M / 8);
     const int lane = tid % (M / 8);
     cpx<T>* x = buf + (size_t)f * lds_stride<T>(M);
+    cpx<T>* y = PP ? buf2 + (size_t)f * lds_stride<T>(M) : nullptr;
     constexpr int REM = ilog2(M) % 3;
     constexpr int P = lds_pad<T>();
     if constexpr (REM == 1) {
-        stockham_pass<T, M, 2, 1, INV, P, P, ZIN, false, true, false>(x, tw, lane, v);
-        radix8_passes<T, M, 2, INV, P, false, ZOUT, false, true>(x, tw, lane, v);
+        stockham_pass<T, M, 2, 1, INV, P, P, ZIN, false, true, false, PP>(x, tw, lane, v, y);
+        if constexpr (PP)
+            radix8_passes<T, M, 2, INV, P, false, ZOUT, false, true, PP>(y, tw, lane, v, x);
+        else radix8_passes<T, M, 2, INV, P, false, ZOUT, false, true>(x, tw, lane, v);
     } else if constexpr (REM == 2) {
-        stockham_pass<T, M, 4, 1, INV, P, P, ZIN, false, true, false>(x, tw, lane, v);
-        radix8_passes<T, M, 4, INV, P, false, ZOUT, false, true>(x, tw, lane, v);
+        stockham_pass<T, M, 4, 1, INV, P, P, ZIN, false, true, false, PP>(x, tw, lane, v, y);
+        if constexpr (PP)
+            radix8_passes<T, M, 4, INV, P, false, ZOUT, false, true, PP>(y, tw, lane, v, x);
+        else radix8_passes<T, M, 4, INV, P, false, ZOUT, false, true>(x, tw, lane, v);
     } else {
-        radix8_passes<T, M, 1, INV, P, ZIN, ZOUT, true, true>(x, tw, lane, v);
+        radix8_passes<T, M, 1, INV, P, ZIN, ZOUT, true, true, PP>(x, tw, lane, v, y);
     }
 }
 

@@ -659,8 +659,9 @@ __device__ __forceinline__ void store_column(const cpx<T> (&w)[8], char* ws, con
 // One column job of the fused column pass (see ColJob).
 template <typename T, int M>
 __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, cpx<T>* A,
-                                        const cpx<T>* tw, int G, int tid)
+                                        const cpx<T>* tw, int G, int tid, cpx<T>* A2)
 {
+    constexpr bool PP = col_pingpong<T, M>();
     constexpr int TPS = M / 8;
     constexpr int SP = lds_stride<T>(M);
     int slot_unused;
@@ -713,8 +714,15 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
             }
             // a slot without an input skips its transform when sequences
-            // are ordered within their wavefront only (M/8 <= 64)
-            if (M / 8 > 64 || ok) fft_regs<T, M, false, true>(v, A, tw);
+            // are ordered within their wavefront only (M/8 <= 64).  Ping-pong
+            // transforms alternate their two buffers from one input to the
+            // next and skip the closing barrier (one before the reduction)
+            if constexpr (PP) {
+                const bool odd = (r0 / G) & 1;
+                fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
+            } else if (M / 8 > 64 || ok) {
+                fft_regs<T, M, false, true>(v, A, tw);
+            }
             if (ok) {
                 // the kernel columns are read after the transform: holding
                 // them across it costs 32 VGPRs, and the other waves of the
@@ -763,14 +771,14 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
         cpx<T> w[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) w[q] = g == 0 ? sx[q] : (g == gy ? sy[q] : cpx<T>{0, 0});
-        if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true>(w, A, tw);
+        if (M / 8 > 64 || g == 0 || g == gy) fft_regs<T, M, true, false, true, PP>(w, A, tw, A2);
         if (col_ok && g == 0) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0), kx, lane);
         if (col_ok && G > 1 && g == 1)
             store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
         if (G == 1) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) w[q] = sy[q];
-            fft_regs<T, M, true, false, true>(w, A, tw);
+            fft_regs<T, M, true, false, true, PP>(w, A, tw, A2);
             if (col_ok) store_column<T, M>(w, ws, load_desc<M>(tabs.outs, J.out0 + 1), kx, lane);
         }
         return;
@@ -786,7 +794,7 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
         if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
         cpx<T> v[8];
         load_column<T, M>(v, ws, I, kx, ok, lane);
-        fft_regs<T, M, false, true>(v, A, tw);
+        fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
 #pragma unroll
         for (int q = 0; q < 8; ++q) a[lds_pos<T>(lane + q * TPS)] = v[q];
         __syncthreads();  // every slot reads the three transformed inputs
@@ -817,7 +825,12 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
             }
         }
-        if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true>(acc, A, tw);
+        if constexpr (PP) {
+            const bool odd = (o0 / G) & 1;
+            fft_regs<T, M, true, false, true, PP>(acc, A, tw, A2);
+        } else if (M / 8 > 64 || ok) {
+            fft_regs<T, M, true, false, true>(acc, A, tw);
+        }
         if (ok) store_column<T, M>(acc, ws, O, kx, lane);
     }
 }
@@ -835,7 +848,9 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
     constexpr int SP = lds_stride<T>(M);
     const int S = blockDim.x / TPS;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* tw = A + S * SP;
+    // the transforms' second buffers follow the first (ping-pong lengths)
+    cpx<T>* A2 = A + S * SP;
+    cpx<T>* tw = A + (col_pingpong<T, M>() ? 2 : 1) * S * SP;
     stage_twiddles<T, M>(tw, tw_g);
     if constexpr (PQ) {
         __shared__ int s_item[2];
@@ -844,10 +859,10 @@ __global__ void __launch_bounds__(TD_MAX_THREADS) k_col(SegTable<ColJob> segs,
             // of the job loop and held across jobs
             int tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
-            col_job<T, M>(segs, item, A, tw, G, tid);
+            col_job<T, M>(segs, item, A, tw, G, tid, A2);
         }
     } else {
-        col_job<T, M>(segs, blockIdx.x, A, tw, G, threadIdx.x);
+        col_job<T, M>(segs, blockIdx.x, A, tw, G, threadIdx.x, A2);
     }
 }
 
@@ -1143,7 +1158,7 @@ hipError_t launch_col(int M, int C, int G, int blocks, const SegTable<ColJob>& s
 {
     if (blocks <= 0) return hipSuccess;
     const int threads = C * G * (M / 8);
-    const size_t smem = lds_bytes(M, C, sizeof(cpx<T>), G);
+    const size_t smem = col_lds_bytes(M, C, sizeof(cpx<T>), G);
     SegTable<ColJob> s = segs;
     const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
     int g = G;
@@ -1226,7 +1241,7 @@ int col_resident_blocks(bool f64, int M, int C, int G)
 {
     const int threads = C * G * (M / 8);
     const size_t es = f64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
-    const size_t smem = lds_bytes(M, C, es, G);
+    const size_t smem = col_lds_bytes(M, C, es, G);
     switch (M) {
 #define X(MM) \
     case MM: return f64 ? occupancy(k_col<double, MM, true>, threads, smem) : occupancy(k_col<float, MM, true>, threads, smem);

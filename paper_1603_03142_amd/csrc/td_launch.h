@@ -146,4 +146,17 @@ inline size_t lds_bytes(int M, int C, size_t elem, int G = 1)
     return ((size_t)C * G * SP + M) * elem;
 }
 
+// The column pass's FP32 transforms of sequences longer than a wavefront
+// (M/8 > 64) ping-pong between two LDS buffers per sequence: one workgroup
+// barrier per FFT pass instead of two.  (FP64 would lose occupancy to the
+// second buffer; shorter sequences synchronise within their wavefront.)
+template <typename T, int M>
+__host__ __device__ constexpr bool col_pingpong() { return sizeof(T) == 4 && M / 8 > 64; }
+inline bool col_pingpong_rt(int M, size_t elem) { return elem == 8 && M / 8 > 64; }
+inline size_t col_lds_bytes(int M, int C, size_t elem, int G = 1)
+{
+    const size_t SP = (size_t)M + M / 8;
+    return lds_bytes(M, C, elem, G) + (col_pingpong_rt(M, elem) ? (size_t)C * G * SP * elem : 0);
+}
+
 }  // namespace td

@@ -52,7 +52,8 @@ def _dev_fields(hier, seed, dtype):
 
 def _host(outs):
     """[(fx list, fy list)] of tensors -> the same structure of numpy arrays."""
-    return [tuple([t.double().cpu().numpy() for t in lst] for lst in pair) for pair in outs]
+    return [tuple([t.double().cpu().numpy() for t in lst] if lst is not None else [] for lst in pair)
+            for pair in outs]
 
 
 @pytest.mark.parametrize("launch", ["persistent", "direct"])
@@ -81,19 +82,23 @@ def test_batch_equals_single_solves(ctx, use_graph, launch):
     batch.close()
 
 
-def test_persistent_launches_equal_direct(ctx):
-    """Deep hierarchies of several lengths in one batch: the persistent
-    column launches (work lists per XCD, stealing, counters zeroed by a
-    kernel ahead of each solve) give the direct launches' results bit for
-    bit, eagerly and on every graph replay, with the launch mode switched
-    between."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_persistent_launches_equal_direct(ctx, dtype):
+    """Deep hierarchies of several lengths in one batch (in FP64 with two
+    potential plans among the force plans): the persistent column launches
+    (work lists per XCD, stealing, counters zeroed by a kernel ahead of each
+    solve) give the direct launches' results bit for bit, eagerly and on
+    every graph replay, with the launch mode switched between."""
     import torch
     import paper_1603_03142_amd as td
     rng = np.random.Generator(np.random.PCG64(808))
     hiers = [synth._random_nested(rng, n, lv) for n, lv in
              ((256, 3), (128, 4), (512, 2), (64, 1), (256, 2), (128, 3), (64, 2), (256, 4))]
-    plans = [ctx.plan(h, "f32") for h in hiers]
-    fields = [_dev_fields(h, 300 + k, "f32")[0] for k, h in enumerate(hiers)]
+    quantity = ["force"] * len(hiers)
+    if dtype == "f64":
+        quantity[1] = quantity[4] = "potential"
+    plans = [ctx.plan(h, dtype, quantity=q) for h, q in zip(hiers, quantity)]
+    fields = [_dev_fields(h, 300 + k, dtype)[0] for k, h in enumerate(hiers)]
     batch = td.Batch(ctx, plans)
     batch.set_launch("direct")
     want = _host(batch.solve(fields))
@@ -108,7 +113,7 @@ def test_persistent_launches_equal_direct(ctx):
             for a, b in zip(ax + ay, bx + by):
                 assert np.array_equal(a, b), f"solve {rep} member {k}"
         for o in outs:
-            for t in o[0] + o[1]:
+            for t in o[0] + (o[1] or []):
                 t.fill_(float("nan"))
     batch.set_launch("direct")
     again = _host(batch.solve(fields, use_graph=True))
