@@ -839,12 +839,13 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
 // workgroup per job.  Separate instantiations: the job loop costs the direct
 // launch registers and scalar uniformity.
 //
-// FP32 at M = 512 is held to 128 VGPRs (4 waves per SIMD, a few registers
+// FP32 at M <= 512 is held to 128 VGPRs (4 waves per SIMD, a few registers
 // spilled): its sequences fit one wavefront, so nothing waits at workgroup
-// barriers and the extra waves hide memory latency (two-level 256^2 column
-// pass 17.6 -> 16.7 us side by side).  At M = 1024 the same cap cost 11%.
+// barriers and the extra waves hide memory latency (side by side: M = 512
+// 17.6 -> 16.7 us on two-level 256^2; on the 64-disk batch M = 256 234 ->
+// 196 us, M = 128 92 -> 70 us).  At M = 1024 the same cap cost 11%.
 template <typename T, int M>
-constexpr int col_waves_per_eu() { return sizeof(T) == 4 && M == 512 ? 4 : 1; }
+constexpr int col_waves_per_eu() { return sizeof(T) == 4 && M <= 512 ? 4 : 1; }
 
 template <typename T, int M, bool PQ>
 __global__ void __launch_bounds__(TD_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(col_waves_per_eu<T, M>())))
