@@ -714,15 +714,8 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
             }
             // a slot without an input skips its transform when sequences
-            // are ordered within their wavefront only (M/8 <= 64).  Ping-pong
-            // transforms alternate their two buffers from one input to the
-            // next and skip the closing barrier (one before the reduction)
-            if constexpr (PP) {
-                const bool odd = (r0 / G) & 1;
-                fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
-            } else if (M / 8 > 64 || ok) {
-                fft_regs<T, M, false, true>(v, A, tw);
-            }
+            // are ordered within their wavefront only (M/8 <= 64)
+            if (M / 8 > 64 || ok) fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
             if (ok) {
                 // the kernel columns are read after the transform: holding
                 // them across it costs 32 VGPRs, and the other waves of the
@@ -825,12 +818,7 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 kern_mac<T, M>(acc, z, vin[f], kern_of(O.comp, f), O.flip, lane);
             }
         }
-        if constexpr (PP) {
-            const bool odd = (o0 / G) & 1;
-            fft_regs<T, M, true, false, true, PP>(acc, A, tw, A2);
-        } else if (M / 8 > 64 || ok) {
-            fft_regs<T, M, true, false, true>(acc, A, tw);
-        }
+        if (M / 8 > 64 || ok) fft_regs<T, M, true, false, true, PP>(acc, A, tw, A2);
         if (ok) store_column<T, M>(acc, ws, O, kx, lane);
     }
 }
