@@ -1744,6 +1744,7 @@ extern "C" td_status td_context_usage(const td_context* c, size_t* in_use, size_
 
 extern "C" td_status td_context_set_debug(td_context* c, int32_t flags)
 {
+    ErrScope es_;
     if (!c) return fail(TD_EINVAL, "NULL context");
     if (flags & ~TD_DEBUG_NONFINITE) return fail(TD_EINVAL, "unknown debug flag");
     DeviceGuard g(c->device);
@@ -1758,6 +1759,7 @@ extern "C" td_status td_context_set_debug(td_context* c, int32_t flags)
 
 extern "C" td_status td_debug_nonfinite(td_context* c, uint64_t* count)
 {
+    ErrScope es_;
     if (!c || !count) return fail(TD_EINVAL, "NULL argument");
     *count = 0;
     if (!c->d_nonfinite) return TD_OK;

@@ -195,3 +195,21 @@ def test_plan_check_random_patches():
     assert multi > 50
     for ex, n in ((3, 32), (3, 1024), (4, 64), (4, 512)):
         assert td.check_plan(synth.example_hierarchy(ex, n), "f32") > 0
+
+
+def test_entry_points_refuse_null_handles():
+    """Host-side argument checks of the batch, server, debug and
+    allocation-free entry points: NULL handles and unknown modes are refused
+    with TD_EINVAL before anything touches a device."""
+    from paper_1603_03142_amd import _binding as B
+    lib = B.lib()
+    count = ctypes.c_uint64(7)
+    assert lib.td_batch_set_launch(None, B.TD_LAUNCH_DIRECT) == B.TD_EINVAL
+    assert lib.td_context_set_debug(None, B.TD_DEBUG_NONFINITE) == B.TD_EINVAL
+    assert lib.td_debug_nonfinite(None, ctypes.byref(count)) == B.TD_EINVAL
+    assert lib.td_solve_noalloc(None, None) == B.TD_EINVAL
+    req = B.td_request()
+    assert lib.td_solve_noalloc(ctypes.byref(req), None) == B.TD_EINVAL  # no plan
+    assert lib.td_server_stats2(None, None, None) == B.TD_EINVAL
+    assert lib.td_batch_solve(None, None, 0, None) == B.TD_EINVAL
+    assert "NULL" in lib.td_last_error().decode()
