@@ -14,6 +14,7 @@
 #include <cstring>
 #include <deque>
 #include <fstream>
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -880,14 +881,31 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             const SpecEntry* k1 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 1, 1, &k1));
             for (int f = 0; f < 3; ++f)
-                g.colins.push_back({ptr(own_in[t] + f * H * G.ny), k1->ptr, G.ny, 0, f, 4 | fam});
+                g.colins.push_back({ptr(own_in[t] + f * H * G.ny), k1->ptr, G.ny, 0, f, 4 | fam, G.ny, 0});
+            // the phase inputs follow, band-limited ones (few enough rows
+            // for the band transforms) last
+            std::vector<ColIn> wide, band;
+            const int band_rows = col_band_rows(G.M, (int)es);
             for (int s = t + 1; s < L; ++s) {
                 const LevelG& S = P->lv[s];
                 const int m = ipow(r, s - t), nr = ph_nr[s][t];
                 const SpecEntry* k2 = nullptr;
                 TD_TRY(plan_spectra(P, G.M, 2, m, &k2));
                 const size_t per_phase = 6 * H * G.M;
-                // mirror images of one stored phase are adjacent
+                // the mirror images of one stored phase (adjacent in
+                // phase_order) are listed field by field: consecutive inputs,
+                // which run side by side in a workgroup's slots or one round
+                // apart, then read the same stored kernel columns
+                std::vector<ColIn> grp;  // field-0 inputs of one stored phase
+                auto flush = [&]() {
+                    for (int f = 0; f < 3; ++f)
+                        for (ColIn I : grp) {
+                            I.in += (int64_t)f * H * nr * es;
+                            I.f = f;
+                            (I.rows <= band_rows ? band : wide).push_back(I);
+                        }
+                    grp.clear();
+                };
                 for (const auto& ph : phase_order(m)) {
                     const int kx = ph.first, ky = ph.second;
                     const int lr_lo = ceil_div(S.oy - ky, m) - G.oy;
@@ -896,17 +914,20 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                     const int phase = ky * m + kx;
                     int flip = 0;
                     const void* kern = phase_kernels(k2, m, kx, ky, per_phase * es, &flip);
-                    for (int f = 0; f < 3; ++f)
-                        g.colins.push_back({ptr(ph_in[s][t] + ((size_t)phase * 3 + f) * H * nr), kern,
-                                            nr, lr_lo, f, flip | fam});
+                    if (!grp.empty() && grp.back().kern != kern) flush();
+                    grp.push_back({ptr(ph_in[s][t] + (size_t)phase * 3 * H * nr), kern, nr, lr_lo, 0,
+                                   flip | fam, lr_hi - lr_lo + 1, 0});
                 }
+                flush();
             }
+            g.colins.insert(g.colins.end(), wide.begin(), wide.end());
+            g.colins.insert(g.colins.end(), band.begin(), band.end());
             const int out0 = (int)g.colouts.size();
             for (int comp = 0; comp < 2; ++comp)
                 g.colouts.push_back({ptr(own_out[t] + comp * H * G.ny), nullptr, G.ny, 0, comp, 0});
             const int nin = (int)g.colins.size() - in0;
             for (int kx0 = 0; kx0 < (int)H; kx0 += C)
-                g.col.push_back({0, kx0, std::min(C, (int)H - kx0), in0, nin, out0, 2, 0});
+                g.col.push_back({0, kx0, std::min(C, (int)H - kx0), in0, nin, out0, 2, (int)band.size()});
         }
         // (b) Case-3 phases of this (coarser) level onto every finer target:
         // the level's three own planes (the first inputs above) are
@@ -920,15 +941,28 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
             const SpecEntry* k3 = nullptr;
             TD_TRY(plan_spectra(P, G.M, 3, m, &k3));
             const size_t per_phase = 6 * H * G.M;
+            // mirror images of one stored phase component by component, as
+            // the Case-2 inputs above
+            std::vector<ColOut> grp;  // component-0 outputs of one stored phase
+            auto flush = [&]() {
+                for (int comp = 0; comp < 2; ++comp)
+                    for (ColOut O : grp) {
+                        O.out += (int64_t)comp * H * ld * es;
+                        O.comp = comp;
+                        g.colouts.push_back(O);
+                    }
+                grp.clear();
+            };
             for (const auto& ph : phase_order(m)) {
                 const int kx = ph.first, ky = ph.second;
                 const int phase = ky * m + kx;
                 int flip = 0;
                 const void* kern = phase_kernels(k3, m, kx, ky, per_phase * es, &flip);
-                for (int comp = 0; comp < 2; ++comp)
-                    g.colouts.push_back({ptr(c3_out[t][s] + ((size_t)phase * 2 + comp) * H * ld), kern, ld,
-                                         floor_div(T.oy, m) - G.oy, comp, flip | fam});
+                if (!grp.empty() && grp.back().kern != kern) flush();
+                grp.push_back({ptr(c3_out[t][s] + (size_t)phase * 2 * H * ld), kern, ld,
+                               floor_div(T.oy, m) - G.oy, 0, flip | fam});
             }
+            flush();
         }
         const int nout = (int)g.colouts.size() - c3_out0;
         const int chunk = std::max(16 * Gs, 256);
@@ -1110,6 +1144,7 @@ td_status validate_jobs(td_plan* P)
         // each plane's stored row 0
         std::map<int64_t, std::vector<char>> rows_written;
         std::map<int64_t, int> plane_lr;
+        std::map<int64_t, std::array<int, 3>> plane_src;  // level, m, row_off
         for (auto& j : g.rowfwd) {
             if (j.lvl < 0 || j.lvl >= P->nlevels || j.f < 0 || j.f > 2) return bad("row source");
             // lattice columns and rows >= M/2 map past the source level's
@@ -1120,6 +1155,10 @@ td_status validate_jobs(td_plan* P)
                 return bad("row source reaches the upper half of the lattice");
             if (plane_lr.emplace(j.out, j.lr_first).first->second != j.lr_first)
                 return bad("row plane origin");
+            {
+                const std::array<int, 3> src = {j.lvl, j.m, j.row_off};
+                if (plane_src.emplace(j.out, src).first->second != src) return bad("row plane source");
+            }
             // slope fields are scaled by their level's cell side, which the
             // row kernel's in-place slope estimate (per-cell differences)
             // takes for granted
@@ -1150,6 +1189,13 @@ td_status validate_jobs(td_plan* P)
                 auto pl = plane_lr.find(I.in);
                 if (pl == plane_lr.end() || pl->second != I.lr_first) return bad("col input origin");
             }
+            // stored rows >= rows map past the source level's window (zeros)
+            {
+                const auto& src = plane_src.at(I.in);
+                if (I.rows < 1 || I.rows > I.ld ||
+                    (int64_t)src[1] * (I.lr_first + I.rows) + src[2] < P->lv[src[0]].ny)
+                    return bad("col input source rows");
+            }
             if (I.f < 0 || I.f > 2 || (I.flip & ~8) < 0 || (I.flip & ~8) > 4 ||
                 ((I.flip >> 3) & 1) != (P->quantity == TD_POTENTIAL ? 1 : 0))
                 return bad("col input kernel");
@@ -1177,8 +1223,13 @@ td_status validate_jobs(td_plan* P)
                 if (j.nout != 2) return bad("col own outputs");
                 for (int i = j.in0; i < j.in0 + j.nin; ++i)
                     if (!g.colins[i].kern) return bad("col input kernel");
+                // band-limited inputs: a band path for M, and few enough rows
+                if (j.nband < 0 || j.nband > j.nin || (j.nband > 0 && col_band_rows(M, (int)es) == 0))
+                    return bad("col band inputs");
+                for (int i = j.in0 + j.nin - j.nband; i < j.in0 + j.nin; ++i)
+                    if (g.colins[i].rows > col_band_rows(M, (int)es)) return bad("col band input rows");
             } else if (j.kind == 1) {
-                if (j.nin != 3) return bad("col Case-3 inputs");
+                if (j.nin != 3 || j.nband != 0) return bad("col Case-3 inputs");
                 for (int o = j.out0; o < j.out0 + j.nout; ++o)
                     if (!g.colouts[o].kern) return bad("col output kernel");
             } else {

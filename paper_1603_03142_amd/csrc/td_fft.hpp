@@ -185,7 +185,8 @@ __device__ __forceinline__ void seq_sync()
 // elements j + r M/R with j = lane + q M/8, are the elements lane + k M/8
 // (k = q + r 8/R), and the outputs of its one radix-8 butterfly in the last
 // pass are again lane + r M/8.  FROMR takes the first pass's inputs from
-// vr[k] instead of LDS; TOR leaves the last pass's outputs in vr[r] instead
+// vr[k] instead of LDS (or a later radix-8 pass's, elements lane + r M/8 of
+// the array that pass reads: see fft_regs_band); TOR leaves the last pass's outputs in vr[r] instead
 // of storing them (and ends without the closing ordering point: the one
 // after its reads already orders them before any later write).
 //
@@ -201,7 +202,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* x, const cpx<T>* __restric
 {
     static_assert(!ZIN || NS == 1, "ZIN applies to the first pass");
     static_assert(!ZOUT || NS * R == M, "ZOUT applies to the last pass");
-    static_assert(!FROMR || NS == 1, "FROMR applies to the first pass");
+    static_assert(!FROMR || NS == 1 || R == 8, "FROMR applies to the first pass (or a radix-8 one)");
     static_assert(!TOR || (NS * R == M && R == 8), "TOR applies to the last (radix-8) pass");
     constexpr int B = 8 / R;          // butterflies per thread
     constexpr int STRIDE = M / R;     // distance between butterfly inputs
@@ -277,7 +278,9 @@ __host__ __device__ constexpr int pass_pad()
     return (sizeof(T) == 4 && NS >= 2 && NS <= 8 && NS * 8 < M) ? 8 : lds_pad<T>();
 }
 
-// PP: each pass reads x and writes y; the next pass reads y and writes x.
+// The radix-8 passes from span NS on.  FROMR: the first of them takes its
+// inputs from vr.  PP: each pass reads x and writes y; the next pass reads
+// y and writes x.
 template <typename T, int M, int NS, bool INV, int PR, bool ZIN, bool ZOUT, bool FROMR = false,
           bool TOR = false, bool PP = false>
 __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restrict__ tw, int lane,
@@ -285,12 +288,12 @@ __device__ __forceinline__ void radix8_passes(cpx<T>* x, const cpx<T>* __restric
 {
     if constexpr (NS < M) {
         constexpr int PW = pass_pad<T, M, NS>();
-        stockham_pass<T, M, 8, NS, INV, PR, PW, ZIN && NS == 1, ZOUT && NS * 8 == M,
-                      FROMR && NS == 1, TOR && NS * 8 == M, PP>(x, tw, lane, vr, y);
+        stockham_pass<T, M, 8, NS, INV, PR, PW, ZIN && NS == 1, ZOUT && NS * 8 == M, FROMR,
+                      TOR && NS * 8 == M, PP>(x, tw, lane, vr, y);
         if constexpr (PP)
-            radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, FROMR, TOR, PP>(y, tw, lane, vr, x);
+            radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, false, TOR, PP>(y, tw, lane, vr, x);
         else
-            radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, FROMR, TOR>(x, tw, lane, vr);
+            radix8_passes<T, M, NS * 8, INV, PW, ZIN, ZOUT, false, TOR>(x, tw, lane, vr);
     }
 }
 
@@ -363,6 +366,43 @@ __device__ __forceinline__ void fft_regs(cpx<T> (&v)[8], cpx<T>* buf, const cpx<
     } else {
         radix8_passes<T, M, 1, INV, P, ZIN, ZOUT, true, true, PP>(x, tw, lane, v, y);
     }
+}
+
+// Band-limited forward transforms.  After the passes up to span S, element
+// c S + k (c < D = M/S, k < S) of a sequence holds
+//   sum_u x[c + u D] w_S^(u k),   u < S,  w_S = exp(-2 pi i / S),
+// the length-S DFT of the elements congruent to c mod D.  When x is
+// non-zero only on D cyclically consecutive elements, each class c holds
+// at most one of them, x[n] with n = c (mod D), and the sum is that one
+// term, x[n] w_S^(k (n div D)).  A transform of such an input can then
+// start at span S from values formed directly from x: fft_regs_band starts
+// at the span that the first radix-8 pass reaches, which saves that pass
+// and the radix-2/4 one before it, with their LDS traffic and ordering
+// points.  At least two passes must remain (the register-ended last one
+// and one before it).
+constexpr int band_span(int M) { return ilog2(M) % 3 == 0 ? 8 : 8 * tw_first_span(M); }
+constexpr bool band_ok(int M) { return band_span(M) * 8 < M; }
+
+// Forward transform with register ends (as fft_regs) of a band-limited
+// sequence: v[r] comes in holding element lane + r M/8 of the span-S array
+// above (S = band_span(M)), and goes out holding element lane + r M/8 of the
+// transform.  Every thread of the workgroup must call it (or, with
+// M/8 <= 64, every thread of the sequence's wavefront).  With ping-pong
+// (buf2) the first remaining pass writes the second buffer, as the first
+// pass of fft_regs does, so the two kinds of transform can follow each
+// other on one sequence.
+template <typename T, int M, bool PP = false>
+__device__ __forceinline__ void fft_regs_band(cpx<T> (&v)[8], cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                              cpx<T>* buf2 = nullptr)
+{
+    static_assert(band_ok(M), "band transforms need two passes after the band span");
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int f = tid / (M / 8);
+    const int lane = tid % (M / 8);
+    cpx<T>* x = buf + (size_t)f * lds_stride<T>(M);
+    cpx<T>* y = PP ? buf2 + (size_t)f * lds_stride<T>(M) : nullptr;
+    radix8_passes<T, M, band_span(M), false, lds_pad<T>(), false, false, true, true, PP>(x, tw, lane, v, y);
 }
 
 }  // namespace td

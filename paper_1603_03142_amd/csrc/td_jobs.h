@@ -62,6 +62,9 @@ struct ColIn {
     int32_t f;           // field: 0 sigma, 1 dsdx, 2 dsdy
     int32_t flip;        // bits 0/1: x/y mirror, 2: quarter-real layout,
                          // 3: potential kernel family (parities P0, Px, Py)
+    int32_t rows;        // stored rows [0, rows) hold every source row (the
+                         // rest of the ld are zeros)
+    int32_t pad;
 };
 
 // One output plane of the column pass: the inverse column FFT of a sum of
@@ -80,7 +83,9 @@ struct ColOut {
 //  kind 0 (a level's own force): inputs [in0, in0 + nin); slot g of a column
 //    takes inputs g, g + G, ..., transforms each and accumulates it times its
 //    kernels into Fx (output out0) and Fy (output out0 + 1); the slots'
-//    partial sums are reduced before the two inverse transforms.
+//    partial sums are reduced before the two inverse transforms.  The last
+//    nband inputs are band-limited (rows <= M / band_span(M)): a round of G
+//    inputs that lies wholly among them uses the band transforms.
 //  kind 1 (Case 3'): the three inputs [in0, in0 + 3) of the coarser level are
 //    transformed once; outputs [out0, out0 + nout), one per (phase,
 //    component), are formed from them G at a time and transformed back.
@@ -89,7 +94,7 @@ struct ColJob {
     int32_t kx0, ncol;
     int32_t in0, nin;
     int32_t out0, nout;
-    int32_t pad;
+    int32_t nband;
 };
 
 struct RowInvContrib {

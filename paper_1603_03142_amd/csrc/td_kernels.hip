@@ -624,10 +624,11 @@ __device__ __forceinline__ void load_column(cpx<T> (&v)[8], const char* ws, cons
 // load_column split in two so that the loads can be issued one iteration
 // ahead: the raw values (unconditional loads from a clamped row) and their
 // validity, applied where the values are used.
-template <typename T, int M>
-__device__ __forceinline__ void load_column_raw(cpx<T> (&x)[4], bool (&val)[4], const char* ws,
+template <typename T, int M, int N>
+__device__ __forceinline__ void load_column_raw(cpx<T> (&x)[N], bool (&val)[N], const char* ws,
                                                 const ColIn& I, int kx, bool ok, int lane)
 {
+    static_assert(N >= 4, "four values per thread");
     constexpr int TPS = M / 8;
     gptr<cpx<T>> src = (gptr<cpx<T>>)(ws + (ok ? I.in + (int64_t)kx * I.ld * (int64_t)sizeof(cpx<T>) : 0));
     const int last = ok ? I.ld - 1 : 0;
@@ -636,6 +637,68 @@ __device__ __forceinline__ void load_column_raw(cpx<T> (&x)[4], bool (&val)[4], 
         const int sr = lane + q * TPS - I.lr_first;
         x[q] = ldg<T>(src, min(max(sr, 0), last));
         val[q] = ok && sr >= 0 && sr <= last;
+    }
+}
+
+// exp(-2 pi i n / M), 0 <= n < M: the last radix-8 pass's twiddle
+// exp(-2 pi i (n mod M/8) / M) (its r = 1 row), times the eighth root of
+// unity exp(-i pi (n div M/8) / 4) by exact rotations and one product by
+// 1/sqrt 2.
+template <typename T, int M>
+__device__ __forceinline__ cpx<T> unit_root(const cpx<T>* tw, int n)
+{
+    constexpr int E = M / 8;
+    cpx<T> z = tw[tw_offset(M, E) + (n & (E - 1))];
+    const int R = n / E;
+    const T h = (T)0.70710678118654752440084436210484903928;
+    if (R & 1) z = cpx<T>{h * (z.re + z.im), h * (z.im - z.re)};  // (1 - i) / sqrt 2
+    if (R & 2) z = cpx<T>{z.im, -z.re};                              // -i
+    if (R & 4) z = cpx<T>{-z.re, -z.im};                             // -1
+    return z;
+}
+
+// Band-limited input plane I (all of its non-zero stored rows among the
+// first I.rows <= D = M/S, S = band_span(M)): the raw values of the calling
+// thread's inputs to the band transform's first pass (fft_regs_band).  Its
+// element r is element c S + k of the span-S array, c = lane/S + r D/8,
+// k = lane % S, which is the lattice row n = c (mod D) of the band
+// [lr_first, lr_first + D), times a twiddle (band_inputs): stored row
+// (c - lr_first) mod D, valid below I.rows.  (Unconditional loads from a
+// clamped row, then a select, as in load_column_raw.)
+template <typename T, int M>
+__device__ __forceinline__ void load_band_raw(cpx<T> (&x)[8], bool (&val)[8], const char* ws,
+                                              const ColIn& I, int kx, bool ok, int lane)
+{
+    constexpr int S = band_span(M), D = M / S;
+    gptr<cpx<T>> src = (gptr<cpx<T>>)(ws + (ok ? I.in + (int64_t)kx * I.ld * (int64_t)sizeof(cpx<T>) : 0));
+    const int last = ok ? I.rows - 1 : 0;
+    const int c0 = lane / S - I.lr_first;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int sr = (c0 + r * (D / 8)) & (D - 1);
+        x[r] = ldg<T>(src, min(sr, last));
+        val[r] = ok && sr <= last;
+    }
+}
+
+// The band transform's inputs from load_band_raw's values: the element of
+// class c holds x[n] w_S^(k u), u = n div D, which is lr_first div D when
+// c >= lr_first mod D and one more when the band wraps past a multiple of D
+// before reaching c.
+template <typename T, int M>
+__device__ __forceinline__ void band_inputs(cpx<T> (&v)[8], const cpx<T> (&x)[8], const bool (&val)[8],
+                                            int lr_first, const cpx<T>* tw, int lane)
+{
+    constexpr int S = band_span(M), D = M / S;
+    const int k = lane % S, c = lane / S;
+    const int t0 = lr_first / D, b = lr_first % D;
+    // w_S^(k u) = exp(-2 pi i k u D / M)
+    const cpx<T> g0 = unit_root<T, M>(tw, (t0 * k * D) & (M - 1));
+    const cpx<T> g1 = unit_root<T, M>(tw, ((t0 + 1) * k * D) & (M - 1));
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const cpx<T> g = c + r * (D / 8) < b ? g1 : g0;
+        v[r] = val[r] ? cmul(x[r], g) : cpx<T>{0, 0};
     }
 }
 
@@ -683,39 +746,62 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
     // iteration instead of being hoisted and held in registers throughout.
 
     if (J.kind == 0) {
+        // band-limited inputs (the job's last nband) in rounds r0 >= nb0:
+        // the round's choice is uniform over the workgroup, so every slot
+        // passes the same ordering points
+        constexpr int BROWS = col_band_rows(M, (int)sizeof(cpx<T>));
+        constexpr bool BAND = BROWS > 0;
+        static_assert(!BAND || (band_ok(M) && BROWS == M / band_span(M)), "band bound");
+        constexpr int NX = BAND ? 8 : 4;
+        const int nb0 = J.nin - J.nband;
         cpx<T> ax[8], ay[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) ax[q] = ay[q] = cpx<T>{0, 0};
         // each input's column is loaded one iteration ahead, while the
         // previous input is transformed and multiplied
-        ColIn In{0, nullptr, 0, 0, 0, 0};
+        ColIn In{};
         bool okn;
-        cpx<T> xn[4];
-        bool vn[4];
-        {
-            const int i = slot_uniform<M>(g);
+        cpx<T> xn[NX];
+        bool vn[NX];
+        auto prefetch = [&](int r, int lane_p) {
+            const int i = slot_uniform<M>(r + g);
             okn = col_ok && i < J.nin;
+            In = ColIn{};
             if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
-            load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_c);
-        }
+            if constexpr (BAND) {
+                if (r >= nb0) {
+                    load_band_raw<T, M>(xn, vn, ws, In, kx, okn, lane_p);
+                    return;
+                }
+            }
+            load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane_p);
+        };
+        prefetch(0, lane_c);
         for (int r0 = 0; r0 < J.nin; r0 += G) {
             int lane = lane_c;
             asm volatile("" : "+v"(lane));
             const ColIn I = In;
             const bool ok = okn;
+            const bool band = BAND && r0 >= nb0;
             cpx<T> v[8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
-            {
-                const int i = slot_uniform<M>(r0 + G + g);
-                okn = col_ok && i < J.nin;
-                In = ColIn{0, nullptr, 0, 0, 0, 0};
-                if (okn) In = load_desc<M>(tabs.ins, J.in0 + i);
-                load_column_raw<T, M>(xn, vn, ws, In, kx, okn, lane);
+            if constexpr (BAND) {
+                if (band) band_inputs<T, M>(v, xn, vn, I.lr_first, tw, lane);
             }
+            if (!band) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
+            }
+            prefetch(r0 + G, lane);
             // a slot without an input skips its transform when sequences
             // are ordered within their wavefront only (M/8 <= 64)
-            if (M / 8 > 64 || ok) fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
+            if (M / 8 > 64 || ok) {
+                if constexpr (BAND) {
+                    if (band) fft_regs_band<T, M, PP>(v, A, tw, A2);
+                    else fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
+                } else {
+                    fft_regs<T, M, false, true, false, PP>(v, A, tw, A2);
+                }
+            }
             if (ok) {
                 // the kernel columns are read after the transform: holding
                 // them across it costs 32 VGPRs, and the other waves of the
@@ -783,7 +869,7 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
     for (int r0 = 0; r0 < 3; r0 += G) {
         const int i = slot_uniform<M>(r0 + g);
         const bool ok = col_ok && i < 3;
-        ColIn I{0, nullptr, 0, 0, 0, 0};
+        ColIn I{};
         if (ok) I = load_desc<M>(tabs.ins, J.in0 + i);
         cpx<T> v[8];
         load_column<T, M>(v, ws, I, kx, ok, lane);

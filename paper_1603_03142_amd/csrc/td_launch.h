@@ -146,6 +146,17 @@ inline size_t lds_bytes(int M, int C, size_t elem, int G = 1)
     return ((size_t)C * G * SP + M) * elem;
 }
 
+// Band-limited column inputs (fft_regs_band in td_fft.hpp): for FP32 and
+// M >= 1024 a forward column transform whose input has at most M/S stored
+// rows that can be non-zero (S the span after the first radix-8 pass: 16
+// for M = 1024, 32 for 2048, 8 for 4096) starts at span S.  The bound M/S,
+// or 0 where the column pass has no band path (FP64 would spill registers
+// to hold the band's inputs).  elem: complex element bytes.
+__host__ __device__ constexpr int col_band_rows(int M, int elem)
+{
+    return elem != 8 || M < 1024 ? 0 : M / (__builtin_ctz(M) % 3 == 0 ? 8 : 8 << (__builtin_ctz(M) % 3));
+}
+
 // The column pass's FP32 transforms of sequences longer than a wavefront
 // (M/8 > 64) ping-pong between two LDS buffers per sequence: one workgroup
 // barrier per FFT pass instead of two.  (FP64 would lose occupancy to the
