@@ -178,6 +178,15 @@ def test_plan_check_workloads():
         assert td.check_plan(h, "f32") > 0
     for h, _ in synth.config4(count=16):
         assert td.check_plan(h, "f32") > 0
+    # band-limited column inputs (phase sub-grids of at most M/16 rows on
+    # M = 1024, M/32 on M = 2048): the band test's hierarchy and a
+    # five-level 1024^2 request (m = 16)
+    import numpy as np
+    from test_gpu_band import band_hierarchy
+    five = synth._random_nested(np.random.Generator(np.random.PCG64(55)), 1024, 5)
+    for h in (band_hierarchy(), five):
+        for dt in ("f32", "f64"):
+            assert td.check_plan(h, dt) > 0
 
 
 def test_plan_check_random_patches():
