@@ -1084,16 +1084,31 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
     // are cut into eight contiguous runs of target rows, one per XCD, so a
     // line is fetched by one or two XCDs rather than by all eight, and every
     // XCD gets the same share of every level's work.
+    // Within each XCD the levels run longest first (a finer level's rows
+    // take more rounds: one item per x-phase of every coarser source), so
+    // the short rows of the coarse levels fill the tail.
     for (auto& g : P->groups)
         for (int a = 0; a < 2; ++a) {
             std::vector<RowInvJob>& jobs = g.rinv[a];
-            std::vector<std::vector<RowInvJob>> bins(8);
+            auto items = [&](const RowInvJob& j) {
+                int n = 0;
+                for (int k = 0; k < j.nc; ++k) n += g.contribs[j.c0 + k].m;
+                return n;
+            };
+            std::vector<std::pair<size_t, size_t>> runs;  // one level's jobs
             for (size_t i = 0; i < jobs.size();) {
                 size_t e = i;
                 while (e < jobs.size() && jobs[e].lvl == jobs[i].lvl) ++e;
-                const size_t n = e - i;
-                for (size_t k = 0; k < n; ++k) bins[k * 8 / n].push_back(jobs[i + k]);
+                runs.push_back({i, e});
                 i = e;
+            }
+            std::stable_sort(runs.begin(), runs.end(), [&](const auto& x, const auto& y) {
+                return items(jobs[x.first]) > items(jobs[y.first]);
+            });
+            std::vector<std::vector<RowInvJob>> bins(8);
+            for (const auto& run : runs) {
+                const size_t n = run.second - run.first;
+                for (size_t k = 0; k < n; ++k) bins[k * 8 / n].push_back(jobs[run.first + k]);
             }
             std::vector<RowInvJob> order;
             order.reserve(jobs.size());
