@@ -49,9 +49,9 @@ DEFAULT_WORKLOAD = "four-level-512"
 # kernels and the plan builder, whose jobs and launch shapes decide the
 # traffic too: a changed source reports null until it is profiled again.
 TRAFFIC = {
-    ("four-level-512", "f32", "given", "row_fwd"): (249436407, "23bbc1034df2da24"),
-    ("four-level-512", "f32", "given", "col"): (1707436143, "23bbc1034df2da24"),
-    ("four-level-512", "f32", "given", "row_inv"): (152987018, "23bbc1034df2da24"),
+    ("four-level-512", "f32", "given", "row_fwd"): (249298202, "6b45e89099d5b944"),
+    ("four-level-512", "f32", "given", "col"): (1707447374, "6b45e89099d5b944"),
+    ("four-level-512", "f32", "given", "row_inv"): (152060739, "6b45e89099d5b944"),
 }
 
 
