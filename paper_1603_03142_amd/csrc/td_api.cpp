@@ -866,6 +866,15 @@ td_status build_jobs(td_plan* P, size_t* ws_elems, bool emit)
                 }
         }
     }
+    // Row-forward jobs gather the lattice columns [lc_lo, lc_hi) of their
+    // source (a level's own rows: its width; a ratio-m phase: 1/m of it),
+    // then transform and write the same M/2 + 1 frequencies: the widest
+    // gathers run first, so the cheaper phase rows fill the tail.  (Each
+    // plane's jobs stay consecutive, in row order.)
+    for (auto& g : P->groups)
+        std::stable_sort(g.rowfwd.begin(), g.rowfwd.end(), [](const RowFwdJob& a, const RowFwdJob& b) {
+            return a.lc_hi - a.lc_lo > b.lc_hi - b.lc_lo;
+        });
     // ---- pass 2: column transforms, products and inverse column
     // transforms, per lattice
     const int fam = P->quantity == TD_POTENTIAL ? 8 : 0;  // kernel family bit
