@@ -184,7 +184,7 @@ def test_plan_check_workloads():
     import numpy as np
     from test_gpu_band import band_hierarchy
     five = synth._random_nested(np.random.Generator(np.random.PCG64(55)), 1024, 5)
-    for h in (band_hierarchy(), five):
+    for h in (band_hierarchy(264), band_hierarchy(520), five):
         for dt in ("f32", "f64"):
             assert td.check_plan(h, dt) > 0
 

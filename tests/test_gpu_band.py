@@ -2,15 +2,15 @@
 
 A ratio-m sub-grid placed on a coarser lattice (a Case 2' phase, Section 2.2,
 eq. eqnbmnn) holds n/m of the lattice's M rows.  When those rows number at
-most M/16 (M = 1024; M/32 for M = 2048) the column pass starts their forward
-transforms after the first radix-8 pass, from the band's values times
-twiddles, and the band may start at any lattice row (it can wrap past a
-multiple of the band width).  These hierarchies put such sub-grids at
-lattice offsets that are aligned, unaligned and wrapping, next to wider
-sub-grids in the same column jobs, and compare with the oracle's direct
-sum (Section 2.1, eqs. eqndPhi, eqnSigma) on stratified targets.
+most M/16 (M = 1024; M/32 for M = 2048: both cases here) the column pass
+starts their forward transforms after the first radix-8 pass, from the
+band's values times twiddles, and the band may start at any lattice row
+(it can wrap past a multiple of the band width).  These hierarchies put
+such sub-grids at lattice offsets that are aligned, unaligned and
+wrapping, next to wider sub-grids in the same column jobs, and compare
+with the oracle's direct sum (Section 2.1, eqs. eqndPhi, eqnSigma) on
+stratified targets.
 """
-import numpy as np
 import pytest
 
 import oracle
@@ -19,23 +19,34 @@ from gpu_helpers import covered_are_zero, gpu_solve, rand_fields, report, sample
 
 pytestmark = pytest.mark.gpu
 
-N0 = 264  # level 0: 2 x 264 > 512, so a lattice of M = 1024 (band rows <= 64)
 
-
-def band_hierarchy():
+def band_hierarchy(n0=264):
+    """n0 = 264: level 0 on a lattice of M = 1024 (2 x 264 > 512; band rows
+    <= 64, the band transform starting at span 16); n0 = 520: M = 2048
+    (band rows <= 64, starting at span 32)."""
     P = synth.Patch
-    pats = [
-        P(0, N0, 0, 0),
-        # level 1 (ratio 2): n / 2 rows per phase on level 0's lattice
-        P(1, 128, 20, 26),    # 64 rows from lattice row 13: wraps past row 64
-        P(1, 100, 300, 300),  # 50 rows from row 150 (150 mod 64 = 22): wraps
-        P(1, 64, 200, 384),   # 32 rows from row 192: aligned
-        P(1, 200, 320, 20),   # 100 rows: transformed in full, same jobs
-        # level 2 inside the first: 24 rows per phase on level 0 (m = 4),
-        # 48 on level 1 (m = 2)
-        P(2, 96, 60, 80),
-    ]
-    return synth.Hierarchy(-1.0, -1.0, 2.0 / N0, 2, pats)
+    if n0 == 264:
+        pats = [
+            P(0, n0, 0, 0),
+            # level 1 (ratio 2): n / 2 rows per phase on level 0's lattice
+            P(1, 128, 20, 26),    # 64 rows from lattice row 13: wraps past row 64
+            P(1, 100, 300, 300),  # 50 rows from row 150 (150 mod 64 = 22): wraps
+            P(1, 64, 200, 384),   # 32 rows from row 192: aligned
+            P(1, 200, 320, 20),   # 100 rows: transformed in full, same jobs
+            # level 2 inside the first: 24 rows per phase on level 0 (m = 4),
+            # 48 on level 1 (m = 2)
+            P(2, 96, 60, 80),
+        ]
+    else:
+        pats = [
+            P(0, n0, 0, 0),
+            P(1, 128, 20, 26),    # 64 rows from lattice row 13: wraps
+            P(1, 100, 600, 600),  # 50 rows from row 300 (300 mod 64 = 44): wraps
+            P(1, 64, 400, 768),   # 32 rows from row 384: aligned
+            P(1, 200, 640, 20),   # 100 rows: transformed in full
+            P(2, 96, 60, 80),     # 24 / 48 rows on levels 0 / 1 (M = 2048 both)
+        ]
+    return synth.Hierarchy(-1.0, -1.0, 2.0 / n0, 2, pats)
 
 
 def band_rows(hier):
@@ -56,14 +67,14 @@ def ctx():
     c.close()
 
 
-@pytest.fixture(scope="module")
-def reference():
-    hier = band_hierarchy()
+@pytest.fixture(scope="module", params=[264, 520])
+def reference(request):
+    hier = band_hierarchy(request.param)
     rows = band_rows(hier)
     assert sum(r <= 64 for r in rows) >= 5 and any(r > 64 for r in rows)
     sig, dx, dy = rand_fields(hier, 77)
     tg = synth.sample_targets(hier, 600, seed=78)
-    print(f"band: oracle on {len(tg[0])} targets", flush=True)
+    print(f"band n0={request.param}: oracle on {len(tg[0])} targets", flush=True)
     ox, oy = oracle.forces(hier, sig, dx, dy, tg)
     return hier, sig, dx, dy, tg, ox, oy
 
@@ -71,10 +82,11 @@ def reference():
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_band_limited_phases(ctx, reference, dtype, tol):
     hier, sig, dx, dy, tg, ox, oy = reference
-    print(f"band {dtype}: solve", flush=True)
+    name = f"band n0={hier.patches[0].n} {dtype}"
+    print(f"{name}: solve", flush=True)
     gx, gy = gpu_solve(ctx, hier, sig, dx, dy, dtype)
     sx, sy = sampled(hier, gx, gy, tg)
-    err, per, _ = report(f"band {dtype}", hier, tg, sx, sy, ox, oy)
+    err, per, _ = report(name, hier, tg, sx, sy, ox, oy)
     assert len(per) == 3
     assert err <= tol
     for lvl, e in per.items():
