@@ -794,6 +794,16 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
             prefetch(r0 + G, lane);
             // a slot without an input skips its transform when sequences
             // are ordered within their wavefront only (M/8 <= 64)
+            // FP32 with M >= 1024 reads the input's kernel columns before its
+            // transform, so that the reads are in flight across it (32 VGPRs
+            // held, still 3 waves per SIMD); FP64 and shorter M, whose
+            // register budgets are tighter, read them after it
+            constexpr bool KEARLY = sizeof(T) == 4 && M >= 1024;
+            cpx<T> z0[8], z1[8];
+            if (KEARLY && ok) {
+                kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+            }
             if (M / 8 > 64 || ok) {
                 if constexpr (BAND) {
                     if (band) fft_regs_band<T, M, PP>(v, A, tw, A2);
@@ -803,12 +813,10 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 }
             }
             if (ok) {
-                // the kernel columns are read after the transform: holding
-                // them across it costs 32 VGPRs, and the other waves of the
-                // CU hide the read latency better than that (measured)
-                cpx<T> z0[8], z1[8];
-                kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
-                kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                if (!KEARLY) {
+                    kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
+                    kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
+                }
                 kern_mac<T, M>(ax, z0, v, kern_of(0, I.f), I.flip, lane);
                 kern_mac<T, M>(ay, z1, v, kern_of(1, I.f), I.flip, lane);
             }
