@@ -792,8 +792,6 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 for (int q = 0; q < 4; ++q) v[q] = vn[q] ? xn[q] : cpx<T>{0, 0};
             }
             prefetch(r0 + G, lane);
-            // a slot without an input skips its transform when sequences
-            // are ordered within their wavefront only (M/8 <= 64)
             // FP32 with M >= 1024 reads the input's kernel columns before its
             // transform, so that the reads are in flight across it (32 VGPRs
             // held, still 3 waves per SIMD); FP64 and shorter M, whose
@@ -804,6 +802,8 @@ __device__ __forceinline__ void col_job(const SegTable<ColJob>& segs, int item, 
                 kern_load<T, M>(z0, I.kern, kern_of(0, I.f), kx, I.flip, lane);
                 kern_load<T, M>(z1, I.kern, kern_of(1, I.f), kx, I.flip, lane);
             }
+            // a slot without an input skips its transform when sequences
+            // are ordered within their wavefront only (M/8 <= 64)
             if (M / 8 > 64 || ok) {
                 if constexpr (BAND) {
                     if (band) fft_regs_band<T, M, PP>(v, A, tw, A2);
