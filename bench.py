@@ -49,9 +49,9 @@ DEFAULT_WORKLOAD = "four-level-512"
 # kernels and the plan builder, whose jobs and launch shapes decide the
 # traffic too: a changed source reports null until it is profiled again.
 TRAFFIC = {
-    ("four-level-512", "f32", "given", "row_fwd"): (244177958, "2267fb3520ee7b1a"),
-    ("four-level-512", "f32", "given", "col"): (1710051241, "2267fb3520ee7b1a"),
-    ("four-level-512", "f32", "given", "row_inv"): (152105228, "2267fb3520ee7b1a"),
+    ("four-level-512", "f32", "given", "row_fwd"): (244308064, "c537993581510c47"),
+    ("four-level-512", "f32", "given", "col"): (1709918767, "c537993581510c47"),
+    ("four-level-512", "f32", "given", "row_inv"): (152142150, "c537993581510c47"),
 }
 
 
